@@ -1,0 +1,129 @@
+/*
+ * qf.h -- C ABI of libqf.so, a counting quotient filter on one MI355X (gfx950).
+ *
+ * The filter is the bulk GPU counting quotient filter of McCoy, Hofmeyr,
+ * Yelick and Pandey, "High-Performance Filters for GPUs" (PPoPP'23):
+ *   - Sec. 1 (footnote): a counting filter stores a multiset; a count may
+ *     over-estimate (fingerprint collisions) but never under-estimates.
+ *   - Sec. 5.1: each key is hashed to a p = q + r bit fingerprint, split into
+ *     a q-bit quotient (canonical slot) and an r-bit remainder; remainders of
+ *     one quotient form a run, runs are stored in quotient order, shifted right
+ *     as far as needed.
+ *   - Sec. 5.3: a bulk insert hashes and sorts the batch, groups it by region
+ *     and merges each region; remainders are sorted inside a run.
+ *   - Sec. 5.4: duplicates in a batch are reduced to <item, count> first.
+ *   - Sec. 6.2/6.4 and the API table of Sec. 6: bulk query, count and delete.
+ * The hash (SplitMix64 finalizer), the fingerprint bits (low p bits), the
+ * counter encoding, the 10*sqrt(2^q) extra slots after the last quotient and
+ * the per-64-slot offsets are this library's readings of what the paper leaves
+ * open; the result is one canonical table per multiset, which qf_export
+ * returns.
+ *
+ * Conventions for every call below:
+ *   - `d_*` pointers are device pointers (e.g. torch tensors' data_ptr());
+ *     keys are any 64-bit values; the caller owns keys and outputs, which hold
+ *     n elements and must not alias.  n == 0 is a no-op that returns QF_OK.
+ *   - `stream` is a hipStream_t passed as void*; NULL is the null stream.
+ *     Calls are stream-ordered and asynchronous: they return after enqueueing.
+ *   - Argument errors return at once with no side effects.  Errors found on
+ *     the device (QF_ERR_FULL, QF_ERR_COUNT_OVERFLOW) make that batch a no-op
+ *     (all or nothing: the table is left exactly as before the call) and are
+ *     reported by the next qf_sync (or qf_export) on that filter.
+ *   - A filter must not be used from two streams without ordering them.
+ *   - The library owns the table (two device copies, written alternately) and
+ *     a grow-only scratch area sized by the largest batch seen.
+ */
+#ifndef QF_H
+#define QF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qf_filter qf_t;
+
+enum {
+  QF_OK = 0,
+  QF_ERR_ARG = -1,            /* bad argument (nothing happened)              */
+  QF_ERR_FULL = -2,           /* a run would end past the last slot           */
+  QF_ERR_OOM = -3,            /* device allocation failed                     */
+  QF_ERR_DEVICE = -4,         /* a HIP runtime call failed                    */
+  QF_ERR_COUNT_OVERFLOW = -5  /* a count would exceed 2^64 - 1                */
+};
+
+/* Logical layout of a table, as host arrays (qf_export / qf_import).
+ *   header       : q, r, N = 2^q, E (extra slots), P = N + E, used slots,
+ *                  distinct fingerprints, total count (mod 2^64)
+ *   occ_words    : N/64 words; bit x%64 of word x/64 = quotient x has a run
+ *   runend_words : P/64 words; bit j%64 of word j/64 = slot j ends a run
+ *   slots        : P values (remainders and counter digits), 0 outside runs
+ *   offsets      : P/64 values; for block b starting at slot i = 64b, the
+ *                  distance from i to the end of the run of the last occupied
+ *                  quotient <= i, or 0 when that end lies before i / no such
+ *                  quotient exists.
+ * The caller allocates the four arrays with the sizes above. */
+typedef struct qf_layout {
+  uint64_t header[8];
+  uint64_t *occ_words;
+  uint64_t *runend_words;
+  uint16_t *slots;
+  uint32_t *offsets;
+} qf_layout_t;
+
+/* Sec. 5.1: a table of 2^q quotients with r-bit remainders.  q in [6, 31],
+ * r in {8, 16}.  Returns NULL on error (see qf_last_error()).  The new filter
+ * is empty and lives on the current HIP device. */
+qf_t *qf_create(uint32_t q, uint32_t r);
+
+/* Frees the filter and its device memory (waits for its pending work).
+ * NULL is ignored. */
+void qf_destroy(qf_t *f);
+
+/* Sec. 5.3-5.4: insert one instance of each key (duplicates are counted).
+ * d_keys: device, n uint64.  All or nothing; QF_ERR_FULL / COUNT_OVERFLOW are
+ * deferred to qf_sync. */
+int qf_insert_batch(qf_t *f, const uint64_t *d_keys, uint64_t n, void *stream);
+
+/* Sec. 6.2: d_out[i] = 1 if the fingerprint of d_keys[i] is stored, else 0.
+ * d_keys: device, n uint64; d_out: device, n uint8. */
+int qf_query_batch(qf_t *f, const uint64_t *d_keys, uint64_t n, uint8_t *d_out, void *stream);
+
+/* Count (API table of Sec. 6): d_out[i] = stored multiplicity of the
+ * fingerprint of d_keys[i] (>= the true count of the key, Sec. 1 footnote).
+ * d_keys: device, n uint64; d_out: device, n uint64. */
+int qf_count_batch(qf_t *f, const uint64_t *d_keys, uint64_t n, uint64_t *d_out, void *stream);
+
+/* Sec. 6.4: for a fingerprint present k times in the batch, remove
+ * min(k, stored count) instances; the shortfall summed over the batch is
+ * ADDED to *d_not_found (device, one uint64; may be NULL). */
+int qf_delete_batch(qf_t *f, const uint64_t *d_keys, uint64_t n, uint64_t *d_not_found,
+                    void *stream);
+
+/* Waits for the filter's work on `stream`; returns the first deferred device
+ * error since the previous qf_sync (and clears it), or QF_OK. */
+int qf_sync(qf_t *f, void *stream);
+
+/* Copies the current table to the caller's host arrays (synchronous; also
+ * returns and clears a pending deferred error, like qf_sync). */
+int qf_export(qf_t *f, qf_layout_t *out, void *stream);
+
+/* Replaces the table by the given logical layout (header q, r must match the
+ * filter; the layout must be a valid canonical table).  Synchronous. */
+int qf_import(qf_t *f, const qf_layout_t *in, void *stream);
+
+/* Error code of the last failed call in this thread. */
+int qf_last_error(void);
+
+/* Device bytes of one table copy of a (q, r) filter (blocks + offsets). */
+uint64_t qf_table_bytes(uint32_t q, uint32_t r);
+
+/* info[0..7] = q, r, N, E, P, region slots, device bytes held, batches run. */
+int qf_info(const qf_t *f, uint64_t *info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QF_H */

@@ -1,0 +1,610 @@
+/*
+ * oqf.c -- plain, sequential CPU counting quotient filter.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the oracle that the GPU path is checked
+ * against.  Only tests/, __graft_entry__.smoke() and the cpu_baseline leg of
+ * bench.py may load it.  It shares no code, header, table or constant with
+ * the HIP library (paper_2212_09005_amd/csrc); the two are written
+ * independently from the paper and from the readings listed in the design doc.
+ *
+ * What it follows (McCoy, Hofmeyr, Yelick, Pandey, "High-Performance Filters
+ * for GPUs", PPoPP'23):
+ *   - Sec. 1 (footnote on counting filters): the filter stores a multiset;
+ *     a count may only over-estimate, never under-estimate.
+ *   - Sec. 5.1 (CQF overview): an item's p-bit fingerprint h(x) is split into
+ *     a q-bit quotient (its canonical slot) and an r-bit remainder; equal
+ *     quotients form a run, contiguous runs form a cluster, and an insert that
+ *     lands inside a cluster shifts the rest of the cluster right.
+ *   - Sec. 5.3 (Sorting hashes): remainders are kept sorted inside a run.
+ *   - Sec. 5.4 (skew): duplicates are aggregated into <item, count> pairs.
+ *   - Sec. 6.4 (deletions): deletes shift the cluster left.
+ *   - Sec. 2 / Sec. 6.7: counters are embedded in the slots with variable size.
+ * The paper does not print the counter encoding, the metadata layout, the
+ * hash or the table end; the readings used here (canonical layout, SplitMix64
+ * finalizer, low p bits, CQF-style counter encoding, 10*sqrt(2^q) overflow
+ * slots, per-64-slot offsets) are the ones listed in the design doc.
+ *
+ * The algorithm is deliberately naive: every unit update decodes the whole
+ * cluster around the target quotient into a list of (quotient, remainder,
+ * count) entries, applies the change, and writes the cluster back from its
+ * first slot ("decode, modify, re-emit").  Re-emitting a longer cluster is the
+ * paper's right shift; re-emitting a shorter one is the left shift of a
+ * delete.  A batch is the unit update applied key by key in input order; on
+ * any error the whole batch is rolled back from a snapshot.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OQF_OK 0
+#define OQF_ERR_ARG (-1)
+#define OQF_ERR_FULL (-2)
+#define OQF_ERR_OOM (-3)
+#define OQF_ERR_COUNT_OVERFLOW (-5)
+
+typedef struct oqf {
+  uint32_t q, r;
+  uint64_t N, E, P; /* quotients, extra slots after slot N-1, physical slots */
+  uint8_t *occ;     /* N flags: quotient has a run                       */
+  uint8_t *runend;  /* P flags: slot is the last slot of a run           */
+  uint8_t *used;    /* P flags: slot belongs to a run (private)          */
+  uint16_t *slot;   /* P remainders / counter digits                     */
+  uint64_t used_slots, distinct, total;
+} oqf_t;
+
+/* ---- hash: SplitMix64 finalizer (Steele, Lea, Flood 2014; "Mix13"
+ *      constants of D. Stafford).  Any key maps to a 64-bit value; the map
+ *      is a bijection on 64-bit words. ---- */
+uint64_t oqf_fin64(uint64_t z) {
+  z ^= z >> 30;
+  z *= 0xbf58476d1ce4e5b9ULL;
+  z ^= z >> 27;
+  z *= 0x94d049bb133111ebULL;
+  z ^= z >> 31;
+  return z;
+}
+
+static uint64_t lowmask(uint32_t bits) {
+  return bits >= 64 ? ~0ULL : ((1ULL << bits) - 1ULL);
+}
+
+/* fingerprint = low p = q + r bits of the hash; quotient = its high q bits,
+ * remainder = its low r bits (Sec. 5.1). */
+uint64_t oqf_fingerprint(const oqf_t *f, uint64_t key) {
+  return oqf_fin64(key) & lowmask(f->q + f->r);
+}
+
+static uint64_t isqrt_u64(uint64_t n) {
+  uint64_t x = 0, bit = 1ULL << 62;
+  while (bit > n) bit >>= 2;
+  while (bit) {
+    if (n >= x + bit) {
+      n -= x + bit;
+      x = (x >> 1) + bit;
+    } else {
+      x >>= 1;
+    }
+    bit >>= 2;
+  }
+  return x;
+}
+
+uint64_t oqf_extra_slots(uint32_t q) {
+  uint64_t N = 1ULL << q;
+  uint64_t e = 10ULL * isqrt_u64(N);
+  return ((e + 63) / 64) * 64;
+}
+
+oqf_t *oqf_create(uint32_t q, uint32_t r) {
+  if (q < 6 || q > 30 || r < 2 || r > 16 || q + r > 64) return NULL;
+  oqf_t *f = (oqf_t *)calloc(1, sizeof(oqf_t));
+  if (!f) return NULL;
+  f->q = q;
+  f->r = r;
+  f->N = 1ULL << q;
+  f->E = oqf_extra_slots(q);
+  f->P = f->N + f->E;
+  f->occ = (uint8_t *)calloc(f->N, 1);
+  f->runend = (uint8_t *)calloc(f->P, 1);
+  f->used = (uint8_t *)calloc(f->P, 1);
+  f->slot = (uint16_t *)calloc(f->P, sizeof(uint16_t));
+  if (!f->occ || !f->runend || !f->used || !f->slot) {
+    free(f->occ); free(f->runend); free(f->used); free(f->slot); free(f);
+    return NULL;
+  }
+  return f;
+}
+
+void oqf_destroy(oqf_t *f) {
+  if (!f) return;
+  free(f->occ); free(f->runend); free(f->used); free(f->slot); free(f);
+}
+
+uint64_t oqf_num_slots(const oqf_t *f) { return f->P; }
+uint64_t oqf_num_extra(const oqf_t *f) { return f->E; }
+
+/* ---- variable-size counters embedded in the slots.
+ * Encoding of one (remainder x, count c) entry, base B = 2^r - 1:
+ *   c == 1            : [x]
+ *   c == 2            : [x, x]
+ *   c >= 3, x > 0     : [x, (0), s_1..s_k, x], s_i the base-B digits of c-3
+ *                       (most significant first), each digit d stored as d
+ *                       if d < x and d+1 otherwise; a 0 is put in front when
+ *                       the first stored digit would exceed x.
+ *   c >= 3, x == 0    : [0, 0, 0, d_1+1 .. d_k+1, 0]
+ * A reader knows the entry ends where the closing x (or 0) appears. ---- */
+static uint64_t base_digits(uint64_t v, uint64_t base, uint64_t *digits) {
+  /* most significant first; at least one digit */
+  uint64_t tmp[80];
+  uint64_t k = 0;
+  do {
+    tmp[k++] = v % base;
+    v /= base;
+  } while (v);
+  for (uint64_t i = 0; i < k; i++) digits[i] = tmp[k - 1 - i];
+  return k;
+}
+
+static uint64_t encode_entry(uint32_t r, uint64_t x, uint64_t c, uint16_t *out) {
+  uint64_t base = (1ULL << r) - 1ULL;
+  uint64_t n = 0;
+  if (c == 1) {
+    out[n++] = (uint16_t)x;
+    return n;
+  }
+  if (c == 2) {
+    out[n++] = (uint16_t)x;
+    out[n++] = (uint16_t)x;
+    return n;
+  }
+  uint64_t d[80];
+  uint64_t k = base_digits(c - 3, base, d);
+  if (x > 0) {
+    out[n++] = (uint16_t)x;
+    if (d[0] >= x) out[n++] = 0; /* first stored digit must lie below x */
+    for (uint64_t i = 0; i < k; i++) out[n++] = (uint16_t)(d[i] < x ? d[i] : d[i] + 1);
+    out[n++] = (uint16_t)x;
+  } else {
+    out[n++] = 0;
+    out[n++] = 0;
+    out[n++] = 0;
+    for (uint64_t i = 0; i < k; i++) out[n++] = (uint16_t)(d[i] + 1);
+    out[n++] = 0;
+  }
+  return n;
+}
+
+/* exported for the encoding pin tests */
+uint64_t oqf_encode_entry(uint32_t r, uint64_t x, uint64_t c, uint16_t *out) {
+  if (r < 2 || r > 16 || c == 0 || x >= (1ULL << r)) return 0;
+  return encode_entry(r, x, c, out);
+}
+
+/* decode the entry starting at slot p of a run ending at e; returns the slot
+ * after it, or (uint64_t)-1 if the slots are not a valid encoding. */
+static uint64_t decode_entry(const uint16_t *s, uint32_t r, uint64_t p, uint64_t e,
+                             uint64_t *x_out, uint64_t *c_out) {
+  uint64_t base = (1ULL << r) - 1ULL;
+  uint64_t x = s[p];
+  *x_out = x;
+  if (x > 0) {
+    if (p == e || s[p + 1] > x) { *c_out = 1; return p + 1; }
+    if (s[p + 1] == x) { *c_out = 2; return p + 2; }
+    uint64_t v = 0, qpos = p + 1;
+    while (qpos <= e && s[qpos] != x) {
+      uint64_t d = s[qpos] < x ? s[qpos] : (uint64_t)s[qpos] - 1;
+      v = v * base + d;
+      qpos++;
+    }
+    if (qpos > e) return (uint64_t)-1;
+    *c_out = v + 3;
+    return qpos + 1;
+  }
+  if (p == e || s[p + 1] != 0) { *c_out = 1; return p + 1; }
+  if (p + 1 == e || s[p + 2] != 0) { *c_out = 2; return p + 2; }
+  uint64_t v = 0, qpos = p + 3;
+  while (qpos <= e && s[qpos] != 0) {
+    v = v * base + ((uint64_t)s[qpos] - 1);
+    qpos++;
+  }
+  if (qpos > e) return (uint64_t)-1;
+  *c_out = v + 3;
+  return qpos + 1;
+}
+
+/* exported for the encoding pin tests: decodes one entry of a run */
+int oqf_decode_entry(uint32_t r, const uint16_t *slots, uint64_t len, uint64_t *x,
+                     uint64_t *c, uint64_t *consumed) {
+  if (len == 0) return OQF_ERR_ARG;
+  uint64_t nx = decode_entry(slots, r, 0, len - 1, x, c);
+  if (nx == (uint64_t)-1) return OQF_ERR_ARG;
+  *consumed = nx;
+  return OQF_OK;
+}
+
+/* ---- entry list used while a cluster is rewritten ---- */
+typedef struct {
+  uint64_t quot, rem, cnt;
+} ent_t;
+
+typedef struct {
+  ent_t *v;
+  uint64_t n, cap;
+} ents_t;
+
+static int ents_push(ents_t *a, uint64_t quot, uint64_t rem, uint64_t cnt) {
+  if (a->n == a->cap) {
+    uint64_t nc = a->cap ? a->cap * 2 : 64;
+    ent_t *nv = (ent_t *)realloc(a->v, nc * sizeof(ent_t));
+    if (!nv) return OQF_ERR_OOM;
+    a->v = nv;
+    a->cap = nc;
+  }
+  a->v[a->n].quot = quot;
+  a->v[a->n].rem = rem;
+  a->v[a->n].cnt = cnt;
+  a->n++;
+  return OQF_OK;
+}
+
+/* Decode the cluster whose first slot is cs (used[cs] == 1): the runs of the
+ * occupied quotients x = cs, ... in increasing order, each starting right
+ * after the previous run and ending at the next runend flag.  Appends the
+ * entries and returns the cluster's last slot. */
+static int decode_cluster(const oqf_t *f, uint64_t cs, ents_t *out, uint64_t *last) {
+  int64_t prev_end = (int64_t)cs - 1;
+  for (uint64_t x = cs; x < f->N && (int64_t)x <= prev_end + 1; x++) {
+    if (!f->occ[x]) continue;
+    uint64_t start = (uint64_t)(prev_end + 1);
+    uint64_t end = start;
+    while (end < f->P && !f->runend[end]) end++;
+    if (end >= f->P) return OQF_ERR_ARG; /* corrupt table */
+    uint64_t p = start;
+    while (p <= end) {
+      uint64_t rem, cnt;
+      uint64_t np = decode_entry(f->slot, f->r, p, end, &rem, &cnt);
+      if (np == (uint64_t)-1) return OQF_ERR_ARG;
+      int rc = ents_push(out, x, rem, cnt);
+      if (rc) return rc;
+      p = np;
+    }
+    prev_end = (int64_t)end;
+  }
+  *last = (uint64_t)prev_end;
+  return OQF_OK;
+}
+
+static uint64_t entry_len(uint32_t r, uint64_t x, uint64_t c) {
+  uint16_t tmp[96];
+  return encode_entry(r, x, c, tmp);
+}
+
+/* Where the entries (sorted by quotient, then remainder) end when they are
+ * written from slot cs on: each run starts at max(quotient, previous end+1). */
+static int64_t layout_end(const oqf_t *f, uint64_t cs, const ents_t *e) {
+  int64_t prev_end = (int64_t)cs - 1;
+  uint64_t i = 0;
+  while (i < e->n) {
+    uint64_t x = e->v[i].quot;
+    int64_t start = (int64_t)x > prev_end + 1 ? (int64_t)x : prev_end + 1;
+    int64_t len = 0;
+    while (i < e->n && e->v[i].quot == x) {
+      len += (int64_t)entry_len(f->r, e->v[i].rem, e->v[i].cnt);
+      i++;
+    }
+    prev_end = start + len - 1;
+  }
+  return prev_end;
+}
+
+/* One unit update: add (delta_sign = +1) or remove (-1) `amount` instances of
+ * fingerprint (quot, rem).  For a removal, *shortfall receives the number of
+ * instances that were not present. */
+static int apply(oqf_t *f, uint64_t quot, uint64_t rem, uint64_t amount, int remove,
+                 uint64_t *shortfall) {
+  if (amount == 0) return OQF_OK;
+  /* 1. the cluster containing (or touching) the canonical slot */
+  uint64_t cs = quot;
+  while (cs > 0 && f->used[cs - 1]) cs--;
+  ents_t ents = {0, 0, 0};
+  int64_t old_last = (int64_t)cs - 1; /* last slot of the decoded clusters */
+  int rc;
+  if (f->used[cs]) {
+    uint64_t last;
+    rc = decode_cluster(f, cs, &ents, &last);
+    if (rc) goto done;
+    old_last = (int64_t)last;
+  }
+  /* 2. apply the change to the entry list (kept sorted by quot, rem) */
+  {
+    uint64_t i = 0;
+    while (i < ents.n && (ents.v[i].quot < quot || (ents.v[i].quot == quot && ents.v[i].rem < rem))) i++;
+    int found = (i < ents.n && ents.v[i].quot == quot && ents.v[i].rem == rem);
+    if (!remove) {
+      if (found) {
+        if (ents.v[i].cnt > UINT64_MAX - amount) { rc = OQF_ERR_COUNT_OVERFLOW; goto done; }
+        ents.v[i].cnt += amount;
+      } else {
+        rc = ents_push(&ents, 0, 0, 0);
+        if (rc) goto done;
+        memmove(&ents.v[i + 1], &ents.v[i], (ents.n - 1 - i) * sizeof(ent_t));
+        ents.v[i].quot = quot;
+        ents.v[i].rem = rem;
+        ents.v[i].cnt = amount;
+        f->distinct++;
+      }
+      f->total += amount;
+    } else {
+      uint64_t have = found ? ents.v[i].cnt : 0;
+      uint64_t take = have < amount ? have : amount;
+      *shortfall += amount - take;
+      if (take == 0) { rc = OQF_OK; goto done; }
+      f->total -= take;
+      if (take == have) {
+        memmove(&ents.v[i], &ents.v[i + 1], (ents.n - i - 1) * sizeof(ent_t));
+        ents.n--;
+        f->distinct--;
+      } else {
+        ents.v[i].cnt -= take;
+      }
+    }
+  }
+  /* 3. if the rewritten cluster now reaches the next cluster, that cluster
+   *    has to move too: absorb it and try again (the paper's shift). */
+  int64_t new_last;
+  for (;;) {
+    new_last = layout_end(f, cs, &ents);
+    int64_t probe = old_last + 1;
+    int64_t hit = -1;
+    for (int64_t j = probe; j <= new_last && j < (int64_t)f->P; j++) {
+      if (f->used[j]) { hit = j; break; }
+    }
+    if (hit < 0) break;
+    uint64_t last;
+    rc = decode_cluster(f, (uint64_t)hit, &ents, &last);
+    if (rc) goto done;
+    old_last = (int64_t)last;
+  }
+  if (new_last >= (int64_t)f->P) { rc = OQF_ERR_FULL; goto done; }
+  /* 4. clear the old extent and write the entries back from cs */
+  uint64_t old_used = 0, new_used = 0;
+  for (int64_t j = (int64_t)cs; j <= old_last; j++) {
+    old_used += f->used[j];
+    f->slot[j] = 0;
+    f->runend[j] = 0;
+    f->used[j] = 0;
+  }
+  {
+    uint64_t qlo = cs, qhi = (uint64_t)(old_last < (int64_t)cs ? (int64_t)cs : old_last);
+    if (quot > qhi) qhi = quot;
+    for (uint64_t x = qlo; x <= qhi && x < f->N; x++) f->occ[x] = 0;
+  }
+  {
+    int64_t prev_end = (int64_t)cs - 1;
+    uint64_t i = 0;
+    uint16_t buf[96];
+    while (i < ents.n) {
+      uint64_t x = ents.v[i].quot;
+      int64_t pos = (int64_t)x > prev_end + 1 ? (int64_t)x : prev_end + 1;
+      f->occ[x] = 1;
+      while (i < ents.n && ents.v[i].quot == x) {
+        uint64_t n = encode_entry(f->r, ents.v[i].rem, ents.v[i].cnt, buf);
+        for (uint64_t k = 0; k < n; k++) {
+          f->slot[pos] = buf[k];
+          f->used[pos] = 1;
+          pos++;
+          new_used++;
+        }
+        i++;
+      }
+      f->runend[pos - 1] = 1;
+      prev_end = pos - 1;
+    }
+    f->used_slots = f->used_slots - old_used + new_used;
+  }
+  rc = OQF_OK;
+done:
+  free(ents.v);
+  return rc;
+}
+
+/* ---- snapshot / rollback for all-or-nothing batches ---- */
+typedef struct {
+  uint8_t *occ, *runend, *used;
+  uint16_t *slot;
+  uint64_t used_slots, distinct, total;
+} snap_t;
+
+static int snap_take(const oqf_t *f, snap_t *s) {
+  s->occ = (uint8_t *)malloc(f->N);
+  s->runend = (uint8_t *)malloc(f->P);
+  s->used = (uint8_t *)malloc(f->P);
+  s->slot = (uint16_t *)malloc(f->P * sizeof(uint16_t));
+  if (!s->occ || !s->runend || !s->used || !s->slot) {
+    free(s->occ); free(s->runend); free(s->used); free(s->slot);
+    return OQF_ERR_OOM;
+  }
+  memcpy(s->occ, f->occ, f->N);
+  memcpy(s->runend, f->runend, f->P);
+  memcpy(s->used, f->used, f->P);
+  memcpy(s->slot, f->slot, f->P * sizeof(uint16_t));
+  s->used_slots = f->used_slots;
+  s->distinct = f->distinct;
+  s->total = f->total;
+  return OQF_OK;
+}
+
+static void snap_restore(oqf_t *f, snap_t *s) {
+  memcpy(f->occ, s->occ, f->N);
+  memcpy(f->runend, s->runend, f->P);
+  memcpy(f->used, s->used, f->P);
+  memcpy(f->slot, s->slot, f->P * sizeof(uint16_t));
+  f->used_slots = s->used_slots;
+  f->distinct = s->distinct;
+  f->total = s->total;
+}
+
+static void snap_free(snap_t *s) {
+  free(s->occ); free(s->runend); free(s->used); free(s->slot);
+}
+
+static void split(const oqf_t *f, uint64_t key, uint64_t *quot, uint64_t *rem) {
+  uint64_t fp = oqf_fingerprint(f, key);
+  *quot = fp >> f->r;
+  *rem = fp & lowmask(f->r);
+}
+
+/* Insert every key of the batch (duplicates are counted).  All or nothing. */
+int oqf_insert_batch(oqf_t *f, const uint64_t *keys, uint64_t n) {
+  if (!f || (n && !keys)) return OQF_ERR_ARG;
+  if (n == 0) return OQF_OK;
+  snap_t s;
+  int rc = snap_take(f, &s);
+  if (rc) return rc;
+  for (uint64_t i = 0; i < n; i++) {
+    uint64_t quot, rem;
+    split(f, keys[i], &quot, &rem);
+    rc = apply(f, quot, rem, 1, 0, NULL);
+    if (rc) { snap_restore(f, &s); break; }
+  }
+  snap_free(&s);
+  return rc;
+}
+
+/* Add `cnt[i]` instances of fingerprint fps[i] (used to build adversarial
+ * tables with large counts without materialising the keys). */
+int oqf_insert_fp_counts(oqf_t *f, const uint64_t *fps, const uint64_t *cnt, uint64_t n) {
+  if (!f || (n && (!fps || !cnt))) return OQF_ERR_ARG;
+  if (n == 0) return OQF_OK;
+  snap_t s;
+  int rc = snap_take(f, &s);
+  if (rc) return rc;
+  uint64_t pm = lowmask(f->q + f->r);
+  for (uint64_t i = 0; i < n; i++) {
+    uint64_t fp = fps[i] & pm;
+    rc = apply(f, fp >> f->r, fp & lowmask(f->r), cnt[i], 0, NULL);
+    if (rc) { snap_restore(f, &s); break; }
+  }
+  snap_free(&s);
+  return rc;
+}
+
+/* Remove one instance per key occurrence; instances that are not present are
+ * added to *not_found.  Deletes cannot fail for lack of space. */
+int oqf_delete_batch(oqf_t *f, const uint64_t *keys, uint64_t n, uint64_t *not_found) {
+  if (!f || (n && !keys)) return OQF_ERR_ARG;
+  uint64_t miss = 0;
+  for (uint64_t i = 0; i < n; i++) {
+    uint64_t quot, rem;
+    split(f, keys[i], &quot, &rem);
+    int rc = apply(f, quot, rem, 1, 1, &miss);
+    if (rc) return rc;
+  }
+  if (not_found) *not_found += miss;
+  return OQF_OK;
+}
+
+/* count of one fingerprint: walk to the run of its quotient and scan it.
+ * The run of an occupied quotient x is found from the cluster start: runs of
+ * the occupied quotients cs, ..., x are laid end to end from cs. */
+static uint64_t count_fp(const oqf_t *f, uint64_t quot, uint64_t rem) {
+  if (!f->occ[quot]) return 0;
+  uint64_t cs = quot;
+  while (cs > 0 && f->used[cs - 1]) cs--;
+  int64_t prev_end = (int64_t)cs - 1;
+  for (uint64_t x = cs; x <= quot; x++) {
+    if (!f->occ[x]) continue;
+    uint64_t start = (int64_t)x > prev_end + 1 ? x : (uint64_t)(prev_end + 1);
+    uint64_t end = start;
+    while (!f->runend[end]) end++;
+    if (x == quot) {
+      uint64_t p = start;
+      while (p <= end) {
+        uint64_t xr, c;
+        p = decode_entry(f->slot, f->r, p, end, &xr, &c);
+        if (p == (uint64_t)-1) return 0;
+        if (xr == rem) return c;
+        if (xr > rem) return 0;
+      }
+      return 0;
+    }
+    prev_end = (int64_t)end;
+  }
+  return 0;
+}
+
+void oqf_count_batch(const oqf_t *f, const uint64_t *keys, uint64_t n, uint64_t *out) {
+  for (uint64_t i = 0; i < n; i++) {
+    uint64_t quot, rem;
+    split(f, keys[i], &quot, &rem);
+    out[i] = count_fp(f, quot, rem);
+  }
+}
+
+void oqf_query_batch(const oqf_t *f, const uint64_t *keys, uint64_t n, uint8_t *out) {
+  for (uint64_t i = 0; i < n; i++) {
+    uint64_t quot, rem;
+    split(f, keys[i], &quot, &rem);
+    out[i] = count_fp(f, quot, rem) > 0;
+  }
+}
+
+/* ---- logical layout ----
+ * occ_words[N/64]    : bit x%64 of word x/64 = quotient x has a run
+ * runend_words[P/64] : bit j%64 of word j/64 = slot j ends a run
+ * slots[P]           : slot contents, 0 outside runs
+ * offsets[P/64]      : for block b with first slot i = 64b,
+ *                      max(0, select(runend, rank(occ, i)) - i), where rank
+ *                      counts occupied quotients <= i and select(0) = -inf
+ * header[8]          : q, r, N, E, P, used slots, distinct fingerprints,
+ *                      total count */
+int oqf_export(const oqf_t *f, uint64_t *occ_words, uint64_t *runend_words, uint16_t *slots,
+               uint32_t *offsets, uint64_t *header) {
+  if (!f) return OQF_ERR_ARG;
+  memset(occ_words, 0, (f->N / 64) * sizeof(uint64_t));
+  memset(runend_words, 0, (f->P / 64) * sizeof(uint64_t));
+  for (uint64_t x = 0; x < f->N; x++)
+    if (f->occ[x]) occ_words[x / 64] |= 1ULL << (x % 64);
+  for (uint64_t j = 0; j < f->P; j++) {
+    if (f->runend[j]) runend_words[j / 64] |= 1ULL << (j % 64);
+    slots[j] = f->slot[j];
+  }
+  /* offsets: walk the slots once, pairing the k-th occupied quotient with
+   * the k-th run end */
+  uint64_t nblocks = f->P / 64;
+  uint64_t k_occ = 0;     /* occupied quotients <= i */
+  uint64_t k_end = 0;     /* run ends seen so far (positions < scan) */
+  uint64_t scan = 0;      /* next slot to examine for run ends */
+  int64_t kth_end = -1;   /* position of the k_occ-th run end */
+  uint64_t xq = 0;        /* next quotient to count */
+  for (uint64_t b = 0; b < nblocks; b++) {
+    uint64_t i = 64 * b;
+    while (xq <= i && xq < f->N) { k_occ += f->occ[xq]; xq++; }
+    if (k_occ == 0) { offsets[b] = 0; continue; }
+    while (k_end < k_occ) {
+      if (f->runend[scan]) { k_end++; if (k_end == k_occ) kth_end = (int64_t)scan; }
+      scan++;
+    }
+    int64_t o = kth_end - (int64_t)i;
+    offsets[b] = o > 0 ? (uint32_t)o : 0;
+  }
+  header[0] = f->q;
+  header[1] = f->r;
+  header[2] = f->N;
+  header[3] = f->E;
+  header[4] = f->P;
+  header[5] = f->used_slots;
+  header[6] = f->distinct;
+  header[7] = f->total;
+  return OQF_OK;
+}
+
+/* longest cluster (contiguous used slots), for the cluster-length checks */
+uint64_t oqf_max_cluster(const oqf_t *f) {
+  uint64_t best = 0, cur = 0;
+  for (uint64_t j = 0; j < f->P; j++) {
+    cur = f->used[j] ? cur + 1 : 0;
+    if (cur > best) best = cur;
+  }
+  return best;
+}
