@@ -122,6 +122,27 @@ uint64_t qf_table_bytes(uint32_t q, uint32_t r);
 /* info[0..7] = q, r, N, E, P, region slots, device bytes held, batches run. */
 int qf_info(const qf_t *f, uint64_t *info);
 
+/* Kernel timing (for benchmarks): while enabled, every kernel launch of this
+ * filter is bracketed by two HIP events recorded on the launch stream.
+ * qf_profile_read waits for the recorded events, returns per kind the summed
+ * milliseconds ms[k] and the number of launches n[k] since the last read
+ * (arrays of QF_PROF_KINDS entries, host memory) and clears them.  The sort
+ * kinds count each radix pass as one launch; QF_PROF_REDUCE covers the four
+ * small kernels of the duplicate reduction. */
+enum {
+  QF_PROF_HASH = 0,
+  QF_PROF_SORT_HIST = 1,
+  QF_PROF_SORT_SCAN = 2,
+  QF_PROF_SORT_SCATTER = 3,
+  QF_PROF_REDUCE = 4,
+  QF_PROF_BOUNDS = 5,
+  QF_PROF_MERGE = 6,
+  QF_PROF_LOOKUP = 7,
+  QF_PROF_KINDS = 8
+};
+int qf_profile_enable(qf_t *f, int enable);
+int qf_profile_read(qf_t *f, double *ms, uint64_t *n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -247,6 +247,39 @@ def changed_blocks(a: Layout, b: Layout) -> int:
     return int(ch.sum())
 
 
+def run_bounds(L: Layout):
+    """(occupied quotients, run starts, run ends) of a table, in quotient order."""
+    q = int(L.header[0])
+    occ = bits(L.occ_words, 1 << q)
+    rq = np.nonzero(occ)[0].astype(np.int64)
+    re = np.nonzero(bits(L.runend_words, int(L.header[4])))[0].astype(np.int64)
+    prev = np.empty_like(re)
+    if len(re):
+        prev[0] = -1
+        prev[1:] = re[:-1]
+    rs = np.maximum(rq, prev + 1)
+    return rq, rs, re
+
+
+def query_blocks(L: Layout, fps: np.ndarray) -> int:
+    """Distinct 64-slot blocks a batch of lookups must read: each key's home
+    block (its occupied bit and offset) plus, when its quotient has a run, the
+    blocks that hold that run."""
+    r = int(L.header[1])
+    nb = len(L.offsets)
+    rq, rs, re = run_bounds(L)
+    x = (np.asarray(fps, dtype=U64) >> U64(r)).astype(np.int64)
+    mark = np.zeros(nb + 1, dtype=np.int64)
+    np.add.at(mark, x // 64, 1)
+    np.add.at(mark, x // 64 + 1, -1)
+    k = np.searchsorted(rq, x)
+    kc = np.minimum(k, max(len(rq) - 1, 0))
+    hit = (k < len(rq)) & (rq[kc] == x) if len(rq) else np.zeros(len(x), dtype=bool)
+    np.add.at(mark, rs[kc[hit]] // 64, 1)
+    np.add.at(mark, re[kc[hit]] // 64 + 1, -1)
+    return int((np.cumsum(mark)[:nb] > 0).sum())
+
+
 def bits(words: np.ndarray, n: int) -> np.ndarray:
     return np.unpackbits(np.asarray(words, dtype="<u8").view(np.uint8), bitorder="little")[:n].astype(bool)
 

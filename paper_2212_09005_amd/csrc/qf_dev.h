@@ -1,0 +1,205 @@
+// qf_dev.h -- device-side building blocks of the MI355X counting quotient filter.
+//
+// Physical table (one of the two copies the library alternates between):
+//   blocks[b]  : 64 slots = { uint64 occupieds; uint64 runends; T slot[64] }
+//                (80 B for r = 8, 144 B for r = 16), array of structs so that a
+//                lookup finds the metadata and most of its run in one or two
+//                128-byte lines;
+//   offsets[b] : uint32, distance from slot 64b to the end of the run of the
+//                last occupied quotient <= 64b (0 if that end lies before 64b).
+// Quotient x's occupied bit is bit x%64 of blocks[x/64].occupieds, slot j's
+// run-end bit is bit j%64 of blocks[j/64].runends (Sec. 5.1: runs, clusters;
+// the rank/select metadata is this library's reading of the paper's CQF).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qf {
+
+template <typename T>
+struct Block {
+  uint64_t occ;
+  uint64_t rend;
+  T s[64];
+};
+
+// Device state words of one filter.
+enum : int {
+  ST_CUR = 0,     // which table copy is current (0/1)
+  ST_ERR = 1,     // first deferred error code (as int64), 0 = none
+  ST_USED = 2,    // used slots of the current table
+  ST_DIST = 3,    // distinct fingerprints
+  ST_TOTAL = 4,   // total count (mod 2^64)
+  ST_NUSED = 5,   // the same three for the table being written
+  ST_NDIST = 6,
+  ST_NTOTAL = 7,
+  ST_TILE = 8,    // region tile counter of the merge launch
+  ST_DONE = 9,    // finished regions of the merge launch
+  ST_BATCH = 10,  // error bits of the running batch
+  ST_NUNIQ = 11,  // distinct fingerprints in the running batch
+  ST_BATCHES = 12,
+  ST_SCRATCH = 13,  // sink for a NULL not-found pointer
+  ST_WORDS = 16
+};
+enum : uint64_t { BATCH_FULL = 1, BATCH_OVF = 2 };
+
+typedef unsigned long long ull;
+
+__device__ __forceinline__ uint64_t atomic_add_u64(uint64_t* p, uint64_t v) {
+  return atomicAdd(reinterpret_cast<ull*>(p), static_cast<ull>(v));
+}
+__device__ __forceinline__ void atomic_or_u64(uint64_t* p, uint64_t v) {
+  atomicOr(reinterpret_cast<ull*>(p), static_cast<ull>(v));
+}
+__device__ __forceinline__ void atomic_and_u64(uint64_t* p, uint64_t v) {
+  atomicAnd(reinterpret_cast<ull*>(p), static_cast<ull>(v));
+}
+
+// SplitMix64 finalizer (Steele, Lea, Flood 2014; Stafford's "Mix13"
+// constants): the key hash.  A bijection on 64-bit words.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z ^= z >> 30;
+  z *= 0xbf58476d1ce4e5b9ull;
+  z ^= z >> 27;
+  z *= 0x94d049bb133111ebull;
+  z ^= z >> 31;
+  return z;
+}
+
+__device__ __forceinline__ int popc64(uint64_t v) { return __popcll(v); }
+__device__ __forceinline__ int ctz64(uint64_t v) { return __builtin_ctzll(v); }
+__device__ __forceinline__ int msb64(uint64_t v) { return 63 - __builtin_clzll(v); }
+// index of the k-th (0-based) set bit of v; v has more than k set bits
+__device__ __forceinline__ int select64(uint64_t v, int k) {
+  for (; k > 0; --k) v &= v - 1;
+  return ctz64(v);
+}
+
+// ---- run placement as a max-plus map --------------------------------------
+// A run of quotient x and length L placed after a previous end e ends at
+// max(x, e + 1) + L - 1 = max(x + L - 1, e + L): a map c -> max(A, c + B).
+// Such maps compose associatively, so the end of every run (and the carry
+// across regions) is a prefix scan over them.  Ends are >= -1, -1 = "none".
+struct Fn {
+  int64_t A, B;
+};
+__device__ __forceinline__ Fn fn_id() { return Fn{-1, 0}; }
+// g first, then h
+__device__ __forceinline__ Fn fn_then(Fn g, Fn h) {
+  return Fn{max(h.A, g.A + h.B), g.B + h.B};
+}
+__device__ __forceinline__ int64_t fn_apply(Fn f, int64_t c) { return max(f.A, c + f.B); }
+
+// ---- tagged words for the merge's look-back ---------------------------------
+// 16-bit launch epoch | 48-bit value + 1.  Each word is written once per
+// launch with one agent-scope atomic store, so a reader that sees the current
+// epoch sees the value; no fences are needed.
+__device__ __forceinline__ void tag_store(uint64_t* p, uint32_t epoch, int64_t v) {
+  const uint64_t w = (static_cast<uint64_t>(epoch) << 48) | static_cast<uint64_t>(v + 1);
+  __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool tag_load(const uint64_t* p, uint32_t epoch, int64_t* v) {
+  const uint64_t w = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if ((w >> 48) != epoch) return false;
+  *v = static_cast<int64_t>(w & ((1ull << 48) - 1)) - 1;
+  return true;
+}
+
+// ---- counter encoding --------------------------------------------------------
+// One (remainder x, count c) entry in r-bit slots, digit base B = 2^r - 1:
+//   c = 1: [x];  c = 2: [x, x];
+//   c >= 3, x > 0: [x, (0), digits of c-3 (MSB first, d >= x stored d+1), x],
+//                  the 0 present when the first stored digit would exceed x;
+//   c >= 3, x = 0: [0, 0, 0, digits + 1, 0].
+// (Sec. 2 and Sec. 6.7 only say that counters are variable-size and embedded
+// in the slots; this is the library's reading, shared by the export format.)
+__device__ __forceinline__ uint32_t enc_len(uint64_t x, uint64_t c, uint32_t r) {
+  if (c <= 2) return static_cast<uint32_t>(c);
+  const uint64_t base = (1ull << r) - 1;
+  const uint64_t v = c - 3;
+  uint32_t nd = 1;
+  uint64_t pw = 1;
+  while (v / pw >= base) {
+    pw *= base;
+    ++nd;
+  }
+  if (x > 0) return 2 + nd + ((v / pw) >= x ? 1u : 0u);
+  return 4 + nd;
+}
+
+template <class Out>
+__device__ __forceinline__ int64_t enc_put(Out& out, int64_t pos, uint64_t x, uint64_t c,
+                                           uint32_t r) {
+  if (c <= 2) {
+    out.emit(pos++, x);
+    if (c == 2) out.emit(pos++, x);
+    return pos;
+  }
+  const uint64_t base = (1ull << r) - 1;
+  uint64_t v = c - 3;
+  uint64_t pw = 1;
+  while (v / pw >= base) pw *= base;
+  if (x > 0) {
+    out.emit(pos++, x);
+    if (v / pw >= x) out.emit(pos++, 0);
+    for (;;) {
+      const uint64_t d = v / pw;
+      v -= d * pw;
+      out.emit(pos++, d < x ? d : d + 1);
+      if (pw == 1) break;
+      pw /= base;
+    }
+    out.emit(pos++, x);
+  } else {
+    out.emit(pos++, 0);
+    out.emit(pos++, 0);
+    out.emit(pos++, 0);
+    for (;;) {
+      const uint64_t d = v / pw;
+      v -= d * pw;
+      out.emit(pos++, d + 1);
+      if (pw == 1) break;
+      pw /= base;
+    }
+    out.emit(pos++, 0);
+  }
+  return pos;
+}
+
+// Decode the entry that starts at slot p of a run ending at slot e; returns the
+// slot after it.  `Old` provides slot(j).
+template <class Old>
+__device__ __forceinline__ int64_t dec_entry(const Old& o, int64_t p, int64_t e, uint32_t r,
+                                             uint64_t& x, uint64_t& c) {
+  const uint64_t base = (1ull << r) - 1;
+  x = o.slot(p);
+  if (x > 0) {
+    if (p == e) { c = 1; return p + 1; }
+    const uint64_t s1 = o.slot(p + 1);
+    if (s1 > x) { c = 1; return p + 1; }
+    if (s1 == x) { c = 2; return p + 2; }
+    uint64_t v = 0;
+    int64_t q = p + 1;
+    for (; q <= e; ++q) {
+      const uint64_t s = o.slot(q);
+      if (s == x) break;
+      v = v * base + (s < x ? s : s - 1);
+    }
+    c = v + 3;
+    return q + 1;
+  }
+  if (p == e || o.slot(p + 1) != 0) { c = 1; return p + 1; }
+  if (p + 1 == e || o.slot(p + 2) != 0) { c = 2; return p + 2; }
+  uint64_t v = 0;
+  int64_t q = p + 3;
+  for (; q <= e; ++q) {
+    const uint64_t s = o.slot(q);
+    if (s == 0) break;
+    v = v * base + (s - 1);
+  }
+  c = v + 3;
+  return q + 1;
+}
+
+}  // namespace qf

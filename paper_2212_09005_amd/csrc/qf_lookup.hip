@@ -1,0 +1,209 @@
+// qf_lookup.hip -- bulk query and count (Sec. 6.2; API table of Sec. 6), and
+// the conversions between the physical table and the logical layout.
+//
+// One lane per key: hash, split the fingerprint, read the home block's
+// occupieds word; if the quotient has a run, locate its end with the block
+// offset plus rank (popcount of occupieds) and select (walk of the run-end
+// words), its start as one past the previous run end (or the quotient itself),
+// then decode the run's entries in remainder order until the remainder is
+// reached or passed.
+#include "qf_dev.h"
+#include "qf.h"
+#include "qf_lib.h"
+
+namespace qf {
+namespace {
+
+constexpr int NT = 256;
+
+template <typename T>
+__device__ __forceinline__ uint64_t lookup_one(const Block<T> *__restrict__ b,
+                                               const uint32_t *__restrict__ off, int64_t nblocks,
+                                               int64_t x, uint64_t rem, uint32_t r) {
+  const int64_t bi = x >> 6;
+  const int bit = static_cast<int>(x & 63);
+  const uint64_t occ = b[bi].occ;
+  if (!((occ >> bit) & 1ull)) return 0;
+  int d = popc64(occ & ((2ull << bit) - 2ull));  // occupied quotients in (64*bi, x]
+  const int64_t p = (bi << 6) + off[bi];
+  int64_t e;
+  if (d == 0) {
+    e = p;
+  } else {
+    // d-th run end strictly after p
+    int64_t w = (p + 1) >> 6;
+    if (w >= nblocks) return 0;
+    uint64_t m = b[w].rend & (~0ull << ((p + 1) & 63));
+    for (;;) {
+      const int pc = popc64(m);
+      if (pc >= d) {
+        e = (w << 6) + select64(m, d - 1);
+        break;
+      }
+      d -= pc;
+      if (++w >= nblocks) return 0;
+      m = b[w].rend;
+    }
+  }
+  // run start: one past the last run end in [x, e-1], else x
+  int64_t s = x;
+  if (e > x) {
+    int64_t w = (e - 1) >> 6;
+    const int64_t wx = x >> 6;
+    uint64_t m = b[w].rend & (~0ull >> (63 - ((e - 1) & 63)));
+    for (;;) {
+      if (w == wx) m &= ~0ull << (x & 63);
+      if (m) {
+        s = (w << 6) + msb64(m) + 1;
+        break;
+      }
+      if (w == wx) break;
+      m = b[--w].rend;
+    }
+  }
+  struct G {
+    const Block<T> *b;
+    __device__ uint64_t slot(int64_t j) const { return b[j >> 6].s[j & 63]; }
+  } g{b};
+  int64_t pos = s;
+  while (pos <= e) {
+    uint64_t xr, c;
+    pos = dec_entry(g, pos, e, r, xr, c);
+    if (xr == rem) return c;
+    if (xr > rem) return 0;
+  }
+  return 0;
+}
+
+template <typename T, bool COUNT>
+__global__ __launch_bounds__(NT) void k_lookup(const Block<T> *b0, const Block<T> *b1,
+                                               const uint32_t *o0, const uint32_t *o1,
+                                               const uint64_t *state,
+                                               const uint64_t *__restrict__ keys, uint64_t n,
+                                               uint32_t q, uint32_t r, int64_t nblocks,
+                                               uint8_t *__restrict__ out8,
+                                               uint64_t *__restrict__ out64) {
+  const int cur = static_cast<int>(state[ST_CUR] & 1ull);
+  const Block<T> *b = cur ? b1 : b0;
+  const uint32_t *off = cur ? o1 : o0;
+  const uint32_t p = q + r;
+  const uint64_t pmask = p >= 64 ? ~0ull : ((1ull << p) - 1ull);
+  const uint64_t rmask = (1ull << r) - 1ull;
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * NT;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * NT + threadIdx.x; i < n; i += stride) {
+    const uint64_t fp = mix64(keys[i]) & pmask;
+    const uint64_t c = lookup_one(b, off, nblocks, static_cast<int64_t>(fp >> r), fp & rmask, r);
+    if (COUNT)
+      out64[i] = c;
+    else
+      out8[i] = c != 0;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_export(const Block<T> *b0, const Block<T> *b1,
+                                               const uint32_t *o0, const uint32_t *o1,
+                                               const uint64_t *state, int64_t nblocks,
+                                               int64_t nqblocks, uint64_t *occ, uint64_t *rend,
+                                               uint16_t *slots, uint32_t *offs) {
+  const int cur = static_cast<int>(state[ST_CUR] & 1ull);
+  const Block<T> *b = cur ? b1 : b0;
+  const uint32_t *off = cur ? o1 : o0;
+  const uint64_t total = static_cast<uint64_t>(nblocks) * 64;
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * NT;
+  for (uint64_t j = static_cast<uint64_t>(blockIdx.x) * NT + threadIdx.x; j < total; j += stride) {
+    const int64_t bi = static_cast<int64_t>(j >> 6);
+    slots[j] = static_cast<uint16_t>(b[bi].s[j & 63]);
+    if ((j & 63) == 0) {
+      rend[bi] = b[bi].rend;
+      offs[bi] = off[bi];
+      if (bi < nqblocks) occ[bi] = b[bi].occ;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_import(Block<T> *b, uint32_t *off, int64_t nblocks,
+                                               int64_t nqblocks, const uint64_t *occ,
+                                               const uint64_t *rend, const uint16_t *slots,
+                                               const uint32_t *offs) {
+  const uint64_t total = static_cast<uint64_t>(nblocks) * 64;
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * NT;
+  for (uint64_t j = static_cast<uint64_t>(blockIdx.x) * NT + threadIdx.x; j < total; j += stride) {
+    const int64_t bi = static_cast<int64_t>(j >> 6);
+    b[bi].s[j & 63] = static_cast<T>(slots[j]);
+    if ((j & 63) == 0) {
+      b[bi].rend = rend[bi];
+      off[bi] = offs[bi];
+      b[bi].occ = bi < nqblocks ? occ[bi] : 0ull;
+    }
+  }
+}
+
+inline uint32_t grid_for(uint64_t n) {
+  uint64_t g = (n + NT - 1) / NT;
+  if (g < 1) g = 1;
+  if (g > 262140) g = 262140;
+  return static_cast<uint32_t>(g);
+}
+
+template <typename T>
+hipError_t lookup_t(qf_filter *f, const uint64_t *keys, uint64_t n, uint8_t *out8,
+                    uint64_t *out64, hipStream_t s) {
+  const Block<T> *b0 = static_cast<const Block<T> *>(f->blk[0]);
+  const Block<T> *b1 = static_cast<const Block<T> *>(f->blk[1]);
+  if (f->timer) f->timer->begin(QF_PROF_LOOKUP, s);
+  if (out64)
+    k_lookup<T, true><<<grid_for(n), NT, 0, s>>>(b0, b1, f->off[0], f->off[1], f->state, keys, n,
+                                                 f->q, f->r, static_cast<int64_t>(f->nblocks),
+                                                 nullptr, out64);
+  else
+    k_lookup<T, false><<<grid_for(n), NT, 0, s>>>(b0, b1, f->off[0], f->off[1], f->state, keys, n,
+                                                  f->q, f->r, static_cast<int64_t>(f->nblocks),
+                                                  out8, nullptr);
+  if (f->timer) f->timer->end(QF_PROF_LOOKUP, s);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+uint64_t table_bytes(uint64_t nblocks, uint32_t r) {
+  const uint64_t bb = r == 8 ? sizeof(Block<uint8_t>) : sizeof(Block<uint16_t>);
+  return nblocks * bb + nblocks * sizeof(uint32_t);
+}
+
+hipError_t launch_lookup(qf_filter *f, const uint64_t *keys, uint64_t n, uint8_t *out8,
+                         uint64_t *out64, hipStream_t s) {
+  if (f->r == 8) return lookup_t<uint8_t>(f, keys, n, out8, out64, s);
+  return lookup_t<uint16_t>(f, keys, n, out8, out64, s);
+}
+
+hipError_t launch_export(qf_filter *f, uint64_t *occ, uint64_t *rend, uint16_t *slots,
+                         uint32_t *offs, hipStream_t s) {
+  const uint64_t total = f->nblocks * 64;
+  const int64_t nb = static_cast<int64_t>(f->nblocks), nq = static_cast<int64_t>(f->N / 64);
+  if (f->r == 8)
+    k_export<uint8_t><<<grid_for(total), NT, 0, s>>>(
+        static_cast<const Block<uint8_t> *>(f->blk[0]), static_cast<const Block<uint8_t> *>(f->blk[1]),
+        f->off[0], f->off[1], f->state, nb, nq, occ, rend, slots, offs);
+  else
+    k_export<uint16_t><<<grid_for(total), NT, 0, s>>>(
+        static_cast<const Block<uint16_t> *>(f->blk[0]), static_cast<const Block<uint16_t> *>(f->blk[1]),
+        f->off[0], f->off[1], f->state, nb, nq, occ, rend, slots, offs);
+  return hipGetLastError();
+}
+
+hipError_t launch_import(qf_filter *f, const uint64_t *occ, const uint64_t *rend,
+                         const uint16_t *slots, const uint32_t *offs, hipStream_t s) {
+  const uint64_t total = f->nblocks * 64;
+  const int64_t nb = static_cast<int64_t>(f->nblocks), nq = static_cast<int64_t>(f->N / 64);
+  if (f->r == 8)
+    k_import<uint8_t><<<grid_for(total), NT, 0, s>>>(static_cast<Block<uint8_t> *>(f->blk[0]), f->off[0],
+                                                     nb, nq, occ, rend, slots, offs);
+  else
+    k_import<uint16_t><<<grid_for(total), NT, 0, s>>>(static_cast<Block<uint16_t> *>(f->blk[0]), f->off[0],
+                                                      nb, nq, occ, rend, slots, offs);
+  return hipGetLastError();
+}
+
+}  // namespace qf

@@ -1,0 +1,309 @@
+// qf_sort.hip -- batch preparation: hash, radix sort, reduction to <fingerprint,
+// count> and region bounds.
+//
+// Sec. 5.3 (Sorting hashes): the batch is hashed and sorted so that a region
+// can take its items in remainder order and the buffers of the regions are
+// contiguous pieces of the sorted input, found by successor search.
+// Sec. 5.4: duplicates are reduced to <item, count> pairs before the insert.
+// The sort is an LSD radix sort written for wave64: 8-bit digits, one LDS
+// histogram per wave, stable ranks from wave ballots.
+#include "qf_dev.h"
+#include "qf.h"
+#include "qf_lib.h"
+
+namespace qf {
+namespace {
+
+constexpr int NT = 256;
+constexpr int NWAVE = NT / 64;
+constexpr uint64_t SORT_MIN_CHUNK = 4096;
+constexpr uint32_t SORT_MAX_GROUPS = 1024;
+
+__device__ __forceinline__ uint64_t chunk_lo(uint64_t n, uint32_t G, uint32_t g) {
+  return (n * g) / G;
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  return (1ull << __lane_id()) - 1ull;
+}
+
+__global__ __launch_bounds__(NT) void k_hash(const uint64_t *__restrict__ keys, uint64_t n,
+                                             uint64_t pmask, uint64_t *__restrict__ fp) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * NT;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * NT + threadIdx.x; i < n; i += stride)
+    fp[i] = mix64(keys[i]) & pmask;
+}
+
+__global__ __launch_bounds__(NT) void k_fill(uint64_t *p, uint64_t n, uint64_t v) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * NT;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * NT + threadIdx.x; i < n; i += stride)
+    p[i] = v;
+}
+
+// per-group digit histogram, stored digit-major: hist[d * G + g]
+__global__ __launch_bounds__(NT) void k_rs_hist(const uint64_t *__restrict__ in, uint64_t n,
+                                                uint32_t G, uint32_t shift,
+                                                uint32_t *__restrict__ hist) {
+  __shared__ uint32_t h[NWAVE][256];
+  const int tid = threadIdx.x, wv = tid >> 6;
+  for (int d = tid; d < 256; d += NT)
+    for (int w = 0; w < NWAVE; ++w) h[w][d] = 0;
+  __syncthreads();
+  const uint32_t g = blockIdx.x;
+  const uint64_t lo = chunk_lo(n, G, g), hi = chunk_lo(n, G, g + 1);
+  for (uint64_t i = lo + tid; i < hi; i += NT) atomicAdd(&h[wv][(in[i] >> shift) & 255u], 1u);
+  __syncthreads();
+  for (int d = tid; d < 256; d += NT) {
+    uint32_t t = 0;
+    for (int w = 0; w < NWAVE; ++w) t += h[w][d];
+    hist[static_cast<uint64_t>(d) * G + g] = t;
+  }
+}
+
+// exclusive scan of a[0..n) in place by one work-group of 1024 threads;
+// the total goes to *total if it is not null
+__global__ __launch_bounds__(1024) void k_scan_u32(uint32_t *a, uint32_t n, uint64_t *total) {
+  __shared__ uint32_t part[1024];
+  const int tid = threadIdx.x;
+  const uint32_t per = (n + 1023) / 1024;
+  const uint32_t lo = min(n, tid * per), hi = min(n, lo + per);
+  uint32_t s = 0;
+  for (uint32_t i = lo; i < hi; ++i) s += a[i];
+  part[tid] = s;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    const uint32_t v = tid >= d ? part[tid - d] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[tid] - s;
+  for (uint32_t i = lo; i < hi; ++i) {
+    const uint32_t v = a[i];
+    a[i] = run;
+    run += v;
+  }
+  if (tid == 1023 && total) *total = part[1023];
+}
+
+// stable scatter of one digit; each group walks its chunk 256 keys at a time
+__global__ __launch_bounds__(NT) void k_rs_scatter(const uint64_t *__restrict__ in,
+                                                   uint64_t *__restrict__ out, uint64_t n,
+                                                   uint32_t G, uint32_t shift, uint32_t nbits,
+                                                   const uint32_t *__restrict__ hist) {
+  __shared__ uint32_t base[256];
+  __shared__ uint32_t wc[NWAVE][256];
+  const int tid = threadIdx.x, wv = tid >> 6;
+  const uint32_t g = blockIdx.x;
+  for (int d = tid; d < 256; d += NT) {
+    base[d] = hist[static_cast<uint64_t>(d) * G + g];
+    for (int w = 0; w < NWAVE; ++w) wc[w][d] = 0;
+  }
+  __syncthreads();
+  const uint64_t lo = chunk_lo(n, G, g), hi = chunk_lo(n, G, g + 1);
+  const uint32_t dmask = (1u << nbits) - 1u;
+  for (uint64_t r0 = lo; r0 < hi; r0 += NT) {
+    const uint64_t i = r0 + tid;
+    const bool valid = i < hi;
+    const uint64_t key = valid ? in[i] : 0;
+    const uint32_t d = static_cast<uint32_t>(key >> shift) & dmask;
+    uint64_t peers = __ballot(valid);
+    for (uint32_t b = 0; b < nbits; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bal = __ballot(bit);
+      peers &= bit ? bal : ~bal;
+    }
+    const uint32_t rank = static_cast<uint32_t>(popc64(peers & lanemask_lt()));
+    if (valid && rank == 0) wc[wv][d] = static_cast<uint32_t>(popc64(peers));
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = base[d] + rank;
+      for (int w = 0; w < wv; ++w) pos += wc[w][d];
+      out[pos] = key;
+    }
+    __syncthreads();
+    for (int dd = tid; dd < 256; dd += NT) {
+      uint32_t t = 0;
+      for (int w = 0; w < NWAVE; ++w) {
+        t += wc[w][dd];
+        wc[w][dd] = 0;
+      }
+      base[dd] += t;
+    }
+    __syncthreads();
+  }
+}
+
+// ---- run-length reduction -------------------------------------------------
+__device__ __forceinline__ bool is_head(const uint64_t *s, uint64_t i) {
+  return i == 0 || s[i] != s[i - 1];
+}
+
+__global__ __launch_bounds__(NT) void k_rle_count(const uint64_t *__restrict__ s, uint64_t n,
+                                                  uint32_t G, uint32_t *__restrict__ cnt) {
+  __shared__ uint32_t red[NWAVE];
+  const int tid = threadIdx.x;
+  const uint32_t g = blockIdx.x;
+  const uint64_t lo = chunk_lo(n, G, g), hi = chunk_lo(n, G, g + 1);
+  uint32_t c = 0;
+  for (uint64_t i = lo + tid; i < hi; i += NT) c += is_head(s, i);
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+  if ((tid & 63) == 0) red[tid >> 6] = c;
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < NWAVE; ++w) t += red[w];
+    cnt[g] = t;
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_rle_write(const uint64_t *__restrict__ s, uint64_t n,
+                                                  uint32_t G, const uint32_t *__restrict__ cnt,
+                                                  uint64_t *__restrict__ ufp,
+                                                  uint64_t *__restrict__ ustart) {
+  __shared__ uint32_t wsum[NWAVE];
+  __shared__ uint32_t base_s;
+  const int tid = threadIdx.x, wv = tid >> 6;
+  const uint32_t g = blockIdx.x;
+  const uint64_t lo = chunk_lo(n, G, g), hi = chunk_lo(n, G, g + 1);
+  if (tid == 0) base_s = cnt[g];
+  __syncthreads();
+  for (uint64_t r0 = lo; r0 < hi; r0 += NT) {
+    const uint64_t i = r0 + tid;
+    const bool h = i < hi && is_head(s, i);
+    const uint64_t bal = __ballot(h);
+    if ((tid & 63) == 0) wsum[wv] = static_cast<uint32_t>(popc64(bal));
+    __syncthreads();
+    uint32_t pos = base_s + static_cast<uint32_t>(popc64(bal & lanemask_lt()));
+    for (int w = 0; w < wv; ++w) pos += wsum[w];
+    if (h) {
+      ufp[pos] = s[i];
+      ustart[pos] = i;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t t = 0;
+      for (int w = 0; w < NWAVE; ++w) t += wsum[w];
+      base_s += t;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_rle_counts(const uint64_t *__restrict__ ustart,
+                                                   uint64_t n, const uint64_t *state,
+                                                   uint64_t *__restrict__ ucnt) {
+  const uint64_t u = state[ST_NUNIQ];
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * NT;
+  for (uint64_t j = static_cast<uint64_t>(blockIdx.x) * NT + threadIdx.x; j < u; j += stride)
+    ucnt[j] = (j + 1 < u ? ustart[j + 1] : n) - ustart[j];
+}
+
+// Successor search (Sec. 5.3): rb[R] = first reduced entry whose quotient is
+// >= the first quotient of region R; regions past the quotients get u.  Also
+// resets the per-launch words of the merge that follows.
+__global__ __launch_bounds__(NT) void k_bounds(const uint64_t *__restrict__ ufp,
+                                               uint64_t *state, uint32_t nregions,
+                                               uint32_t nqregions, uint32_t shift,
+                                               uint64_t *__restrict__ rb) {
+  const uint32_t R = blockIdx.x * NT + threadIdx.x;
+  if (R == 0) {
+    state[ST_TILE] = 0;
+    state[ST_DONE] = 0;
+    state[ST_BATCH] = 0;
+    state[ST_NUSED] = 0;
+    state[ST_NDIST] = 0;
+    state[ST_NTOTAL] = 0;
+  }
+  if (R > nregions) return;
+  const uint64_t u = state[ST_NUNIQ];
+  if (R >= nqregions) {
+    rb[R] = u;
+    return;
+  }
+  const uint64_t key = static_cast<uint64_t>(R) << shift;
+  uint64_t lo = 0, hi = u;
+  while (lo < hi) {
+    const uint64_t mid = (lo + hi) >> 1;
+    if (ufp[mid] < key)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  rb[R] = lo;
+}
+
+inline uint32_t blocks_for(uint64_t n, uint32_t cap = 65535u * 4u) {
+  const uint64_t b = (n + NT - 1) / NT;
+  return static_cast<uint32_t>(b < 1 ? 1 : (b > cap ? cap : b));
+}
+
+}  // namespace
+
+uint32_t sort_groups(uint64_t n) {
+  uint64_t g = (n + SORT_MIN_CHUNK - 1) / SORT_MIN_CHUNK;
+  if (g < 1) g = 1;
+  if (g > SORT_MAX_GROUPS) g = SORT_MAX_GROUPS;
+  return static_cast<uint32_t>(g);
+}
+
+hipError_t launch_hash(const uint64_t *keys, uint64_t n, uint64_t pmask, uint64_t *fp,
+                       hipStream_t s, Timer *t) {
+  if (t) t->begin(QF_PROF_HASH, s);
+  k_hash<<<blocks_for(n), NT, 0, s>>>(keys, n, pmask, fp);
+  if (t) t->end(QF_PROF_HASH, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_fill<<<blocks_for(n), NT, 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort(uint64_t *a, uint64_t *b, uint64_t n, uint32_t bits, uint32_t *hist,
+                       uint64_t **result, hipStream_t s, Timer *t) {
+  const uint32_t G = sort_groups(n);
+  uint64_t *in = a, *out = b;
+  for (uint32_t shift = 0; shift < bits; shift += 8) {
+    const uint32_t nb = bits - shift < 8 ? bits - shift : 8;
+    if (t) t->begin(QF_PROF_SORT_HIST, s);
+    k_rs_hist<<<G, NT, 0, s>>>(in, n, G, shift, hist);
+    if (t) t->end(QF_PROF_SORT_HIST, s);
+    if (t) t->begin(QF_PROF_SORT_SCAN, s);
+    k_scan_u32<<<1, 1024, 0, s>>>(hist, 256u * G, nullptr);
+    if (t) t->end(QF_PROF_SORT_SCAN, s);
+    if (t) t->begin(QF_PROF_SORT_SCATTER, s);
+    k_rs_scatter<<<G, NT, 0, s>>>(in, out, n, G, shift, nb, hist);
+    if (t) t->end(QF_PROF_SORT_SCATTER, s);
+    uint64_t *t = in;
+    in = out;
+    out = t;
+  }
+  *result = in;
+  return hipGetLastError();
+}
+
+hipError_t launch_rle(const uint64_t *sorted, uint64_t n, uint64_t *scratch_start,
+                      uint64_t *ufp, uint64_t *ucnt, uint32_t *tile_counts, uint64_t *state,
+                      hipStream_t s, Timer *t) {
+  const uint32_t G = sort_groups(n);
+  if (t) t->begin(QF_PROF_REDUCE, s);
+  k_rle_count<<<G, NT, 0, s>>>(sorted, n, G, tile_counts);
+  k_scan_u32<<<1, 1024, 0, s>>>(tile_counts, G, state + ST_NUNIQ);
+  k_rle_write<<<G, NT, 0, s>>>(sorted, n, G, tile_counts, ufp, scratch_start);
+  k_rle_counts<<<blocks_for(n), NT, 0, s>>>(scratch_start, n, state, ucnt);
+  if (t) t->end(QF_PROF_REDUCE, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_bounds(const uint64_t *ufp, uint64_t *state, qf_filter *f, hipStream_t s) {
+  const uint32_t nthreads = f->nregions + 1;
+  if (f->timer) f->timer->begin(QF_PROF_BOUNDS, s);
+  k_bounds<<<(nthreads + NT - 1) / NT, NT, 0, s>>>(ufp, state, f->nregions, f->nqregions,
+                                                   f->rlog + f->r, f->rb);
+  if (f->timer) f->timer->end(QF_PROF_BOUNDS, s);
+  return hipGetLastError();
+}
+
+}  // namespace qf

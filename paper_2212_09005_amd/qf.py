@@ -1,0 +1,285 @@
+"""Python binding of libqf.so (include/qf.h): the same calls, marshalled with ctypes.
+
+Only argument marshalling happens here: every step of insert / query / count /
+delete runs in the library's HIP kernels on the device that holds the tensors.
+PyTorch supplies device memory and streams.  If libqf.so has not been built,
+loading fails with an error instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "lib", "libqf.so")
+HEADER = os.path.join(os.path.dirname(_PKG), "include", "qf.h")
+
+QF_OK = 0
+QF_ERR_ARG = -1
+QF_ERR_FULL = -2
+QF_ERR_OOM = -3
+QF_ERR_DEVICE = -4
+QF_ERR_COUNT_OVERFLOW = -5
+ERRORS = {
+    QF_ERR_ARG: "QF_ERR_ARG",
+    QF_ERR_FULL: "QF_ERR_FULL",
+    QF_ERR_OOM: "QF_ERR_OOM",
+    QF_ERR_DEVICE: "QF_ERR_DEVICE",
+    QF_ERR_COUNT_OVERFLOW: "QF_ERR_COUNT_OVERFLOW",
+}
+
+
+class QFError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        super().__init__(f"{what}: {ERRORS.get(code, code)}")
+        self.code = code
+
+
+class _Layout(ctypes.Structure):
+    _fields_ = [
+        ("header", ctypes.c_uint64 * 8),
+        ("occ_words", ctypes.c_void_p),
+        ("runend_words", ctypes.c_void_p),
+        ("slots", ctypes.c_void_p),
+        ("offsets", ctypes.c_void_p),
+    ]
+
+
+@dataclass
+class QFLayout:
+    """Logical table as host arrays (see qf_layout_t in include/qf.h)."""
+
+    occ_words: np.ndarray  # uint64[N/64]
+    runend_words: np.ndarray  # uint64[P/64]
+    slots: np.ndarray  # uint16[P]
+    offsets: np.ndarray  # uint32[P/64]
+    header: np.ndarray  # uint64[8]
+
+
+_lib = None
+
+
+def declared_functions() -> list[str]:
+    """Names of the functions include/qf.h declares."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(qf_[a-z0-9_]+)\s*\(", txt)))
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with paper_2212_09005_amd/build.py "
+            "(or __graft_entry__.build()); there is no fallback implementation"
+        )
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    sig = {
+        "qf_create": (vp, [u32, u32]),
+        "qf_destroy": (None, [vp]),
+        "qf_insert_batch": (i32, [vp, vp, u64, vp]),
+        "qf_query_batch": (i32, [vp, vp, u64, vp, vp]),
+        "qf_count_batch": (i32, [vp, vp, u64, vp, vp]),
+        "qf_delete_batch": (i32, [vp, vp, u64, vp, vp]),
+        "qf_sync": (i32, [vp, vp]),
+        "qf_export": (i32, [vp, ctypes.POINTER(_Layout), vp]),
+        "qf_import": (i32, [vp, ctypes.POINTER(_Layout), vp]),
+        "qf_last_error": (i32, []),
+        "qf_table_bytes": (u64, [u32, u32]),
+        "qf_info": (i32, [vp, ctypes.POINTER(ctypes.c_uint64)]),
+        "qf_profile_enable": (i32, [vp, i32]),
+        "qf_profile_read": (i32, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _stream(stream) -> int | None:
+    if stream is not None:
+        return int(stream)
+    import torch
+
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dev_ptr(t, n: int | None = None, itemsize: int | None = None) -> int:
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if itemsize is not None and t.element_size() != itemsize:
+        raise ValueError(f"expected {itemsize}-byte elements, got {t.dtype}")
+    if n is not None and t.numel() < n:
+        raise ValueError("tensor too small")
+    return t.data_ptr()
+
+
+def _check(rc: int, what: str) -> int:
+    if rc != QF_OK:
+        raise QFError(rc, what)
+    return rc
+
+
+# ---- the C ABI, one wrapper per call ------------------------------------
+def qf_create(q: int, r: int) -> int:
+    h = lib().qf_create(q, r)
+    if not h:
+        raise QFError(lib().qf_last_error(), f"qf_create({q}, {r})")
+    return h
+
+
+def qf_destroy(f: int) -> None:
+    lib().qf_destroy(f)
+
+
+def qf_insert_batch(f: int, keys, stream=None) -> int:
+    n = keys.numel()
+    return lib().qf_insert_batch(f, _dev_ptr(keys, n, 8) if n else None, n, _stream(stream))
+
+
+def qf_query_batch(f: int, keys, out, stream=None) -> int:
+    n = keys.numel()
+    if not n:
+        return QF_OK
+    return lib().qf_query_batch(f, _dev_ptr(keys, n, 8), n, _dev_ptr(out, n, 1), _stream(stream))
+
+
+def qf_count_batch(f: int, keys, out, stream=None) -> int:
+    n = keys.numel()
+    if not n:
+        return QF_OK
+    return lib().qf_count_batch(f, _dev_ptr(keys, n, 8), n, _dev_ptr(out, n, 8), _stream(stream))
+
+
+def qf_delete_batch(f: int, keys, not_found=None, stream=None) -> int:
+    n = keys.numel()
+    nf = _dev_ptr(not_found, 1, 8) if not_found is not None else None
+    return lib().qf_delete_batch(f, _dev_ptr(keys, n, 8) if n else None, n, nf, _stream(stream))
+
+
+def qf_sync(f: int, stream=None) -> int:
+    return lib().qf_sync(f, _stream(stream))
+
+
+def qf_table_bytes(q: int, r: int) -> int:
+    return int(lib().qf_table_bytes(q, r))
+
+
+def qf_last_error() -> int:
+    return int(lib().qf_last_error())
+
+
+def qf_info(f: int) -> dict:
+    buf = (ctypes.c_uint64 * 8)()
+    _check(lib().qf_info(f, buf), "qf_info")
+    keys = ("q", "r", "N", "E", "P", "region_slots", "device_bytes", "batches")
+    return dict(zip(keys, (int(v) for v in buf)))
+
+
+PROF_KINDS = ("hash", "sort_hist", "sort_scan", "sort_scatter", "reduce", "bounds", "merge", "lookup")
+
+
+def qf_profile_enable(f: int, enable: bool = True) -> int:
+    return lib().qf_profile_enable(f, 1 if enable else 0)
+
+
+def qf_profile_read(f: int) -> dict:
+    """{kind: (milliseconds, launches)} since the last read."""
+    ms = (ctypes.c_double * len(PROF_KINDS))()
+    n = (ctypes.c_uint64 * len(PROF_KINDS))()
+    _check(lib().qf_profile_read(f, ms, n), "qf_profile_read")
+    return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(PROF_KINDS)}
+
+
+def qf_export(f: int, stream=None) -> tuple[int, QFLayout]:
+    info = qf_info(f)
+    N, P = info["N"], info["P"]
+    lay = QFLayout(
+        np.zeros(N // 64, np.uint64),
+        np.zeros(P // 64, np.uint64),
+        np.zeros(P, np.uint16),
+        np.zeros(P // 64, np.uint32),
+        np.zeros(8, np.uint64),
+    )
+    c = _Layout()
+    c.occ_words = lay.occ_words.ctypes.data
+    c.runend_words = lay.runend_words.ctypes.data
+    c.slots = lay.slots.ctypes.data
+    c.offsets = lay.offsets.ctypes.data
+    rc = lib().qf_export(f, ctypes.byref(c), _stream(stream))
+    lay.header[:] = np.frombuffer(bytes(c.header), dtype=np.uint64)
+    return rc, lay
+
+
+def qf_import(f: int, lay, stream=None) -> int:
+    arrays = [np.ascontiguousarray(lay.occ_words, np.uint64), np.ascontiguousarray(lay.runend_words, np.uint64),
+              np.ascontiguousarray(lay.slots, np.uint16), np.ascontiguousarray(lay.offsets, np.uint32)]
+    c = _Layout()
+    for i, v in enumerate(np.asarray(lay.header, dtype=np.uint64)):
+        c.header[i] = int(v)
+    c.occ_words, c.runend_words, c.slots, c.offsets = (a.ctypes.data for a in arrays)
+    return lib().qf_import(f, ctypes.byref(c), _stream(stream))
+
+
+class CQF:
+    """Owning handle: a counting quotient filter on the current HIP device."""
+
+    def __init__(self, q: int, r: int):
+        self.q, self.r = q, r
+        self.h = qf_create(q, r)
+
+    def close(self):
+        if getattr(self, "h", None):
+            qf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def insert(self, keys, stream=None):
+        _check(qf_insert_batch(self.h, keys, stream), "qf_insert_batch")
+
+    def delete(self, keys, not_found=None, stream=None):
+        _check(qf_delete_batch(self.h, keys, not_found, stream), "qf_delete_batch")
+
+    def query(self, keys, out=None, stream=None):
+        import torch
+
+        if out is None:
+            out = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device)
+        _check(qf_query_batch(self.h, keys, out, stream), "qf_query_batch")
+        return out
+
+    def count(self, keys, out=None, stream=None):
+        import torch
+
+        if out is None:
+            out = torch.empty(keys.numel(), dtype=torch.int64, device=keys.device)
+        _check(qf_count_batch(self.h, keys, out, stream), "qf_count_batch")
+        return out
+
+    def sync(self, stream=None) -> int:
+        return qf_sync(self.h, stream)
+
+    def export(self, stream=None) -> tuple[int, QFLayout]:
+        return qf_export(self.h, stream)
+
+    def load(self, lay, stream=None):
+        _check(qf_import(self.h, lay, stream), "qf_import")
+
+    def info(self) -> dict:
+        return qf_info(self.h)
