@@ -208,7 +208,7 @@ qf_t *qf_create(uint32_t q, uint32_t r) {
            hipMemset(f->off[c], 0, f->nblocks * sizeof(uint32_t)) == hipSuccess;
     }
   }
-  f->hist_words = 256ull * 1024ull;
+  f->hist_words = 256ull * 1024ull + 256ull * 8;  // histograms + per-pass digit totals
   ok = ok && hipMalloc(reinterpret_cast<void **>(&f->state), qf::ST_WORDS * sizeof(uint64_t)) == hipSuccess &&
        hipMalloc(reinterpret_cast<void **>(&f->rb), (f->nregions + 1ull) * sizeof(uint64_t)) == hipSuccess &&
        hipMalloc(reinterpret_cast<void **>(&f->tags), 3ull * f->nregions * sizeof(uint64_t)) == hipSuccess &&

@@ -11,20 +11,25 @@
 //   * The paper makes regions exclusive with two phases and a spill limit of
 //     one region.  Here a run's end is a max-plus map of the previous end,
 //     c -> max(A, c + B), and maps compose; each region publishes the
-//     composition of its runs, a decoupled look-back gives every region the
-//     exact end of all earlier runs (its carry-in), and no spill limit exists.
+//     composition of its runs, a wave-parallel decoupled look-back gives every
+//     region the exact end of all earlier runs (its carry-in), and there is no
+//     spill limit.
 //   * The table has two device copies; a batch reads the current one and
 //     writes the other, so no region reads what another region writes.  The
 //     last region to finish flips the current copy -- unless a run ran past
 //     the last slot or a count overflowed, which leaves the old copy current
 //     (all-or-nothing without a host round trip).
-//   * Inside a region, the old runs are staged in LDS; each of the 256 lanes
-//     merges a contiguous chunk of quotients; lane carries are a block scan of
-//     the same max-plus maps; the new runs are assembled in LDS and written out
-//     with coalesced stores.  Regions whose runs do not fit in LDS fall back
-//     to one lane reading and writing global memory directly.
-#include "qf_dev.h"
+//   * Inside a region: the old blocks and the region's new entries are staged
+//     in LDS with 16-byte loads; each of the 256 lanes owns a contiguous chunk
+//     of quotients.  Pass 1 composes the lanes' run maps; a run that receives
+//     no new entry keeps its length, read off the run-end bits without
+//     decoding.  A block scan of the maps gives each lane its carry; pass 2
+//     copies unchanged runs, decodes/merges/re-encodes the others, assembles
+//     the region's new slots in LDS and writes them with 16-byte stores.
+//     Regions whose runs or entries do not fit in LDS are done by one lane
+//     straight from and to global memory.
 #include "qf.h"
+#include "qf_dev.h"
 #include "qf_lib.h"
 
 namespace qf {
@@ -35,10 +40,16 @@ constexpr int64_t INF = INT64_MAX / 4;
 
 template <typename T>
 struct Cfg {
-  static constexpr int CAP = 16384 / static_cast<int>(sizeof(T));  // LDS slots per buffer
+  // largest region: 8192 slots (r = 8), 4096 (r = 16); LDS buffers hold 1.5
+  // regions of slots (a region's runs plus what spills past its end)
+  static constexpr int SMAXLOG = sizeof(T) == 1 ? 13 : 12;
+  static constexpr int SMAX = 1 << SMAXLOG;
+  static constexpr int CAP = SMAX + SMAX / 2;
   static constexpr int CAPW = CAP / 64;
-  static constexpr int SMAX = CAP / 2;  // largest region
   static constexpr int OW = SMAX / 64;
+  static constexpr int NCAP = 512;  // new entries staged in LDS (2 per lane)
+  static constexpr int CH = 64 * static_cast<int>(sizeof(T)) / 16;  // 16-byte chunks per block
+  static constexpr int PER = 16 / static_cast<int>(sizeof(T));      // slots per chunk
 };
 
 template <typename T>
@@ -57,22 +68,21 @@ struct MergeArgs {
 
 // ---- readers of the current (old) table -------------------------------------
 template <typename T>
-struct OldLds {  // slots [base, base + len) staged in LDS; bits relative to base
+struct OldLds {  // whole blocks staged from slot `base` (a multiple of 64); hi = last slot
   const T *s;
-  const uint64_t *b;
-  int64_t base, len;
+  const uint64_t *b;  // run-end words, bits outside the region's span cleared
+  int64_t base, hi;
   __device__ uint64_t slot(int64_t j) const { return s[j - base]; }
   __device__ int64_t next_end(int64_t from) const {
-    int64_t t = from - base;
-    if (t >= len) return base + len - 1;
-    int w = static_cast<int>(t >> 6);
-    const int nw = static_cast<int>((len + 63) >> 6);
+    const int64_t t = from - base;
+    int64_t w = t >> 6;
+    const int64_t wl = (hi - base) >> 6;
     uint64_t m = b[w] & (~0ull << (t & 63));
     while (!m) {
-      if (++w >= nw) return base + len - 1;
+      if (++w > wl) return hi;
       m = b[w];
     }
-    return base + (static_cast<int64_t>(w) << 6) + ctz64(m);
+    return base + (w << 6) + ctz64(m);
   }
 };
 
@@ -92,6 +102,19 @@ struct OldGlb {
   }
 };
 
+// ---- the region's new <fingerprint, count> entries --------------------------
+struct NewLds {
+  const uint64_t *fp;
+  const uint32_t *cnt;
+  __device__ uint64_t f(uint64_t i) const { return fp[i]; }
+  __device__ uint64_t c(uint64_t i) const { return cnt[i]; }
+};
+struct NewGlb {
+  const uint64_t *fp, *cnt;
+  __device__ uint64_t f(uint64_t i) const { return fp[i]; }
+  __device__ uint64_t c(uint64_t i) const { return cnt[i]; }
+};
+
 // ---- writers of the new table -------------------------------------------
 // emit(j, v) writes slot j (positions strictly increasing per lane), set_end()
 // marks the last written slot as a run end, flush() ends the lane's output.
@@ -101,14 +124,16 @@ template <typename T>
 struct OutLds {
   T *s;
   uint64_t *b;
-  int64_t base, hi;  // positions [base, hi]
+  int64_t base, hi;  // base is a multiple of 64; positions [.., hi]
   int64_t cw;
   uint64_t acc, accm;
   __device__ void init(T *s_, uint64_t *b_, int64_t base_, int64_t hi_) {
     s = s_; b = b_; base = base_; hi = hi_; cw = -1; acc = 0; accm = 0;
   }
   __device__ void flush() {
-    if (accm) {
+    if (accm == ~0ull) {
+      b[cw] = acc;
+    } else if (accm) {
       atomicAnd(reinterpret_cast<ull *>(&b[cw]), static_cast<ull>(~accm));
       atomicOr(reinterpret_cast<ull *>(&b[cw]), static_cast<ull>(acc));
     }
@@ -120,7 +145,7 @@ struct OutLds {
     s[t] = static_cast<T>(v);
     const int64_t w = t >> 6;
     if (w != cw) {
-      flush();
+      if (cw >= 0) flush();
       cw = w;
     }
     accm |= 1ull << (t & 63);
@@ -129,6 +154,29 @@ struct OutLds {
     if (j > hi) return;
     acc |= 1ull << ((j - base) & 63);
   }
+  // account for slot j without storing it (its value is written later)
+  __device__ void mark(int64_t j) {
+    if (j > hi) return;
+    const int64_t t = j - base;
+    const int64_t w = t >> 6;
+    if (w != cw) {
+      if (cw >= 0) flush();
+      cw = w;
+    }
+    accm |= 1ull << (t & 63);
+  }
+};
+
+// slot values only (run-end bits of these slots are set by the owning lane)
+template <typename T>
+struct SlotsLds {
+  T *s;
+  int64_t base, hi;
+  __device__ void emit(int64_t j, uint64_t v) {
+    if (j <= hi) s[j - base] = static_cast<T>(v);
+  }
+  __device__ void set_end(int64_t) {}
+  __device__ void flush() {}
 };
 
 template <typename T>
@@ -154,7 +202,7 @@ struct OutGlb {
     blk[j >> 6].s[j & 63] = static_cast<T>(v);
     const int64_t w = j >> 6;
     if (w != cw) {
-      flush();
+      if (cw >= 0) flush();
       cw = w;
     }
     accm |= 1ull << (j & 63);
@@ -173,7 +221,10 @@ struct NoOut {
 
 struct Acc {
   Fn F;
-  uint64_t entries, total, shortfall, used;
+  uint64_t used;       // slots of all runs
+  uint64_t dent;       // change of the number of distinct fingerprints (mod 2^64)
+  uint64_t dtot;       // change of the total count (mod 2^64)
+  uint64_t shortfall;  // delete: instances not present
   uint32_t ovf;
 };
 
@@ -216,23 +267,89 @@ __device__ int64_t carry_old(const Block<T> *b, const uint32_t *off, int64_t i, 
   }
 }
 
+// Merge of one quotient's old run [op, oe] with its new entries [ni, nj):
+// pass 1 returns the new run length, pass 2 writes the run from `pos`.
+template <bool EMIT, class Old, class New, class Out>
+__device__ __forceinline__ int64_t merge_run(const Old &old, int64_t op, int64_t oe, const New &nw,
+                                             uint64_t ni, uint64_t nj, uint32_t r, int del,
+                                             Out &out, int64_t pos, Acc &acc) {
+  const uint64_t rmask = (1ull << r) - 1ull;
+  int64_t L = 0;
+  uint64_t orem = 0, ocnt = 0;
+  bool ohave = false;
+  if (op <= oe) {
+    op = dec_entry(old, op, oe, r, orem, ocnt);
+    ohave = true;
+  }
+  uint64_t k = ni;
+  while (ohave || k < nj) {
+    const uint64_t nrem = k < nj ? (nw.f(k) & rmask) : ~0ull;
+    uint64_t rem, c;
+    if (ohave && (k >= nj || orem < nrem)) {
+      rem = orem;
+      c = ocnt;
+      if (op <= oe) op = dec_entry(old, op, oe, r, orem, ocnt); else ohave = false;
+    } else if (!ohave || nrem < orem) {
+      rem = nrem;
+      const uint64_t cn = nw.c(k++);
+      if (del) {
+        if (!EMIT) acc.shortfall += cn;
+        c = 0;
+      } else {
+        c = cn;
+        if (!EMIT) {
+          acc.dent += 1;
+          acc.dtot += cn;
+        }
+      }
+    } else {
+      rem = orem;
+      const uint64_t cn = nw.c(k++);
+      if (del) {
+        const uint64_t t = min(ocnt, cn);
+        c = ocnt - t;
+        if (!EMIT) {
+          acc.shortfall += cn - t;
+          acc.dtot -= t;
+          if (c == 0) acc.dent -= 1;
+        }
+      } else {
+        c = ocnt + cn;
+        if (c < ocnt) {
+          if (!EMIT) acc.ovf = 1;
+          c = ~0ull;
+        }
+        if (!EMIT) acc.dtot += cn;
+      }
+      if (op <= oe) op = dec_entry(old, op, oe, r, orem, ocnt); else ohave = false;
+    }
+    if (c == 0) continue;
+    if (EMIT)
+      pos = enc_put(out, pos, rem, c, r);
+    else
+      L += enc_len(rem, c, r);
+  }
+  return EMIT ? pos : L;
+}
+
 // Walk one lane's chunk: quotients [x0, x1) (the same numbers as its slots
 // [s0, s1) in a quotient region; empty in the extra slots).  Pass 1 (EMIT =
-// false) composes the lane's run maps and counts; pass 2 writes the lane's
-// extent [max(carry + 1, s0), max(last end, s1 - 1)] -- runs and zero gaps --
-// plus the occupied bits and the offsets of the blocks that start in it.
-template <typename T, bool EMIT, class Old, class Out>
-__device__ void walk(const MergeArgs<T> &a, int64_t RS, const uint64_t *occ_l, int64_t x0,
-                     int64_t x1, int64_t s0, int64_t s1, int64_t ope, uint64_t ni, uint64_t nb,
-                     const Old &old, Out &out, int64_t carry, Acc &acc, uint64_t *nocc_l,
-                     uint32_t *noff) {
+// false) composes the lane's run maps; pass 2 writes the lane's extent
+// [max(carry + 1, s0), max(last end, s1 - 1)] -- runs and zero gaps -- plus
+// the occupied bits and the offsets of the blocks that start in it.
+template <typename T, bool EMIT, class Old, class New, class Out>
+__device__ __forceinline__ void walk(const MergeArgs<T> &a, int64_t RS, const uint64_t *occ_l,
+                                     int64_t x0, int64_t x1, int64_t s0, int64_t s1, int64_t ope,
+                                     uint64_t ni, uint64_t nb, const Old &old, const New &nw,
+                                     Out &out, int64_t carry, Acc &acc, uint64_t *nocc_l,
+                                     uint32_t *noff) {
   const uint32_t r = a.r;
-  const uint64_t rmask = (1ull << r) - 1ull;
   int64_t wpos = max(carry + 1, s0);
   int64_t next_bs = (s0 + 63) & ~static_cast<int64_t>(63);
   int64_t xo = x0 < x1 ? next_occ(occ_l, RS, x0, x1) : INF;
+  uint64_t nfp = ni < nb ? nw.f(ni) : 0;
   for (;;) {
-    const int64_t xn = ni < nb ? static_cast<int64_t>(a.ufp[ni] >> r) : INF;
+    const int64_t xn = ni < nb ? static_cast<int64_t>(nfp >> r) : INF;
     const int64_t x = min(xo, xn);
     if (x >= INF) break;
     if (EMIT) {
@@ -247,64 +364,19 @@ __device__ void walk(const MergeArgs<T> &a, int64_t RS, const uint64_t *occ_l, i
       xo = next_occ(occ_l, RS, x + 1, x1);
     }
     uint64_t nj = ni;
-    while (nj < nb && static_cast<int64_t>(a.ufp[nj] >> r) == x) ++nj;
-
-    int64_t start = 0, pos = 0;
+    while (nj < nb && static_cast<int64_t>(nfp >> r) == x) {
+      ++nj;
+      if (nj < nb) nfp = nw.f(nj);
+    }
     if (EMIT) {
-      start = max(x, carry + 1);
+      const int64_t start = max(x, carry + 1);
       for (; wpos < start; ++wpos) out.emit(wpos, 0);
-      pos = start;
-    }
-    int64_t L = 0;
-    uint64_t orem = 0, ocnt = 0;
-    bool ohave = false;
-    if (op <= oe) {
-      op = dec_entry(old, op, oe, r, orem, ocnt);
-      ohave = true;
-    }
-    uint64_t k = ni;
-    while (ohave || k < nj) {
-      const uint64_t nrem = k < nj ? (a.ufp[k] & rmask) : ~0ull;
-      uint64_t rem, c;
-      if (ohave && (k >= nj || orem < nrem)) {
-        rem = orem;
-        c = ocnt;
-        if (op <= oe) op = dec_entry(old, op, oe, r, orem, ocnt); else ohave = false;
-      } else if (!ohave || nrem < orem) {
-        rem = nrem;
-        const uint64_t cn = a.ucnt[k++];
-        if (a.del) {
-          if (!EMIT) acc.shortfall += cn;
-          c = 0;
-        } else {
-          c = cn;
-        }
+      int64_t pos = start;
+      if (ni == nj) {
+        for (int64_t j = op; j <= oe; ++j) out.emit(pos++, old.slot(j));
       } else {
-        rem = orem;
-        const uint64_t cn = a.ucnt[k++];
-        if (a.del) {
-          const uint64_t t = min(ocnt, cn);
-          if (!EMIT) acc.shortfall += cn - t;
-          c = ocnt - t;
-        } else {
-          c = ocnt + cn;
-          if (c < ocnt) {
-            if (!EMIT) acc.ovf = 1;
-            c = ~0ull;
-          }
-        }
-        if (op <= oe) op = dec_entry(old, op, oe, r, orem, ocnt); else ohave = false;
+        pos = merge_run<true>(old, op, oe, nw, ni, nj, r, a.del, out, pos, acc);
       }
-      if (c == 0) continue;
-      if (EMIT) {
-        pos = enc_put(out, pos, rem, c, r);
-      } else {
-        L += enc_len(rem, c, r);
-        acc.entries += 1;
-        acc.total += c;
-      }
-    }
-    if (EMIT) {
       if (pos > start) {
         out.set_end(pos - 1);
         carry = pos - 1;
@@ -316,9 +388,13 @@ __device__ void walk(const MergeArgs<T> &a, int64_t RS, const uint64_t *occ_l, i
         noff[x >> 6] = static_cast<uint32_t>(max(carry - x, static_cast<int64_t>(0)));
         next_bs += 64;
       }
-    } else if (L > 0) {
-      acc.F = fn_then(acc.F, Fn{x + L - 1, L});
-      acc.used += static_cast<uint64_t>(L);
+    } else {
+      const int64_t L = ni == nj ? oe - op + 1
+                                 : merge_run<false>(old, op, oe, nw, ni, nj, r, a.del, out, 0, acc);
+      if (L > 0) {
+        acc.F = fn_then(acc.F, Fn{x + L - 1, L});
+        acc.used += static_cast<uint64_t>(L);
+      }
     }
     ni = nj;
   }
@@ -328,6 +404,100 @@ __device__ void walk(const MergeArgs<T> &a, int64_t RS, const uint64_t *occ_l, i
     const int64_t ext_end = max(carry, s1 - 1);
     for (; wpos <= ext_end; ++wpos) out.emit(wpos, 0);
     out.flush();
+  }
+}
+
+// The per-lane walk of the staged path.  Runs that receive no new entry keep
+// their old length (read off the run-end bits); the lengths of the lane's
+// changed runs [c0, c1) were computed beforehand, one run per lane.  Pass 1
+// (EMIT = false) composes the lane's run maps; pass 2 copies unchanged runs to
+// their new place, reserves the changed runs' slots (cstart), zero-fills gaps
+// and writes run-end and occupied bits and the offsets of the blocks that
+// start in the lane's chunk.
+template <typename T, bool EMIT>
+__device__ __forceinline__ void walk_fast(int64_t RS, const uint64_t *occ_l, int64_t x0, int64_t x1,
+                                          int64_t s0, int64_t s1, int64_t ope, const OldLds<T> &old,
+                                          uint32_t c0, uint32_t c1, const uint16_t *cxr,
+                                          const uint32_t *cL, uint16_t *cstart, OutLds<T> &out,
+                                          int64_t carry, Fn &F, uint64_t &used, uint64_t *nocc_l,
+                                          uint32_t *noff) {
+  int64_t wpos = max(carry + 1, s0);
+  int64_t next_bs = (s0 + 63) & ~static_cast<int64_t>(63);
+  int64_t xo = x0 < x1 ? next_occ(occ_l, RS, x0, x1) : INF;
+  uint32_t c = c0;
+  int64_t xc = c < c1 ? RS + cxr[c] : INF;
+  for (;;) {
+    const int64_t x = min(xo, xc);
+    if (x >= INF) break;
+    if (EMIT) {
+      for (; next_bs < x; next_bs += 64)
+        noff[next_bs >> 6] = static_cast<uint32_t>(max(carry - next_bs, static_cast<int64_t>(0)));
+    }
+    int64_t op = 0, oe = -1;
+    if (xo == x) {
+      op = max(x, ope + 1);
+      oe = old.next_end(op);
+      ope = oe;
+      xo = next_occ(occ_l, RS, x + 1, x1);
+    }
+    const bool changed = xc == x;
+    const int64_t L = changed ? static_cast<int64_t>(cL[c]) : oe - op + 1;
+    if (EMIT) {
+      const int64_t start = max(x, carry + 1);
+      for (; wpos < start; ++wpos) out.emit(wpos, 0);
+      if (L > 0) {
+        if (changed) {
+          cstart[c] = static_cast<uint16_t>(start - out.base);
+          for (int64_t j = start; j < start + L; ++j) out.mark(j);
+        } else {
+          int64_t pos = start;
+          for (int64_t j = op; j <= oe; ++j) out.emit(pos++, old.slot(j));
+        }
+        out.set_end(start + L - 1);
+        carry = start + L - 1;
+        wpos = start + L;
+        const int64_t t = x - RS;
+        atomicOr(reinterpret_cast<ull *>(&nocc_l[t >> 6]), static_cast<ull>(1ull << (t & 63)));
+      }
+      if (x == next_bs) {
+        noff[x >> 6] = static_cast<uint32_t>(max(carry - x, static_cast<int64_t>(0)));
+        next_bs += 64;
+      }
+    } else if (L > 0) {
+      F = fn_then(F, Fn{x + L - 1, L});
+      used += static_cast<uint64_t>(L);
+    }
+    if (changed) {
+      ++c;
+      xc = c < c1 ? RS + cxr[c] : INF;
+    }
+  }
+  if (EMIT) {
+    for (; next_bs < s1; next_bs += 64)
+      noff[next_bs >> 6] = static_cast<uint32_t>(max(carry - next_bs, static_cast<int64_t>(0)));
+    const int64_t ext_end = max(carry, s1 - 1);
+    for (; wpos <= ext_end; ++wpos) out.emit(wpos, 0);
+    out.flush();
+  }
+}
+
+// the rare whole-region path: one lane, global memory in and out
+template <typename T, bool EMIT>
+__device__ __forceinline__ void walk_global(const MergeArgs<T> &a, int64_t RS, const uint64_t *occ_l,
+                                            int64_t x0, int64_t x1, int64_t s0, int64_t s1,
+                                            int64_t ope, uint64_t ni, uint64_t nb,
+                                            const Block<T> *ob, Block<T> *nbk, int64_t hi,
+                                            int64_t carry, Acc &acc, uint64_t *nocc_l,
+                                            uint32_t *noff) {
+  OldGlb<T> old{ob, a.nblocks};
+  NewGlb nw{a.ufp, a.ucnt};
+  if (EMIT) {
+    OutGlb<T> out;
+    out.init(nbk, hi);
+    walk<T, true>(a, RS, occ_l, x0, x1, s0, s1, ope, ni, nb, old, nw, out, carry, acc, nocc_l, noff);
+  } else {
+    NoOut out;
+    walk<T, false>(a, RS, occ_l, x0, x1, s0, s1, ope, ni, nb, old, nw, out, carry, acc, nocc_l, noff);
   }
 }
 
@@ -386,43 +556,76 @@ __device__ uint64_t block_sum_u64(uint64_t v, uint64_t *sh) {
   return t;
 }
 
-__device__ __forceinline__ uint64_t lower_bound_u64(const uint64_t *a, uint64_t lo, uint64_t hi,
-                                                    uint64_t key) {
-  while (lo < hi) {
-    const uint64_t mid = (lo + hi) >> 1;
-    if (a[mid] < key) lo = mid + 1; else hi = mid;
-  }
-  return lo;
-}
-
-// Carry-in of region R: compose the published maps of R-1, R-2, ... until a
-// region whose inclusive carry is already known.
-__device__ int64_t look_back(const uint64_t *tags, uint32_t nreg, uint32_t epoch, int64_t R) {
-  Fn acc = fn_id();
-  int64_t j = R - 1;
-  while (j >= 0) {
-    int64_t v, A, B;
-    if (tag_load(&tags[2ull * nreg + j], epoch, &v)) return fn_apply(acc, v);
-    if (tag_load(&tags[j], epoch, &A) && tag_load(&tags[static_cast<uint64_t>(nreg) + j], epoch, &B)) {
-      acc = fn_then(Fn{A, B}, acc);
-      --j;
-      continue;
+// Carry-in of region R (called by the 64 lanes of one wave): lane l looks at
+// region hi - l; the nearest region with a known inclusive carry ends the walk,
+// the aggregates of the regions in between are composed in order.  One memory
+// round trip covers 64 predecessors.
+__device__ int64_t look_back_wave(const uint64_t *tags, uint32_t nreg, uint32_t epoch, int64_t R) {
+  const int lane = threadIdx.x & 63;
+  Fn acc = fn_id();  // regions (hi, R-1], applied in order
+  int64_t hi = R - 1;
+  for (;;) {
+    const int64_t j = hi - lane;
+    int kind = 0;  // 0 not ready, 1 aggregate, 2 inclusive, 3 before region 0
+    int64_t v = -1, A = -1, B = 0;
+    if (j < 0) {
+      kind = 3;
+    } else {
+      int64_t tv = 0, tA = 0, tB = 0;
+      const bool hv = tag_load(&tags[2ull * nreg + j], epoch, &tv);
+      const bool hA = tag_load(&tags[j], epoch, &tA);
+      const bool hB = tag_load(&tags[static_cast<uint64_t>(nreg) + j], epoch, &tB);
+      if (hv) {
+        kind = 2;
+        v = tv;
+      } else if (hA && hB) {
+        kind = 1;
+        A = tA;
+        B = tB;
+      }
     }
-    __builtin_amdgcn_s_sleep(2);
+    const uint64_t stop_m = __ballot(kind >= 2);
+    const uint64_t miss_m = __ballot(kind == 0);
+    const int stop = stop_m ? ctz64(stop_m) : 64;
+    const int miss = miss_m ? ctz64(miss_m) : 64;
+    const int take = min(stop, miss);  // lanes [0, take) hold usable aggregates
+    for (int l = 0; l < take; ++l) {
+      Fn g;
+      g.A = __shfl(A, l);
+      g.B = __shfl(B, l);
+      acc = fn_then(g, acc);  // region hi - l is applied before the ones already in acc
+    }
+    if (stop < 64 && stop <= miss) {
+      const int64_t c = __shfl(v, stop);
+      return fn_apply(acc, c);
+    }
+    hi -= take;
+    if (take == 0) __builtin_amdgcn_s_sleep(2);
   }
-  return fn_apply(acc, -1);
 }
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_merge(MergeArgs<T> a) {
   using C = Cfg<T>;
-  __shared__ T old_s[C::CAP];
+  __shared__ __align__(16) T old_s[C::CAP];
+  __shared__ __align__(16) T new_s[C::CAP];
   __shared__ uint64_t old_b[C::CAPW];
   __shared__ uint32_t old_wp[C::CAPW + 1];
-  __shared__ T new_s[C::CAP];
   __shared__ uint64_t new_b[C::CAPW];
   __shared__ uint64_t occ_l[C::OW];
+  __shared__ uint32_t occ_wp[C::OW + 1];
   __shared__ uint64_t nocc_l[C::OW];
+  // the region's new entries, and its changed runs (one per distinct quotient)
+  __shared__ uint64_t nfp_l[C::NCAP];
+  __shared__ uint32_t ncnt_l[C::NCAP];
+  __shared__ uint16_t chg_of[C::NCAP];  // changed run of each entry
+  __shared__ uint16_t cxr[C::NCAP];     // its quotient - RS
+  __shared__ uint16_t chead[C::NCAP];   // its first entry
+  __shared__ uint16_t cop[C::NCAP];     // its old run, relative to the staged base
+  __shared__ uint16_t coe[C::NCAP];
+  __shared__ uint32_t cL[C::NCAP];      // its new length
+  __shared__ uint16_t cstart[C::NCAP];  // its new first slot, relative to the output base
+  __shared__ uint32_t lane_start[NT + 1];
   __shared__ int64_t sh_i[8];
   __shared__ Fn sh_fn[NT / 64];
   __shared__ uint32_t sh_u[NT / 64];
@@ -434,14 +637,18 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs<T> a) {
   const int64_t R = sh_i[0];
   const int64_t S = 1ll << a.rlog;
   const int64_t RS = R << a.rlog;
+  // (selects, not a dynamic index into the argument struct, which would put
+  // the struct in scratch memory)
   const int cur = static_cast<int>(a.state[ST_CUR] & 1ull);
-  const Block<T> *ob = a.blk[cur];
-  Block<T> *nbk = a.blk[cur ^ 1];
-  const uint32_t *ooff = a.off[cur];
-  uint32_t *noff = a.off[cur ^ 1];
+  const Block<T> *ob = cur ? a.blk[1] : a.blk[0];
+  Block<T> *nbk = cur ? a.blk[0] : a.blk[1];
+  const uint32_t *ooff = cur ? a.off[1] : a.off[0];
+  uint32_t *noff = cur ? a.off[0] : a.off[1];
   const bool qreg = RS < a.N;
   const int64_t send = min(RS + S, a.P);
   const int nw_reg = static_cast<int>((send - RS + 63) >> 6);
+  const uint64_t rb0 = a.rb[R], rb1 = a.rb[R + 1];
+  const uint64_t ne = rb1 - rb0;
 
   for (int w = tid; w < nw_reg; w += NT) {
     occ_l[w] = qreg ? ob[(RS >> 6) + w].occ : 0ull;
@@ -451,42 +658,92 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs<T> a) {
     if (tid == 0) sh_i[1] = carry_old(ob, ooff, RS, a.N);
     if (tid == 64) sh_i[2] = carry_old(ob, ooff, RS + S, a.N);
   }
+  const bool new_lds = ne <= static_cast<uint64_t>(C::NCAP);
+  if (new_lds) {
+    for (uint64_t i = tid; i < ne; i += NT) {
+      nfp_l[i] = a.ufp[rb0 + i];
+      ncnt_l[i] = static_cast<uint32_t>(a.ucnt[rb0 + i]);
+    }
+  }
   __syncthreads();
   const int64_t lo_old = qreg ? sh_i[1] + 1 : RS;
   const int64_t hi_old = qreg ? sh_i[2] : RS - 1;
-  const int64_t len_old = max(hi_old - lo_old + 1, static_cast<int64_t>(0));
-  const bool par = len_old <= C::CAP;
-  const int nwo = static_cast<int>((len_old + 63) >> 6);
+  const bool has_old = hi_old >= lo_old;
+  const int64_t bb = has_old ? (lo_old >> 6) : (RS >> 6);
+  const int nblk = has_old ? static_cast<int>((hi_old >> 6) - bb + 1) : 0;
+  const bool par = new_lds && nblk <= C::CAPW;
+  const int64_t obase = bb << 6;
 
-  if (par) {
-    for (int64_t t = tid; t < len_old; t += NT) {
-      const int64_t j = lo_old + t;
-      old_s[t] = ob[j >> 6].s[j & 63];
+  if (par && nblk > 0) {
+    // 16-byte chunks of the staged blocks' slots, then their run-end words
+    for (int idx = tid; idx < nblk * C::CH; idx += NT) {
+      const int b = idx / C::CH, c = idx % C::CH;
+      const uint4 v = reinterpret_cast<const uint4 *>(ob[bb + b].s)[c];
+      reinterpret_cast<uint4 *>(old_s + b * 64)[c] = v;
     }
-    for (int w = tid; w < nwo; w += NT) {
-      const int64_t p = lo_old + 64ll * w;
-      const int64_t gw = p >> 6;
-      const int shf = static_cast<int>(p & 63);
-      uint64_t v = ob[gw].rend >> shf;
-      if (shf && gw + 1 < a.nblocks) v |= ob[gw + 1].rend << (64 - shf);
-      const int64_t left = len_old - 64ll * w;
-      if (left < 64) v &= (1ull << left) - 1ull;
+    for (int w = tid; w < nblk; w += NT) {
+      uint64_t v = ob[bb + w].rend;
+      if (w == 0) v &= ~0ull << (lo_old & 63);
+      if (w == nblk - 1) v &= ~0ull >> (63 - (hi_old & 63));
       old_b[w] = v;
     }
   }
+  // lane ranges of the new entries; changed runs = groups of equal quotient
+  const int64_t QT = max(S >> 8, static_cast<int64_t>(1));
+  const int qshift = __builtin_ctzll(static_cast<uint64_t>(QT));
+  if (par) {
+    lane_start[tid] = static_cast<uint32_t>(ne);
+    if (tid == 0) lane_start[NT] = static_cast<uint32_t>(ne);
+  }
   __syncthreads();
-  // prefix of run-end counts per staged word (for the lanes' select)
+  uint32_t nchg = 0;
+  if (par) {
+    for (uint64_t e = tid; e < ne; e += NT) {
+      const int le = static_cast<int>((static_cast<int64_t>(nfp_l[e] >> a.r) - RS) >> qshift);
+      const int lp = e == 0 ? -1 : static_cast<int>((static_cast<int64_t>(nfp_l[e - 1] >> a.r) - RS) >> qshift);
+      for (int l = lp + 1; l <= le; ++l) lane_start[l] = static_cast<uint32_t>(e);
+    }
+  }
+  {
+    // heads of quotient groups: entries [2 tid, 2 tid + 2) per lane (ne <= 512
+    // here; more entries take the global path)
+    uint32_t h0 = 0, h1 = 0;
+    const uint64_t e0 = 2ull * tid, e1 = e0 + 1;
+    if (par && e0 < ne) h0 = e0 == 0 || (nfp_l[e0] >> a.r) != (nfp_l[e0 - 1] >> a.r);
+    if (par && e1 < ne) h1 = (nfp_l[e1] >> a.r) != (nfp_l[e0] >> a.r);
+    uint32_t tot;
+    const uint32_t ex = block_exscan_u32(h0 + h1, sh_u, &tot);
+    nchg = tot;
+    if (par && e0 < ne) {
+      chg_of[e0] = static_cast<uint16_t>(ex + h0 - 1);
+      if (h0) {
+        cxr[ex] = static_cast<uint16_t>((nfp_l[e0] >> a.r) - RS);
+        chead[ex] = static_cast<uint16_t>(e0);
+      }
+    }
+    if (par && e1 < ne) {
+      chg_of[e1] = static_cast<uint16_t>(ex + h0 + h1 - 1);
+      if (h1) {
+        cxr[ex + h0] = static_cast<uint16_t>((nfp_l[e1] >> a.r) - RS);
+        chead[ex + h0] = static_cast<uint16_t>(e1);
+      }
+    }
+  }
+  // prefix counts of run ends per staged word and of occupied quotients per
+  // region word (for rank / select)
   {
     uint32_t tot;
-    const uint32_t pc = (par && tid < nwo) ? static_cast<uint32_t>(popc64(old_b[tid])) : 0u;
+    const uint32_t pc = (par && tid < nblk) ? static_cast<uint32_t>(popc64(old_b[tid])) : 0u;
     const uint32_t ex = block_exscan_u32(pc, sh_u, &tot);
-    // only the staged (parallel) path has nwo <= CAPW words to index
-    if (par && tid < nwo) old_wp[tid] = ex;
-    if (par && tid == 0) old_wp[nwo] = tot;
+    if (par && tid < nblk) old_wp[tid] = ex;
+    if (par && tid == 0) old_wp[nblk] = tot;
+    const uint32_t po = (par && tid < nw_reg) ? static_cast<uint32_t>(popc64(occ_l[tid])) : 0u;
+    const uint32_t exo = block_exscan_u32(po, sh_u, &tot);
+    if (par && tid < nw_reg) occ_wp[tid] = exo;
+    if (par && tid == 0) occ_wp[nw_reg] = tot;
   }
 
-  // lane chunk: quotients / slots [cs0, cs1)
-  const int64_t QT = max(S >> 8, static_cast<int64_t>(1));
+  // lane chunk: quotients / slots [s0, s1)
   int64_t s0, s1;
   if (par) {
     s0 = min(RS + tid * QT, send);
@@ -496,121 +753,143 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs<T> a) {
     s1 = send;
   }
   const int64_t x0 = qreg ? s0 : 0, x1 = qreg ? s1 : 0;
-  // old runs before the chunk, and the end of the last of them
-  uint32_t pc_occ = 0;
-  if (qreg && x0 < x1) {
-    const int64_t t0 = x0 - RS;
-    const int nbits = static_cast<int>(x1 - x0);
-    uint64_t m = occ_l[t0 >> 6] >> (t0 & 63);
-    if (nbits < 64) m &= (1ull << nbits) - 1ull;
-    pc_occ = static_cast<uint32_t>(popc64(m));
-  }
-  uint32_t occ_tot;
-  const uint32_t k_t = block_exscan_u32(par ? pc_occ : 0u, sh_u, &occ_tot);
+  // end of the last old run before the lane's chunk
   int64_t ope = lo_old - 1;
-  if (par && k_t > 0 && x0 < x1) {
-    int lo = 0, hi = nwo - 1;  // word w with old_wp[w] <= k_t - 1 < old_wp[w + 1]
-    const uint32_t k = k_t - 1;
+  uint32_t c0 = 0, c1 = 0;
+  auto select_end = [&](uint32_t k) -> int64_t {  // position of the k-th (0-based) staged run end
+    int lo = 0, hi = nblk - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (old_wp[mid] <= k) lo = mid; else hi = mid - 1;
     }
-    ope = lo_old + (static_cast<int64_t>(lo) << 6) + select64(old_b[lo], static_cast<int>(k - old_wp[lo]));
+    return obase + (static_cast<int64_t>(lo) << 6) + select64(old_b[lo], static_cast<int>(k - old_wp[lo]));
+  };
+  if (par && qreg && x0 < x1) {
+    const int64_t t0 = x0 - RS;
+    const uint32_t k = occ_wp[t0 >> 6] + static_cast<uint32_t>(popc64(occ_l[t0 >> 6] & ((1ull << (t0 & 63)) - 1ull)));
+    if (k > 0) ope = select_end(k - 1);
+    const uint32_t ea = lane_start[tid], eb = lane_start[tid + 1];
+    c0 = ea < ne ? chg_of[ea] : nchg;
+    c1 = eb < ne ? chg_of[eb] : nchg;
   }
-  const uint64_t rb0 = a.rb[R], rb1 = a.rb[R + 1];
-  uint64_t na = rb0, nb = rb0;
-  if (qreg && x0 < x1) {
-    na = lower_bound_u64(a.ufp, rb0, rb1, static_cast<uint64_t>(x0) << a.r);
-    nb = lower_bound_u64(a.ufp, na, rb1, static_cast<uint64_t>(x1) << a.r);
-  }
+  __syncthreads();
 
-  // ---- pass 1: lengths -------------------------------------------------
   Acc acc{fn_id(), 0, 0, 0, 0, 0};
-  NoOut none;
   if (par) {
-    OldLds<T> old{old_s, old_b, lo_old, len_old};
-    walk<T, false>(a, RS, occ_l, x0, x1, s0, s1, ope, na, nb, old, none, 0, acc, nocc_l, noff);
+    // ---- pass 1a: new lengths of the changed runs, one run per lane --------
+    OldLds<T> old{old_s, old_b, obase, hi_old};
+    NewLds nw{nfp_l, ncnt_l};
+    NoOut none;
+    for (uint32_t c = tid; c < nchg; c += NT) {
+      const int64_t x = RS + cxr[c];
+      const uint64_t ni = chead[c], nj = c + 1 < nchg ? chead[c + 1] : ne;
+      const int64_t t = x - RS;
+      int64_t op = 0, oe = -1;
+      if ((occ_l[t >> 6] >> (t & 63)) & 1ull) {
+        const uint32_t k = occ_wp[t >> 6] + static_cast<uint32_t>(popc64(occ_l[t >> 6] & ((1ull << (t & 63)) - 1ull)));
+        oe = select_end(k);
+        op = max(x, (k > 0 ? select_end(k - 1) : lo_old - 1) + 1);
+      }
+      // staged positions are < CAP, so 0xFFFF marks "no old run"
+      cop[c] = oe >= op ? static_cast<uint16_t>(op - obase) : 0;
+      coe[c] = oe >= op ? static_cast<uint16_t>(oe - obase) : 0xFFFF;
+      cL[c] = static_cast<uint32_t>(merge_run<false>(old, op, oe, nw, ni, nj, a.r, a.del, none, 0, acc));
+    }
+    __syncthreads();
+    // ---- pass 1b: the lane's run maps -------------------------------------
+    OutLds<T> dummy_out;
+    dummy_out.init(new_s, new_b, 0, -1);
+    walk_fast<T, false>(RS, occ_l, x0, x1, s0, s1, ope, old, c0, c1, cxr, cL, cstart, dummy_out, 0,
+                        acc.F, acc.used, nocc_l, noff);
   } else if (tid == 0) {
-    OldGlb<T> old{ob, a.nblocks};
-    walk<T, false>(a, RS, occ_l, x0, x1, s0, s1, ope, na, nb, old, none, 0, acc, nocc_l, noff);
+    walk_global<T, false>(a, RS, occ_l, x0, x1, s0, s1, ope, rb0, rb1, ob, nbk, 0, 0, acc, nocc_l, noff);
   }
   Fn Ftot;
   const Fn Fex = block_exscan_fn(acc.F, sh_fn, &Ftot);
-  const uint64_t entries = block_sum_u64(acc.entries, sh_r);
-  const uint64_t total = block_sum_u64(acc.total, sh_r);
-  const uint64_t shortfall = block_sum_u64(acc.shortfall, sh_r);
   const uint64_t used = block_sum_u64(acc.used, sh_r);
+  const uint64_t dent = block_sum_u64(acc.dent, sh_r);
+  const uint64_t dtot = block_sum_u64(acc.dtot, sh_r);
+  const uint64_t shortfall = block_sum_u64(acc.shortfall, sh_r);
   const uint64_t ovf = block_sum_u64(acc.ovf, sh_r);
 
   if (tid == 0) {
     tag_store(&a.tags[R], a.epoch, Ftot.A);
     tag_store(&a.tags[static_cast<uint64_t>(a.nregions) + R], a.epoch, Ftot.B);
-    const int64_t c_in = look_back(a.tags, a.nregions, a.epoch, R);
-    const int64_t c_out = fn_apply(Ftot, c_in);
-    tag_store(&a.tags[2ull * a.nregions + R], a.epoch, c_out);
-    sh_i[3] = c_in;
-    sh_i[4] = c_out;
-    if (c_out >= a.P) atomic_or_u64(&a.state[ST_BATCH], BATCH_FULL);
-    if (ovf) atomic_or_u64(&a.state[ST_BATCH], BATCH_OVF);
-    if (used) atomic_add_u64(&a.state[ST_NUSED], used);
-    if (entries) atomic_add_u64(&a.state[ST_NDIST], entries);
-    if (total) atomic_add_u64(&a.state[ST_NTOTAL], total);
-    if (a.del && shortfall) atomic_add_u64(a.not_found, shortfall);
+  }
+  if (tid < 64) {
+    const int64_t c_in = look_back_wave(a.tags, a.nregions, a.epoch, R);
+    if (tid == 0) {
+      const int64_t c_out = fn_apply(Ftot, c_in);
+      tag_store(&a.tags[2ull * a.nregions + R], a.epoch, c_out);
+      sh_i[3] = c_in;
+      sh_i[4] = c_out;
+      if (c_out >= a.P) atomic_or_u64(&a.state[ST_BATCH], BATCH_FULL);
+      if (ovf) atomic_or_u64(&a.state[ST_BATCH], BATCH_OVF);
+      if (used) atomic_add_u64(&a.state[ST_NUSED], used);
+      if (dent) atomic_add_u64(&a.state[ST_NDIST], dent);
+      if (dtot) atomic_add_u64(&a.state[ST_NTOTAL], dtot);
+      if (a.del && shortfall) atomic_add_u64(a.not_found, shortfall);
+    }
   }
   __syncthreads();
 
-  // ---- pass 2: write the region's extent into the other copy ------------
+  // ---- pass 2: write the region's extent into the other copy --------------
   const int64_t c_in = sh_i[3], c_out = sh_i[4];
   const int64_t ext_lo = max(c_in + 1, RS);
   const int64_t ext_hi = min(max(c_out, send - 1), a.P - 1);
-  const int64_t ext_len = max(ext_hi - ext_lo + 1, static_cast<int64_t>(0));
-  const bool lds_out = ext_len <= C::CAP;
+  const int64_t xbase = (ext_lo >> 6) << 6;
+  const int nxb = ext_hi >= ext_lo ? static_cast<int>((ext_hi >> 6) - (ext_lo >> 6) + 1) : 0;
+  const bool lds_out = par && nxb <= C::CAPW;
   const int64_t c_t = fn_apply(Fex, c_in);
-  Acc dummy{fn_id(), 0, 0, 0, 0, 0};
-  if (par || tid == 0) {
-    if (lds_out) {
-      OutLds<T> out;
-      out.init(new_s, new_b, ext_lo, ext_hi);
-      if (par) {
-        OldLds<T> old{old_s, old_b, lo_old, len_old};
-        walk<T, true>(a, RS, occ_l, x0, x1, s0, s1, ope, na, nb, old, out, c_t, dummy, nocc_l, noff);
-      } else {
-        OldGlb<T> old{ob, a.nblocks};
-        walk<T, true>(a, RS, occ_l, x0, x1, s0, s1, ope, na, nb, old, out, c_t, dummy, nocc_l, noff);
-      }
-    } else {
-      OutGlb<T> out;
-      out.init(nbk, ext_hi);
-      if (par) {
-        OldLds<T> old{old_s, old_b, lo_old, len_old};
-        walk<T, true>(a, RS, occ_l, x0, x1, s0, s1, ope, na, nb, old, out, c_t, dummy, nocc_l, noff);
-      } else {
-        OldGlb<T> old{ob, a.nblocks};
-        walk<T, true>(a, RS, occ_l, x0, x1, s0, s1, ope, na, nb, old, out, c_t, dummy, nocc_l, noff);
-      }
+  if (lds_out) {
+    // 2a: unchanged runs, gaps, bits, offsets; reserve the changed runs
+    OldLds<T> old{old_s, old_b, obase, hi_old};
+    OutLds<T> out;
+    out.init(new_s, new_b, xbase, ext_hi);
+    Fn Fd = fn_id();
+    uint64_t ud = 0;
+    walk_fast<T, true>(RS, occ_l, x0, x1, s0, s1, ope, old, c0, c1, cxr, cL, cstart, out, c_t, Fd, ud,
+                       nocc_l, noff);
+    __syncthreads();
+    // 2b: the changed runs' slots, one run per lane
+    NewLds nw{nfp_l, ncnt_l};
+    SlotsLds<T> so{new_s, xbase, ext_hi};
+    Acc dummy{fn_id(), 0, 0, 0, 0, 0};
+    for (uint32_t c = tid; c < nchg; c += NT) {
+      if (cL[c] == 0) continue;
+      const uint64_t ni = chead[c], nj = c + 1 < nchg ? chead[c + 1] : ne;
+      const int64_t op = coe[c] == 0xFFFF ? 0 : obase + cop[c];
+      const int64_t oe = coe[c] == 0xFFFF ? -1 : obase + coe[c];
+      merge_run<true>(old, op, oe, nw, ni, nj, a.r, a.del, so, xbase + cstart[c], dummy);
     }
+  } else if (tid == 0) {
+    // one lane redoes the whole region from global memory
+    Acc dummy{fn_id(), 0, 0, 0, 0, 0};
+    walk_global<T, true>(a, RS, occ_l, qreg ? RS : 0, qreg ? send : 0, RS, send, lo_old - 1, rb0, rb1,
+                         ob, nbk, ext_hi, c_in, dummy, nocc_l, noff);
   }
   __syncthreads();
 
-  // copy-out of the LDS extent: slots, then run-end words (masked at the ends)
-  if (lds_out && ext_len > 0) {
-    for (int64_t t = tid; t < ext_len; t += NT) {
-      const int64_t j = ext_lo + t;
-      nbk[j >> 6].s[j & 63] = new_s[t];
+  if (lds_out && nxb > 0) {
+    // slots: whole 16-byte chunks inside the extent, single slots at its ends
+    for (int idx = tid; idx < nxb * C::CH; idx += NT) {
+      const int b = idx / C::CH, c = idx % C::CH;
+      const int64_t p0 = xbase + b * 64 + c * C::PER;
+      const int64_t p1 = p0 + C::PER - 1;
+      T *dst = nbk[(xbase >> 6) + b].s + c * C::PER;
+      const T *src = new_s + b * 64 + c * C::PER;
+      if (p0 >= ext_lo && p1 <= ext_hi) {
+        *reinterpret_cast<uint4 *>(dst) = *reinterpret_cast<const uint4 *>(src);
+      } else {
+        for (int k = 0; k < C::PER; ++k)
+          if (p0 + k >= ext_lo && p0 + k <= ext_hi) dst[k] = src[k];
+      }
     }
-    const int64_t w0 = ext_lo >> 6, w1 = ext_hi >> 6;
-    for (int64_t w = w0 + tid; w <= w1; w += NT) {
+    for (int b = tid; b < nxb; b += NT) {
+      const int64_t w = (xbase >> 6) + b;
       const int64_t plo = max(w << 6, ext_lo), phi = min((w << 6) + 63, ext_hi);
-      const int n = static_cast<int>(phi - plo + 1);
-      const int64_t t = plo - ext_lo;
-      const int shf = static_cast<int>(t & 63);
-      uint64_t v = new_b[t >> 6] >> shf;
-      if (shf && n > 64 - shf) v |= new_b[(t >> 6) + 1] << (64 - shf);
-      const uint64_t lowm = n == 64 ? ~0ull : ((1ull << n) - 1ull);
-      v &= lowm;
-      const int pos = static_cast<int>(plo & 63);
-      const uint64_t mask = lowm << pos;
-      v <<= pos;
+      const uint64_t mask = (~0ull >> (63 - (phi & 63))) & (~0ull << (plo & 63));
+      const uint64_t v = new_b[b] & mask;
       if (mask == ~0ull) {
         nbk[w].rend = v;
       } else {
@@ -630,8 +909,8 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs<T> a) {
       const uint64_t st = __hip_atomic_load(&a.state[ST_BATCH], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (st == 0) {
         a.state[ST_USED] = __hip_atomic_load(&a.state[ST_NUSED], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        a.state[ST_DIST] = __hip_atomic_load(&a.state[ST_NDIST], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        a.state[ST_TOTAL] = __hip_atomic_load(&a.state[ST_NTOTAL], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        a.state[ST_DIST] += __hip_atomic_load(&a.state[ST_NDIST], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        a.state[ST_TOTAL] += __hip_atomic_load(&a.state[ST_NTOTAL], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         a.state[ST_CUR] = static_cast<uint64_t>(cur ^ 1);
       } else {
         const int64_t code = (st & BATCH_FULL) ? -2 : -5;
@@ -678,6 +957,6 @@ hipError_t launch_merge(qf_filter *f, const uint64_t *ufp, const uint64_t *ucnt,
   return launch_merge_t<uint16_t>(f, ufp, ucnt, del, not_found, s);
 }
 
-int max_region_log2(uint32_t r) { return r == 8 ? 13 : 12; }
+int max_region_log2(uint32_t r) { return r == 8 ? Cfg<uint8_t>::SMAXLOG : Cfg<uint16_t>::SMAXLOG; }
 
 }  // namespace qf

@@ -60,8 +60,42 @@ __global__ __launch_bounds__(NT) void k_rs_hist(const uint64_t *__restrict__ in,
   }
 }
 
-// exclusive scan of a[0..n) in place by one work-group of 1024 threads;
-// the total goes to *total if it is not null
+// Work-group d turns the G group counts of digit d into exclusive prefixes
+// and writes the digit's total to dtot[d].
+__global__ __launch_bounds__(NT) void k_rs_offsets(uint32_t *__restrict__ hist, uint32_t G,
+                                                   uint32_t *__restrict__ dtot) {
+  __shared__ uint32_t sh[NWAVE];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const uint32_t d = blockIdx.x;
+  uint32_t *row = hist + static_cast<uint64_t>(d) * G;
+  const uint32_t per = (G + NT - 1) / NT;
+  const uint32_t lo = min(G, tid * per), hi = min(G, lo + per);
+  uint32_t loc = 0;
+  for (uint32_t i = lo; i < hi; ++i) loc += row[i];
+  uint32_t inc = loc;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(inc, o);
+    if (lane >= o) inc += t;
+  }
+  if (lane == 63) sh[wv] = inc;
+  __syncthreads();
+  uint32_t run = inc - loc;
+  for (int w = 0; w < wv; ++w) run += sh[w];
+  for (uint32_t i = lo; i < hi; ++i) {
+    const uint32_t c = row[i];
+    row[i] = run;
+    run += c;
+  }
+  if (tid == NT - 1) {
+    uint32_t t = 0;
+    for (int w = 0; w < NWAVE; ++w) t += sh[w];
+    dtot[d] = t;
+  }
+}
+
+// exclusive scan of a[0..n) in place by one work-group of 1024 threads (used
+// for the G tile counts of the duplicate reduction); the total goes to
+// *total if it is not null
 __global__ __launch_bounds__(1024) void k_scan_u32(uint32_t *a, uint32_t n, uint64_t *total) {
   __shared__ uint32_t part[1024];
   const int tid = threadIdx.x;
@@ -90,14 +124,27 @@ __global__ __launch_bounds__(1024) void k_scan_u32(uint32_t *a, uint32_t n, uint
 __global__ __launch_bounds__(NT) void k_rs_scatter(const uint64_t *__restrict__ in,
                                                    uint64_t *__restrict__ out, uint64_t n,
                                                    uint32_t G, uint32_t shift, uint32_t nbits,
-                                                   const uint32_t *__restrict__ hist) {
+                                                   const uint32_t *__restrict__ hist,
+                                                   const uint32_t *__restrict__ dtot) {
   __shared__ uint32_t base[256];
   __shared__ uint32_t wc[NWAVE][256];
-  const int tid = threadIdx.x, wv = tid >> 6;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const uint32_t g = blockIdx.x;
-  for (int d = tid; d < 256; d += NT) {
-    base[d] = hist[static_cast<uint64_t>(d) * G + g];
-    for (int w = 0; w < NWAVE; ++w) wc[w][d] = 0;
+  {
+    // keys with a smaller digit: exclusive scan of the 256 digit totals
+    const uint32_t v = dtot[tid];
+    uint32_t inc = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t t = __shfl_up(inc, o);
+      if (lane >= o) inc += t;
+    }
+    if (lane == 63) wc[0][wv] = inc;
+    __syncthreads();
+    uint32_t ex = inc - v;
+    for (int w = 0; w < wv; ++w) ex += wc[0][w];
+    __syncthreads();
+    base[tid] = ex + hist[static_cast<uint64_t>(tid) * G + g];
+    for (int w = 0; w < NWAVE; ++w) wc[w][tid] = 0;
   }
   __syncthreads();
   const uint64_t lo = chunk_lo(n, G, g), hi = chunk_lo(n, G, g + 1);
@@ -264,21 +311,25 @@ hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s) {
 hipError_t launch_sort(uint64_t *a, uint64_t *b, uint64_t n, uint32_t bits, uint32_t *hist,
                        uint64_t **result, hipStream_t s, Timer *t) {
   const uint32_t G = sort_groups(n);
+  const uint32_t npass = (bits + 7) / 8;
+  // digit totals live after the G * 256 histogram words
+  uint32_t *dtot = hist + 256ull * SORT_MAX_GROUPS;
   uint64_t *in = a, *out = b;
-  for (uint32_t shift = 0; shift < bits; shift += 8) {
+  for (uint32_t p = 0; p < npass; ++p) {
+    const uint32_t shift = 8 * p;
     const uint32_t nb = bits - shift < 8 ? bits - shift : 8;
     if (t) t->begin(QF_PROF_SORT_HIST, s);
     k_rs_hist<<<G, NT, 0, s>>>(in, n, G, shift, hist);
     if (t) t->end(QF_PROF_SORT_HIST, s);
     if (t) t->begin(QF_PROF_SORT_SCAN, s);
-    k_scan_u32<<<1, 1024, 0, s>>>(hist, 256u * G, nullptr);
+    k_rs_offsets<<<256, NT, 0, s>>>(hist, G, dtot);
     if (t) t->end(QF_PROF_SORT_SCAN, s);
     if (t) t->begin(QF_PROF_SORT_SCATTER, s);
-    k_rs_scatter<<<G, NT, 0, s>>>(in, out, n, G, shift, nb, hist);
+    k_rs_scatter<<<G, NT, 0, s>>>(in, out, n, G, shift, nb, hist, dtot);
     if (t) t->end(QF_PROF_SORT_SCATTER, s);
-    uint64_t *t = in;
+    uint64_t *tmp = in;
     in = out;
-    out = t;
+    out = tmp;
   }
   *result = in;
   return hipGetLastError();

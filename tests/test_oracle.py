@@ -314,3 +314,44 @@ def test_inputs_are_deterministic_and_disjoint():
     # head frequency of a Zipf(1.1) stream: P(1) = 1 / H, H = sum k^-1.1
     H = sum(k ** -1.1 for k in range(1, 200000)) + (200000 ** -0.1) / 0.1
     assert abs((z == 1).mean() - 1 / H) < 0.02
+
+
+def test_block_counts_match_brute_force():
+    """changed_blocks / query_blocks (units of the algorithmic-bytes model)
+    against a per-block, per-key Python loop on small tables."""
+    q, r = 10, 8
+    keys = inputs.uniform_keys(61, 800)
+    more = inputs.uniform_keys(62, 60)
+    ms0 = brute.multiset(brute.fingerprints(keys, q, r))
+    ms1 = brute.merge_multisets(ms0, brute.multiset(brute.fingerprints(more, q, r)))
+    L0 = brute.layout(*ms0, q, r)
+    L1 = brute.layout(*ms1, q, r)
+    P = int(L0.header[4])
+    nb = P // 64
+    occ0, occ1 = brute.bits(L0.occ_words, 1 << q), brute.bits(L1.occ_words, 1 << q)
+    re0, re1 = brute.bits(L0.runend_words, P), brute.bits(L1.runend_words, P)
+    changed = 0
+    for b in range(nb):
+        sl = slice(64 * b, 64 * b + 64)
+        diff = (np.any(L0.slots[sl] != L1.slots[sl]) or np.any(re0[sl] != re1[sl])
+                or L0.offsets[b] != L1.offsets[b] or (64 * b < (1 << q) and np.any(occ0[sl] != occ1[sl])))
+        changed += bool(diff)
+    assert brute.changed_blocks(L0, L1) == changed
+    # query blocks: home block, plus the blocks of the run found by walking runs
+    probe = np.concatenate([keys[:100], inputs.absent_keys(63, 100)])
+    fps = brute.fingerprints(probe, q, r)
+    runs = {}
+    prev = -1
+    ends = iter(np.nonzero(re1)[0])
+    for x in np.nonzero(occ1)[0]:
+        e = int(next(ends))
+        runs[int(x)] = (max(int(x), prev + 1), e)
+        prev = e
+    touched = set()
+    for fp in fps:
+        x = int(fp) >> r
+        touched.add(x // 64)
+        if x in runs:
+            s, e = runs[x]
+            touched.update(range(s // 64, e // 64 + 1))
+    assert brute.query_blocks(L1, fps) == len(touched)
