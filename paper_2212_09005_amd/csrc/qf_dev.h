@@ -114,64 +114,78 @@ __device__ __forceinline__ bool tag_load(const uint64_t* p, uint32_t epoch, int6
 //   c >= 3, x = 0: [0, 0, 0, digits + 1, 0].
 // (Sec. 2 and Sec. 6.7 only say that counters are variable-size and embedded
 // in the slots; this is the library's reading, shared by the export format.)
-__device__ __forceinline__ uint32_t enc_len(uint64_t x, uint64_t c, uint32_t r) {
-  if (c <= 2) return static_cast<uint32_t>(c);
+// v / (2^r - 1) and the remainder, without a divide: the sum of v >> (r k),
+// k >= 1, never exceeds the quotient and misses it by at most 64 / r + 1.
+__device__ __forceinline__ uint64_t div_base(uint64_t v, uint32_t r, uint64_t *rem) {
   const uint64_t base = (1ull << r) - 1;
-  const uint64_t v = c - 3;
+  uint64_t q = 0;
+  for (uint32_t s = r; s < 64; s += r) q += v >> s;
+  uint64_t m = v - q * base;
+  while (m >= base) {
+    m -= base;
+    ++q;
+  }
+  *rem = m;
+  return q;
+}
+
+// digits of v in base 2^r - 1 (at least one) and the most significant one
+__device__ __forceinline__ uint32_t base_digits(uint64_t v, uint32_t r, uint64_t *msd) {
+  const uint64_t base = (1ull << r) - 1;
   uint32_t nd = 1;
-  uint64_t pw = 1;
-  while (v / pw >= base) {
-    pw *= base;
+  while (v >= base) {
+    uint64_t d;
+    v = div_base(v, r, &d);
     ++nd;
   }
-  if (x > 0) return 2 + nd + ((v / pw) >= x ? 1u : 0u);
+  *msd = v;
+  return nd;
+}
+
+__device__ __forceinline__ uint32_t enc_len(uint64_t x, uint64_t c, uint32_t r) {
+  if (c <= 2) return static_cast<uint32_t>(c);
+  uint64_t msd;
+  const uint32_t nd = base_digits(c - 3, r, &msd);
+  if (x > 0) return 2 + nd + (msd >= x ? 1u : 0u);
   return 4 + nd;
 }
 
-template <class Out>
-__device__ __forceinline__ int64_t enc_put(Out& out, int64_t pos, uint64_t x, uint64_t c,
-                                           uint32_t r) {
+// Writes the entry's slots at [pos, pos + enc_len); digits are produced least
+// significant first and written back to front.
+template <class Out, typename P>
+__device__ __forceinline__ P enc_put(Out &out, P pos, uint64_t x, uint64_t c, uint32_t r) {
   if (c <= 2) {
     out.emit(pos++, x);
     if (c == 2) out.emit(pos++, x);
     return pos;
   }
-  const uint64_t base = (1ull << r) - 1;
-  uint64_t v = c - 3;
-  uint64_t pw = 1;
-  while (v / pw >= base) pw *= base;
+  uint64_t msd;
+  const uint32_t nd = base_digits(c - 3, r, &msd);
+  P p0;  // first digit slot
   if (x > 0) {
-    out.emit(pos++, x);
-    if (v / pw >= x) out.emit(pos++, 0);
-    for (;;) {
-      const uint64_t d = v / pw;
-      v -= d * pw;
-      out.emit(pos++, d < x ? d : d + 1);
-      if (pw == 1) break;
-      pw /= base;
-    }
-    out.emit(pos++, x);
+    out.emit(pos, x);
+    p0 = pos + 1;
+    if (msd >= x) out.emit(p0++, 0);
   } else {
-    out.emit(pos++, 0);
-    out.emit(pos++, 0);
-    out.emit(pos++, 0);
-    for (;;) {
-      const uint64_t d = v / pw;
-      v -= d * pw;
-      out.emit(pos++, d + 1);
-      if (pw == 1) break;
-      pw /= base;
-    }
-    out.emit(pos++, 0);
+    out.emit(pos, 0);
+    out.emit(pos + 1, 0);
+    out.emit(pos + 2, 0);
+    p0 = pos + 3;
   }
-  return pos;
+  uint64_t v = c - 3;
+  for (uint32_t k = 0; k < nd; ++k) {
+    uint64_t d;
+    v = div_base(v, r, &d);
+    out.emit(p0 + static_cast<P>(nd - 1 - k), x > 0 ? (d < x ? d : d + 1) : d + 1);
+  }
+  out.emit(p0 + static_cast<P>(nd), x);
+  return p0 + static_cast<P>(nd) + 1;
 }
 
 // Decode the entry that starts at slot p of a run ending at slot e; returns the
 // slot after it.  `Old` provides slot(j).
-template <class Old>
-__device__ __forceinline__ int64_t dec_entry(const Old& o, int64_t p, int64_t e, uint32_t r,
-                                             uint64_t& x, uint64_t& c) {
+template <class Old, typename P>
+__device__ __forceinline__ P dec_entry(const Old& o, P p, P e, uint32_t r, uint64_t& x, uint64_t& c) {
   const uint64_t base = (1ull << r) - 1;
   x = o.slot(p);
   if (x > 0) {
@@ -180,7 +194,7 @@ __device__ __forceinline__ int64_t dec_entry(const Old& o, int64_t p, int64_t e,
     if (s1 > x) { c = 1; return p + 1; }
     if (s1 == x) { c = 2; return p + 2; }
     uint64_t v = 0;
-    int64_t q = p + 1;
+    P q = p + 1;
     for (; q <= e; ++q) {
       const uint64_t s = o.slot(q);
       if (s == x) break;
@@ -192,7 +206,7 @@ __device__ __forceinline__ int64_t dec_entry(const Old& o, int64_t p, int64_t e,
   if (p == e || o.slot(p + 1) != 0) { c = 1; return p + 1; }
   if (p + 1 == e || o.slot(p + 2) != 0) { c = 2; return p + 2; }
   uint64_t v = 0;
-  int64_t q = p + 3;
+  P q = p + 3;
   for (; q <= e; ++q) {
     const uint64_t s = o.slot(q);
     if (s == 0) break;

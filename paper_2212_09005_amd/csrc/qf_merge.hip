@@ -269,19 +269,18 @@ __device__ int64_t carry_old(const Block<T> *b, const uint32_t *off, int64_t i, 
 
 // Merge of one quotient's old run [op, oe] with its new entries [ni, nj):
 // pass 1 returns the new run length, pass 2 writes the run from `pos`.
-template <bool EMIT, class Old, class New, class Out>
-__device__ __forceinline__ int64_t merge_run(const Old &old, int64_t op, int64_t oe, const New &nw,
-                                             uint64_t ni, uint64_t nj, uint32_t r, int del,
-                                             Out &out, int64_t pos, Acc &acc) {
+template <bool EMIT, class Old, class New, class Out, typename P>
+__device__ __forceinline__ P merge_run(const Old &old, P op, P oe, const New &nw, uint32_t ni,
+                                       uint32_t nj, uint32_t r, int del, Out &out, P pos, Acc &acc) {
   const uint64_t rmask = (1ull << r) - 1ull;
-  int64_t L = 0;
+  P L = 0;
   uint64_t orem = 0, ocnt = 0;
   bool ohave = false;
   if (op <= oe) {
     op = dec_entry(old, op, oe, r, orem, ocnt);
     ohave = true;
   }
-  uint64_t k = ni;
+  uint32_t k = ni;
   while (ohave || k < nj) {
     const uint64_t nrem = k < nj ? (nw.f(k) & rmask) : ~0ull;
     uint64_t rem, c;
@@ -327,7 +326,7 @@ __device__ __forceinline__ int64_t merge_run(const Old &old, int64_t op, int64_t
     if (EMIT)
       pos = enc_put(out, pos, rem, c, r);
     else
-      L += enc_len(rem, c, r);
+      L += static_cast<P>(enc_len(rem, c, r));
   }
   return EMIT ? pos : L;
 }
@@ -338,12 +337,11 @@ __device__ __forceinline__ int64_t merge_run(const Old &old, int64_t op, int64_t
 // [max(carry + 1, s0), max(last end, s1 - 1)] -- runs and zero gaps -- plus
 // the occupied bits and the offsets of the blocks that start in it.
 template <typename T, bool EMIT, class Old, class New, class Out>
-__device__ __forceinline__ void walk(const MergeArgs<T> &a, int64_t RS, const uint64_t *occ_l,
+__device__ __forceinline__ void walk(uint32_t r, int del, int64_t RS, const uint64_t *occ_l,
                                      int64_t x0, int64_t x1, int64_t s0, int64_t s1, int64_t ope,
                                      uint64_t ni, uint64_t nb, const Old &old, const New &nw,
                                      Out &out, int64_t carry, Acc &acc, uint64_t *nocc_l,
                                      uint32_t *noff) {
-  const uint32_t r = a.r;
   int64_t wpos = max(carry + 1, s0);
   int64_t next_bs = (s0 + 63) & ~static_cast<int64_t>(63);
   int64_t xo = x0 < x1 ? next_occ(occ_l, RS, x0, x1) : INF;
@@ -375,7 +373,7 @@ __device__ __forceinline__ void walk(const MergeArgs<T> &a, int64_t RS, const ui
       if (ni == nj) {
         for (int64_t j = op; j <= oe; ++j) out.emit(pos++, old.slot(j));
       } else {
-        pos = merge_run<true>(old, op, oe, nw, ni, nj, r, a.del, out, pos, acc);
+        pos = merge_run<true>(old, op, oe, nw, ni, nj, r, del, out, pos, acc);
       }
       if (pos > start) {
         out.set_end(pos - 1);
@@ -390,7 +388,7 @@ __device__ __forceinline__ void walk(const MergeArgs<T> &a, int64_t RS, const ui
       }
     } else {
       const int64_t L = ni == nj ? oe - op + 1
-                                 : merge_run<false>(old, op, oe, nw, ni, nj, r, a.del, out, 0, acc);
+                                 : merge_run<false>(old, op, oe, nw, ni, nj, r, del, out, int64_t{0}, acc);
       if (L > 0) {
         acc.F = fn_then(acc.F, Fn{x + L - 1, L});
         acc.used += static_cast<uint64_t>(L);
@@ -423,7 +421,33 @@ __device__ __forceinline__ void walk_fast(int64_t RS, const uint64_t *occ_l, int
                                           uint32_t *noff) {
   int64_t wpos = max(carry + 1, s0);
   int64_t next_bs = (s0 + 63) & ~static_cast<int64_t>(63);
-  int64_t xo = x0 < x1 ? next_occ(occ_l, RS, x0, x1) : INF;
+  // the chunk's occupied bits (a chunk never crosses a 64-bit word) and the
+  // run-end word being consumed stay in registers
+  uint64_t occ = 0;
+  if (x0 < x1) {
+    const int64_t t0 = x0 - RS;
+    occ = occ_l[t0 >> 6] >> (t0 & 63);
+    if (x1 - x0 < 64) occ &= (1ull << (x1 - x0)) - 1ull;
+  }
+  uint64_t nocc = 0;  // new occupied bits of the chunk
+  int64_t rw = -1;    // index of the run-end word held in rv
+  uint64_t rv = 0;
+  const int64_t rwl = (old.hi - old.base) >> 6;
+  auto next_end = [&](int64_t from) -> int64_t {
+    int64_t w = (from - old.base) >> 6;
+    if (w != rw) {
+      rw = w;
+      rv = old.b[w];
+    }
+    uint64_t m = rv & (~0ull << ((from - old.base) & 63));
+    while (!m) {
+      if (++rw > rwl) return old.hi;
+      rv = old.b[rw];
+      m = rv;
+    }
+    return old.base + (rw << 6) + ctz64(m);
+  };
+  int64_t xo = occ ? x0 + ctz64(occ) : INF;
   uint32_t c = c0;
   int64_t xc = c < c1 ? RS + cxr[c] : INF;
   for (;;) {
@@ -436,9 +460,10 @@ __device__ __forceinline__ void walk_fast(int64_t RS, const uint64_t *occ_l, int
     int64_t op = 0, oe = -1;
     if (xo == x) {
       op = max(x, ope + 1);
-      oe = old.next_end(op);
+      oe = next_end(op);
       ope = oe;
-      xo = next_occ(occ_l, RS, x + 1, x1);
+      occ &= occ - 1;
+      xo = occ ? x0 + ctz64(occ) : INF;
     }
     const bool changed = xc == x;
     const int64_t L = changed ? static_cast<int64_t>(cL[c]) : oe - op + 1;
@@ -456,8 +481,7 @@ __device__ __forceinline__ void walk_fast(int64_t RS, const uint64_t *occ_l, int
         out.set_end(start + L - 1);
         carry = start + L - 1;
         wpos = start + L;
-        const int64_t t = x - RS;
-        atomicOr(reinterpret_cast<ull *>(&nocc_l[t >> 6]), static_cast<ull>(1ull << (t & 63)));
+        nocc |= 1ull << (x - x0);
       }
       if (x == next_bs) {
         noff[x >> 6] = static_cast<uint32_t>(max(carry - x, static_cast<int64_t>(0)));
@@ -478,27 +502,34 @@ __device__ __forceinline__ void walk_fast(int64_t RS, const uint64_t *occ_l, int
     const int64_t ext_end = max(carry, s1 - 1);
     for (; wpos <= ext_end; ++wpos) out.emit(wpos, 0);
     out.flush();
+    if (nocc) {
+      const int64_t t0 = x0 - RS;
+      atomicOr(reinterpret_cast<ull *>(&nocc_l[t0 >> 6]), static_cast<ull>(nocc << (t0 & 63)));
+    }
   }
 }
 
-// the rare whole-region path: one lane, global memory in and out
+// the rare whole-region path: one lane, global memory in and out (inlined: an
+// out-of-line call would cost the whole kernel a call frame and registers)
 template <typename T, bool EMIT>
-__device__ __forceinline__ void walk_global(const MergeArgs<T> &a, int64_t RS, const uint64_t *occ_l,
-                                            int64_t x0, int64_t x1, int64_t s0, int64_t s1,
-                                            int64_t ope, uint64_t ni, uint64_t nb,
-                                            const Block<T> *ob, Block<T> *nbk, int64_t hi,
-                                            int64_t carry, Acc &acc, uint64_t *nocc_l,
-                                            uint32_t *noff) {
-  OldGlb<T> old{ob, a.nblocks};
-  NewGlb nw{a.ufp, a.ucnt};
+__device__ __forceinline__ void walk_global(const Block<T> *ob, Block<T> *nbk, int64_t nblocks,
+                                         const uint64_t *ufp, const uint64_t *ucnt, uint32_t r,
+                                         int del, int64_t RS, const uint64_t *occ_l, int64_t x0,
+                                         int64_t x1, int64_t s0, int64_t s1, int64_t ope,
+                                         uint64_t ni, uint64_t nb, int64_t hi, int64_t carry,
+                                         Acc *acc, uint64_t *nocc_l, uint32_t *noff) {
+  OldGlb<T> old{ob, nblocks};
+  NewGlb nw{ufp, ucnt};
+  Acc a = *acc;
   if (EMIT) {
     OutGlb<T> out;
     out.init(nbk, hi);
-    walk<T, true>(a, RS, occ_l, x0, x1, s0, s1, ope, ni, nb, old, nw, out, carry, acc, nocc_l, noff);
+    walk<T, true>(r, del, RS, occ_l, x0, x1, s0, s1, ope, ni, nb, old, nw, out, carry, a, nocc_l, noff);
   } else {
     NoOut out;
-    walk<T, false>(a, RS, occ_l, x0, x1, s0, s1, ope, ni, nb, old, nw, out, carry, acc, nocc_l, noff);
+    walk<T, false>(r, del, RS, occ_l, x0, x1, s0, s1, ope, ni, nb, old, nw, out, carry, a, nocc_l, noff);
   }
+  *acc = a;
 }
 
 // ---- block-wide helpers (256 lanes = 4 waves) ---------------------------
@@ -793,7 +824,7 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs<T> a) {
       // staged positions are < CAP, so 0xFFFF marks "no old run"
       cop[c] = oe >= op ? static_cast<uint16_t>(op - obase) : 0;
       coe[c] = oe >= op ? static_cast<uint16_t>(oe - obase) : 0xFFFF;
-      cL[c] = static_cast<uint32_t>(merge_run<false>(old, op, oe, nw, ni, nj, a.r, a.del, none, 0, acc));
+      cL[c] = static_cast<uint32_t>(merge_run<false>(old, op, oe, nw, ni, nj, a.r, a.del, none, int64_t{0}, acc));
     }
     __syncthreads();
     // ---- pass 1b: the lane's run maps -------------------------------------
@@ -802,7 +833,10 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs<T> a) {
     walk_fast<T, false>(RS, occ_l, x0, x1, s0, s1, ope, old, c0, c1, cxr, cL, cstart, dummy_out, 0,
                         acc.F, acc.used, nocc_l, noff);
   } else if (tid == 0) {
-    walk_global<T, false>(a, RS, occ_l, x0, x1, s0, s1, ope, rb0, rb1, ob, nbk, 0, 0, acc, nocc_l, noff);
+    Acc ag{fn_id(), 0, 0, 0, 0, 0};
+    walk_global<T, false>(ob, nbk, a.nblocks, a.ufp, a.ucnt, a.r, a.del, RS, occ_l, x0, x1, s0, s1, ope,
+                          rb0, rb1, 0, 0, &ag, nocc_l, noff);
+    acc = ag;
   }
   Fn Ftot;
   const Fn Fex = block_exscan_fn(acc.F, sh_fn, &Ftot);
@@ -860,13 +894,14 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs<T> a) {
       const uint64_t ni = chead[c], nj = c + 1 < nchg ? chead[c + 1] : ne;
       const int64_t op = coe[c] == 0xFFFF ? 0 : obase + cop[c];
       const int64_t oe = coe[c] == 0xFFFF ? -1 : obase + coe[c];
-      merge_run<true>(old, op, oe, nw, ni, nj, a.r, a.del, so, xbase + cstart[c], dummy);
+      merge_run<true>(old, op, oe, nw, ni, nj, a.r, a.del, so, static_cast<int64_t>(xbase + cstart[c]), dummy);
     }
   } else if (tid == 0) {
     // one lane redoes the whole region from global memory
     Acc dummy{fn_id(), 0, 0, 0, 0, 0};
-    walk_global<T, true>(a, RS, occ_l, qreg ? RS : 0, qreg ? send : 0, RS, send, lo_old - 1, rb0, rb1,
-                         ob, nbk, ext_hi, c_in, dummy, nocc_l, noff);
+    walk_global<T, true>(ob, nbk, a.nblocks, a.ufp, a.ucnt, a.r, a.del, RS, occ_l, qreg ? RS : 0,
+                         qreg ? send : 0, RS, send, lo_old - 1, rb0, rb1, ext_hi, c_in, &dummy, nocc_l,
+                         noff);
   }
   __syncthreads();
 

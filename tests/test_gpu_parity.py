@@ -287,3 +287,28 @@ def test_history_independence_on_gpu():
     o = oqf.OracleQF(q, r)
     o.insert(keys)
     assert same_layout(ref, o.export())[0]
+
+
+@pytest.mark.parametrize("q,r,batches", [(18, 16, 1), (16, 8, 3)])
+def test_zipf_counting_scaled(q, r, batches):
+    """Counting config at reduced size: Zipf(1.1) instances over a universe of
+    2^(q-2) values, 0.9 * 2^q instances, then counts over the universe and a
+    Bernoulli(0.25) delete of the inserted instances."""
+    note(f"zipf counting q={q} r={r} batches={batches}")
+    qf = _qf()
+    n = int(0.9 * (1 << q))
+    keys = inputs.zipf_keys(3, n, 1.1, 1 << (q - 2))
+    f = qf.CQF(q, r)
+    m = Model(q, r)
+    for part in np.array_split(keys, batches):
+        f.insert(dev(part))
+        m.insert(part)
+    export_ok(f, m.layout(), "zipf insert")
+    probe = inputs.rank_to_key(inputs.sample_without_replacement(4, 1 << (q - 2), 1 << 14) + 1)
+    assert np.array_equal(host(f.count(dev(probe))), m.counts(probe))
+    dmask = inputs.bernoulli_mask(5, n, 0.25)
+    nf = torch.zeros(1, dtype=torch.int64, device="cuda")
+    f.delete(dev(keys[dmask]), nf)
+    short = m.delete(keys[dmask])
+    export_ok(f, m.layout(), "zipf delete")
+    assert int(nf.item()) == short == 0
