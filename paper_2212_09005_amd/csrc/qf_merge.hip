@@ -21,11 +21,16 @@
 //     (all-or-nothing without a host round trip).
 //   * Inside a region: the old blocks and the region's new entries are staged
 //     in LDS with 16-byte loads; each of the 256 lanes owns a contiguous chunk
-//     of quotients.  Pass 1 composes the lanes' run maps; a run that receives
-//     no new entry keeps its length, read off the run-end bits without
-//     decoding.  A block scan of the maps gives each lane its carry; pass 2
-//     copies unchanged runs, decodes/merges/re-encodes the others, assembles
-//     the region's new slots in LDS and writes them with 16-byte stores.
+//     of quotients and works in int32 positions relative to the region.  Pass
+//     1 walks the chunk once: runs that receive no new entry keep their
+//     length (read off the run-end bits without decoding) and are composed
+//     into max-plus maps, cut at each changed run, whose old extent is
+//     recorded.  Then one lane per changed run decodes, merges and sizes it;
+//     the lane maps are finished, block-scanned and chained across regions.
+//     Pass 2 walks the chunk again from its carry: unchanged runs are copied
+//     to their new place, changed runs get their slots reserved and are then
+//     re-encoded one per lane.  The output buffers start zeroed, so gaps cost
+//     nothing; the region's extent leaves LDS in 16-byte stores.
 //     Regions whose runs or entries do not fit in LDS are done by one lane
 //     straight from and to global memory.
 #include "qf.h"
@@ -40,14 +45,14 @@ constexpr int64_t INF = INT64_MAX / 4;
 
 template <typename T>
 struct Cfg {
-  // largest region: 8192 slots (r = 8), 4096 (r = 16); LDS buffers hold 1.5
-  // regions of slots (a region's runs plus what spills past its end)
+  // largest region: 8192 slots (r = 8), 4096 (r = 16); the LDS buffers hold
+  // 1.25 regions of slots (a region's runs plus what spills past its end)
   static constexpr int SMAXLOG = sizeof(T) == 1 ? 13 : 12;
   static constexpr int SMAX = 1 << SMAXLOG;
-  static constexpr int CAP = SMAX + SMAX / 2;
+  static constexpr int CAP = SMAX + SMAX / 4;
   static constexpr int CAPW = CAP / 64;
   static constexpr int OW = SMAX / 64;
-  static constexpr int NCAP = 512;  // new entries staged in LDS (2 per lane)
+  static constexpr int NCAP = 448;  // distinct new entries staged in LDS (<= 2 per lane)
   static constexpr int CH = 64 * static_cast<int>(sizeof(T)) / 16;  // 16-byte chunks per block
   static constexpr int PER = 16 / static_cast<int>(sizeof(T));      // slots per chunk
 };
@@ -60,6 +65,7 @@ struct MergeArgs {
   uint32_t r, rlog, nregions;
   const uint64_t *ufp, *ucnt, *rb;
   uint64_t *tags;
+  uint64_t *rstat;  // 4 words per region: used, distinct, total, shortfall
   uint32_t epoch;
   uint64_t *state;
   int del;
@@ -67,25 +73,6 @@ struct MergeArgs {
 };
 
 // ---- readers of the current (old) table -------------------------------------
-template <typename T>
-struct OldLds {  // whole blocks staged from slot `base` (a multiple of 64); hi = last slot
-  const T *s;
-  const uint64_t *b;  // run-end words, bits outside the region's span cleared
-  int64_t base, hi;
-  __device__ uint64_t slot(int64_t j) const { return s[j - base]; }
-  __device__ int64_t next_end(int64_t from) const {
-    const int64_t t = from - base;
-    int64_t w = t >> 6;
-    const int64_t wl = (hi - base) >> 6;
-    uint64_t m = b[w] & (~0ull << (t & 63));
-    while (!m) {
-      if (++w > wl) return hi;
-      m = b[w];
-    }
-    return base + (w << 6) + ctz64(m);
-  }
-};
-
 template <typename T>
 struct OldGlb {
   const Block<T> *blk;
@@ -103,11 +90,12 @@ struct OldGlb {
 };
 
 // ---- the region's new <fingerprint, count> entries --------------------------
-struct NewLds {
-  const uint64_t *fp;
+// staged in LDS: (quotient - region start) << r | remainder, and the count
+struct NewRel {
+  const uint32_t *fp;
   const uint32_t *cnt;
-  __device__ uint64_t f(uint64_t i) const { return fp[i]; }
-  __device__ uint64_t c(uint64_t i) const { return cnt[i]; }
+  __device__ uint64_t f(uint32_t i) const { return fp[i]; }
+  __device__ uint64_t c(uint32_t i) const { return cnt[i]; }
 };
 struct NewGlb {
   const uint64_t *fp, *cnt;
@@ -120,65 +108,6 @@ struct NewGlb {
 // marks the last written slot as a run end, flush() ends the lane's output.
 // Run-end bits are gathered per 64-bit word; words shared with a neighbour's
 // extent are merged with and/or under the lane's mask.
-template <typename T>
-struct OutLds {
-  T *s;
-  uint64_t *b;
-  int64_t base, hi;  // base is a multiple of 64; positions [.., hi]
-  int64_t cw;
-  uint64_t acc, accm;
-  __device__ void init(T *s_, uint64_t *b_, int64_t base_, int64_t hi_) {
-    s = s_; b = b_; base = base_; hi = hi_; cw = -1; acc = 0; accm = 0;
-  }
-  __device__ void flush() {
-    if (accm == ~0ull) {
-      b[cw] = acc;
-    } else if (accm) {
-      atomicAnd(reinterpret_cast<ull *>(&b[cw]), static_cast<ull>(~accm));
-      atomicOr(reinterpret_cast<ull *>(&b[cw]), static_cast<ull>(acc));
-    }
-    acc = accm = 0;
-  }
-  __device__ void emit(int64_t j, uint64_t v) {
-    if (j > hi) return;
-    const int64_t t = j - base;
-    s[t] = static_cast<T>(v);
-    const int64_t w = t >> 6;
-    if (w != cw) {
-      if (cw >= 0) flush();
-      cw = w;
-    }
-    accm |= 1ull << (t & 63);
-  }
-  __device__ void set_end(int64_t j) {
-    if (j > hi) return;
-    acc |= 1ull << ((j - base) & 63);
-  }
-  // account for slot j without storing it (its value is written later)
-  __device__ void mark(int64_t j) {
-    if (j > hi) return;
-    const int64_t t = j - base;
-    const int64_t w = t >> 6;
-    if (w != cw) {
-      if (cw >= 0) flush();
-      cw = w;
-    }
-    accm |= 1ull << (t & 63);
-  }
-};
-
-// slot values only (run-end bits of these slots are set by the owning lane)
-template <typename T>
-struct SlotsLds {
-  T *s;
-  int64_t base, hi;
-  __device__ void emit(int64_t j, uint64_t v) {
-    if (j <= hi) s[j - base] = static_cast<T>(v);
-  }
-  __device__ void set_end(int64_t) {}
-  __device__ void flush() {}
-};
-
 template <typename T>
 struct OutGlb {
   Block<T> *blk;
@@ -405,108 +334,170 @@ __device__ __forceinline__ void walk(uint32_t r, int del, int64_t RS, const uint
   }
 }
 
-// The per-lane walk of the staged path.  Runs that receive no new entry keep
-// their old length (read off the run-end bits); the lengths of the lane's
-// changed runs [c0, c1) were computed beforehand, one run per lane.  Pass 1
-// (EMIT = false) composes the lane's run maps; pass 2 copies unchanged runs to
-// their new place, reserves the changed runs' slots (cstart), zero-fills gaps
-// and writes run-end and occupied bits and the offsets of the blocks that
-// start in the lane's chunk.
-template <typename T, bool EMIT>
-__device__ __forceinline__ void walk_fast(int64_t RS, const uint64_t *occ_l, int64_t x0, int64_t x1,
-                                          int64_t s0, int64_t s1, int64_t ope, const OldLds<T> &old,
-                                          uint32_t c0, uint32_t c1, const uint16_t *cxr,
-                                          const uint32_t *cL, uint16_t *cstart, OutLds<T> &out,
-                                          int64_t carry, Fn &F, uint64_t &used, uint64_t *nocc_l,
-                                          uint32_t *noff) {
-  int64_t wpos = max(carry + 1, s0);
-  int64_t next_bs = (s0 + 63) & ~static_cast<int64_t>(63);
-  // the chunk's occupied bits (a chunk never crosses a 64-bit word) and the
-  // run-end word being consumed stay in registers
-  uint64_t occ = 0;
-  if (x0 < x1) {
-    const int64_t t0 = x0 - RS;
-    occ = occ_l[t0 >> 6] >> (t0 & 63);
-    if (x1 - x0 < 64) occ &= (1ull << (x1 - x0)) - 1ull;
+// ---- the staged path: one region in LDS, each lane a chunk of quotients ----
+// Positions are int32: quotients relative to the region start, old slots as
+// indexes into the staged blocks, new slots as indexes into the assembled
+// output.  Maps are kept relative to the region start too (-1 = "none").
+struct Fn32 {
+  int32_t A, B;
+};
+__device__ __forceinline__ Fn32 f32_id() { return Fn32{-1, 0}; }
+__device__ __forceinline__ Fn32 f32_then(Fn32 g, Fn32 h) { return Fn32{max(h.A, g.A + h.B), g.B + h.B}; }
+
+template <typename T>
+struct OldStaged {
+  const T *s;
+  __device__ uint64_t slot(int32_t j) const { return s[j]; }
+};
+template <typename T>
+struct SlotsRel {
+  T *s;
+  __device__ void emit(int32_t j, uint64_t v) { s[j] = static_cast<T>(v); }
+};
+
+// Next run end at or after staged index j, reading the staged run-end words
+// through a one-word cursor (a lane's runs are visited in order).
+struct EndCursor {
+  const uint64_t *b;
+  int32_t nw, w;
+  uint64_t v;
+  __device__ void init(const uint64_t *b_, int32_t nw_) {
+    b = b_;
+    nw = nw_;
+    w = -1;
+    v = 0;
   }
-  uint64_t nocc = 0;  // new occupied bits of the chunk
-  int64_t rw = -1;    // index of the run-end word held in rv
-  uint64_t rv = 0;
-  const int64_t rwl = (old.hi - old.base) >> 6;
-  auto next_end = [&](int64_t from) -> int64_t {
-    int64_t w = (from - old.base) >> 6;
-    if (w != rw) {
-      rw = w;
-      rv = old.b[w];
+  __device__ int32_t next(int32_t j) {
+    const int32_t wj = j >> 6;
+    if (wj >= nw) return nw * 64 - 1;
+    if (wj != w) {
+      w = wj;
+      v = b[wj];
     }
-    uint64_t m = rv & (~0ull << ((from - old.base) & 63));
+    uint64_t m = v & (~0ull << (j & 63));
     while (!m) {
-      if (++rw > rwl) return old.hi;
-      rv = old.b[rw];
-      m = rv;
+      if (++w >= nw) return nw * 64 - 1;
+      v = b[w];
+      m = v;
     }
-    return old.base + (rw << 6) + ctz64(m);
-  };
-  int64_t xo = occ ? x0 + ctz64(occ) : INF;
-  uint32_t c = c0;
-  int64_t xc = c < c1 ? RS + cxr[c] : INF;
-  for (;;) {
-    const int64_t x = min(xo, xc);
-    if (x >= INF) break;
-    if (EMIT) {
-      for (; next_bs < x; next_bs += 64)
-        noff[next_bs >> 6] = static_cast<uint32_t>(max(carry - next_bs, static_cast<int64_t>(0)));
+    return (w << 6) + ctz64(m);
+  }
+};
+
+// Pass 1 over the lane's quotients [t0, t0 + QT): occ / chg are the chunk's
+// old-occupied bits and its bits of quotients that receive new entries.
+// Unchanged runs keep their length and are composed into maps; the maps are
+// cut at every changed run, whose old extent is recorded for the merge:
+// first = the maps before the lane's first changed run, gaf[c] = those after
+// changed run c up to the next one (or the chunk's end).
+__device__ __forceinline__ void walk1(int32_t t0, uint32_t occ, uint32_t chg, int32_t ob, int32_t ope,
+                                      EndCursor &ec, uint32_t c, uint16_t *cop, uint16_t *coe, Fn32 *gaf,
+                                      Fn32 &first, uint32_t &used) {
+  uint32_t u = occ | chg;
+  Fn32 G = f32_id();
+  bool seen = false;
+  while (u) {
+    const int b = __builtin_ctz(u);
+    u &= u - 1;
+    const int32_t x = t0 + b;
+    int32_t o = 0, e = -1;
+    if ((occ >> b) & 1u) {
+      o = max(x - ob, ope + 1);
+      e = ec.next(o);
+      ope = e;
     }
-    int64_t op = 0, oe = -1;
-    if (xo == x) {
-      op = max(x, ope + 1);
-      oe = next_end(op);
-      ope = oe;
-      occ &= occ - 1;
-      xo = occ ? x0 + ctz64(occ) : INF;
-    }
-    const bool changed = xc == x;
-    const int64_t L = changed ? static_cast<int64_t>(cL[c]) : oe - op + 1;
-    if (EMIT) {
-      const int64_t start = max(x, carry + 1);
-      for (; wpos < start; ++wpos) out.emit(wpos, 0);
-      if (L > 0) {
-        if (changed) {
-          cstart[c] = static_cast<uint16_t>(start - out.base);
-          for (int64_t j = start; j < start + L; ++j) out.mark(j);
-        } else {
-          int64_t pos = start;
-          for (int64_t j = op; j <= oe; ++j) out.emit(pos++, old.slot(j));
-        }
-        out.set_end(start + L - 1);
-        carry = start + L - 1;
-        wpos = start + L;
-        nocc |= 1ull << (x - x0);
-      }
-      if (x == next_bs) {
-        noff[x >> 6] = static_cast<uint32_t>(max(carry - x, static_cast<int64_t>(0)));
-        next_bs += 64;
-      }
-    } else if (L > 0) {
-      F = fn_then(F, Fn{x + L - 1, L});
-      used += static_cast<uint64_t>(L);
-    }
-    if (changed) {
+    if ((chg >> b) & 1u) {
+      // staged indexes are < CAP < 0xFFFF, so 0xFFFF marks "no old run"
+      cop[c] = static_cast<uint16_t>(o);
+      coe[c] = e >= o ? static_cast<uint16_t>(e) : static_cast<uint16_t>(0xFFFF);
+      // (a value select, not a store through a pointer picked between LDS
+      // and the lane's own `first`)
+      first = seen ? first : G;
+      if (seen) gaf[c - 1] = G;
+      seen = true;
+      G = f32_id();
       ++c;
-      xc = c < c1 ? RS + cxr[c] : INF;
+    } else {
+      const int32_t L = e - o + 1;
+      G = f32_then(G, Fn32{x + L - 1, L});
+      used += static_cast<uint32_t>(L);
     }
   }
-  if (EMIT) {
-    for (; next_bs < s1; next_bs += 64)
-      noff[next_bs >> 6] = static_cast<uint32_t>(max(carry - next_bs, static_cast<int64_t>(0)));
-    const int64_t ext_end = max(carry, s1 - 1);
-    for (; wpos <= ext_end; ++wpos) out.emit(wpos, 0);
-    out.flush();
-    if (nocc) {
-      const int64_t t0 = x0 - RS;
-      atomicOr(reinterpret_cast<ull *>(&nocc_l[t0 >> 6]), static_cast<ull>(nocc << (t0 & 63)));
+  first = seen ? first : G;
+  if (seen) gaf[c - 1] = G;
+}
+
+// Pass 2 over the same chunk, from the lane's carry (relative end of all
+// earlier runs): copies unchanged runs to their new place, reserves the
+// changed runs' slots (cst), sets run-end bits (output buffers start zeroed,
+// so gaps cost nothing) and collects the chunk's new occupied bits.  Returns
+// the carry after quotient t0 (for the offset of a block starting there).
+template <typename T>
+__device__ __forceinline__ int32_t walk2(int32_t t0, uint32_t occ, uint32_t chg, int32_t ob, int32_t ope,
+                                         EndCursor &ec, uint32_t c, const uint32_t *cL, uint16_t *cst,
+                                         const T *old_s, T *new_s, uint64_t *new_b, int32_t xb,
+                                         int32_t carry, uint32_t &nocc) {
+  uint32_t u = occ | chg;
+  int32_t c_t0 = carry;
+  int32_t cw = -1;
+  uint64_t bits = 0;
+  while (u) {
+    const int b = __builtin_ctz(u);
+    u &= u - 1;
+    const int32_t x = t0 + b;
+    int32_t o = 0, e = -1;
+    if ((occ >> b) & 1u) {
+      o = max(x - ob, ope + 1);
+      e = ec.next(o);
+      ope = e;
+    }
+    const bool ch = (chg >> b) & 1u;
+    const int32_t L = ch ? static_cast<int32_t>(cL[c]) : e - o + 1;
+    if (L > 0) {
+      const int32_t p = max(x, carry + 1) - xb;
+      if (ch) {
+        cst[c] = static_cast<uint16_t>(p);
+      } else {
+        for (int32_t k = 0; k < L; ++k) new_s[p + k] = old_s[o + k];
+      }
+      const int32_t pe = p + L - 1;
+      carry = pe + xb;
+      if ((pe >> 6) != cw) {
+        if (bits) atomicOr(reinterpret_cast<ull *>(&new_b[cw]), static_cast<ull>(bits));
+        cw = pe >> 6;
+        bits = 0;
+      }
+      bits |= 1ull << (pe & 63);
+      nocc |= 1u << b;
+    }
+    if (ch) ++c;
+    if (b == 0) c_t0 = carry;
+  }
+  if (bits) atomicOr(reinterpret_cast<ull *>(&new_b[cw]), static_cast<ull>(bits));
+  return c_t0;
+}
+
+// index of the k-th (0-based) set bit of v (v has more than k set bits), by
+// halving with popcounts
+__device__ __forceinline__ int select64_fast(uint64_t v, int k) {
+  int pos = 0;
+  uint32_t w = static_cast<uint32_t>(v);
+  int c = __popc(w);
+  if (k >= c) {
+    k -= c;
+    w = static_cast<uint32_t>(v >> 32);
+    pos = 32;
+  }
+#pragma unroll
+  for (int h = 16; h >= 1; h >>= 1) {
+    c = __popc(w & ((1u << h) - 1u));
+    if (k >= c) {
+      k -= c;
+      w >>= h;
+      pos += h;
     }
   }
+  return pos;
 }
 
 // the rare whole-region path: one lane, global memory in and out (inlined: an
@@ -533,7 +524,7 @@ __device__ __forceinline__ void walk_global(const Block<T> *ob, Block<T> *nbk, i
 }
 
 // ---- block-wide helpers (256 lanes = 4 waves) ---------------------------
-__device__ Fn block_exscan_fn(Fn v, Fn *sh, Fn *total) {
+__device__ __forceinline__ Fn block_exscan_fn(Fn v, Fn *sh, Fn *total) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   Fn inc = v;
   for (int d = 1; d < 64; d <<= 1) {
@@ -558,7 +549,7 @@ __device__ Fn block_exscan_fn(Fn v, Fn *sh, Fn *total) {
   return fn_then(wpre, ex);
 }
 
-__device__ uint32_t block_exscan_u32(uint32_t v, uint32_t *sh, uint32_t *total) {
+__device__ __forceinline__ uint32_t block_exscan_u32(uint32_t v, uint32_t *sh, uint32_t *total) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   uint32_t inc = v;
   for (int d = 1; d < 64; d <<= 1) {
@@ -577,7 +568,37 @@ __device__ uint32_t block_exscan_u32(uint32_t v, uint32_t *sh, uint32_t *total) 
   return wpre + inc - v;
 }
 
-__device__ uint64_t block_sum_u64(uint64_t v, uint64_t *sh) {
+// two exclusive sums at once (one set of barriers); sh holds 2 * NT / 64 words
+__device__ __forceinline__ uint2 block_exscan2_u32(uint2 v, uint32_t *sh, uint2 *total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint2 inc = v;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t ox = __shfl_up(inc.x, d), oy = __shfl_up(inc.y, d);
+    if (lane >= d) {
+      inc.x += ox;
+      inc.y += oy;
+    }
+  }
+  if (lane == 63) {
+    sh[2 * wv] = inc.x;
+    sh[2 * wv + 1] = inc.y;
+  }
+  __syncthreads();
+  uint2 wpre = make_uint2(0, 0), tot = make_uint2(0, 0);
+  for (int w = 0; w < NT / 64; ++w) {
+    if (w < wv) {
+      wpre.x += sh[2 * w];
+      wpre.y += sh[2 * w + 1];
+    }
+    tot.x += sh[2 * w];
+    tot.y += sh[2 * w + 1];
+  }
+  *total = tot;
+  __syncthreads();
+  return make_uint2(wpre.x + inc.x - v.x, wpre.y + inc.y - v.y);
+}
+
+__device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t *sh) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
@@ -641,32 +662,35 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs<T> a) {
   __shared__ __align__(16) T old_s[C::CAP];
   __shared__ __align__(16) T new_s[C::CAP];
   __shared__ uint64_t old_b[C::CAPW];
-  __shared__ uint32_t old_wp[C::CAPW + 1];
   __shared__ uint64_t new_b[C::CAPW];
+  __shared__ uint32_t old_wp[C::CAPW + 1];
   __shared__ uint64_t occ_l[C::OW];
-  __shared__ uint32_t occ_wp[C::OW + 1];
-  __shared__ uint64_t nocc_l[C::OW];
+  // quotients that receive new entries; reused for the new occupied bits of
+  // the one-lane path
+  __shared__ uint64_t chg_l[C::OW];
   // the region's new entries, and its changed runs (one per distinct quotient)
-  __shared__ uint64_t nfp_l[C::NCAP];
+  __shared__ uint32_t nfp_l[C::NCAP];
   __shared__ uint32_t ncnt_l[C::NCAP];
-  __shared__ uint16_t chg_of[C::NCAP];  // changed run of each entry
-  __shared__ uint16_t cxr[C::NCAP];     // its quotient - RS
-  __shared__ uint16_t chead[C::NCAP];   // its first entry
-  __shared__ uint16_t cop[C::NCAP];     // its old run, relative to the staged base
+  __shared__ uint16_t cxr[C::NCAP];    // quotient - RS
+  __shared__ uint16_t chead[C::NCAP];  // first entry
+  __shared__ uint16_t cop[C::NCAP];    // old run, staged indexes (coe 0xFFFF: none)
   __shared__ uint16_t coe[C::NCAP];
-  __shared__ uint32_t cL[C::NCAP];      // its new length
-  __shared__ uint16_t cstart[C::NCAP];  // its new first slot, relative to the output base
-  __shared__ uint32_t lane_start[NT + 1];
+  __shared__ uint32_t cL[C::NCAP];     // new length
+  __shared__ uint16_t cst[C::NCAP];    // new first slot, output index
+  __shared__ Fn32 gaf[C::NCAP];        // maps of the unchanged runs after it
   __shared__ int64_t sh_i[8];
   __shared__ Fn sh_fn[NT / 64];
-  __shared__ uint32_t sh_u[NT / 64];
+  __shared__ uint32_t sh_u[2 * NT / 64];
   __shared__ uint64_t sh_r[NT / 64];
 
   const int tid = threadIdx.x;
+  // tickets hand out regions in order, so every region's predecessors belong
+  // to running or finished work-groups (the look-back cannot wait on a
+  // work-group that has not started)
   if (tid == 0) sh_i[0] = static_cast<int64_t>(atomic_add_u64(&a.state[ST_TILE], 1));
   __syncthreads();
   const int64_t R = sh_i[0];
-  const int64_t S = 1ll << a.rlog;
+  const int32_t S = 1 << a.rlog;
   const int64_t RS = R << a.rlog;
   // (selects, not a dynamic index into the argument struct, which would put
   // the struct in scratch memory)
@@ -680,19 +704,25 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs<T> a) {
   const int nw_reg = static_cast<int>((send - RS + 63) >> 6);
   const uint64_t rb0 = a.rb[R], rb1 = a.rb[R + 1];
   const uint64_t ne = rb1 - rb0;
+  const uint32_t r = a.r;
 
   for (int w = tid; w < nw_reg; w += NT) {
     occ_l[w] = qreg ? ob[(RS >> 6) + w].occ : 0ull;
-    nocc_l[w] = 0ull;
+    chg_l[w] = 0ull;
   }
+  for (int w = tid; w < C::CAPW; w += NT) new_b[w] = 0ull;
+  for (int i = tid; i < C::CAP * static_cast<int>(sizeof(T)) / 16; i += NT)
+    reinterpret_cast<uint4 *>(new_s)[i] = make_uint4(0u, 0u, 0u, 0u);
   if (qreg) {
     if (tid == 0) sh_i[1] = carry_old(ob, ooff, RS, a.N);
     if (tid == 64) sh_i[2] = carry_old(ob, ooff, RS + S, a.N);
   }
   const bool new_lds = ne <= static_cast<uint64_t>(C::NCAP);
   if (new_lds) {
-    for (uint64_t i = tid; i < ne; i += NT) {
-      nfp_l[i] = a.ufp[rb0 + i];
+    const uint64_t rmask = (1ull << r) - 1ull;
+    for (uint32_t i = tid; i < ne; i += NT) {
+      const uint64_t fp = a.ufp[rb0 + i];
+      nfp_l[i] = static_cast<uint32_t>((((fp >> r) - static_cast<uint64_t>(RS)) << r) | (fp & rmask));
       ncnt_l[i] = static_cast<uint32_t>(a.ucnt[rb0 + i]);
     }
   }
@@ -701,9 +731,11 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs<T> a) {
   const int64_t hi_old = qreg ? sh_i[2] : RS - 1;
   const bool has_old = hi_old >= lo_old;
   const int64_t bb = has_old ? (lo_old >> 6) : (RS >> 6);
-  const int nblk = has_old ? static_cast<int>((hi_old >> 6) - bb + 1) : 0;
-  const bool par = new_lds && nblk <= C::CAPW;
-  const int64_t obase = bb << 6;
+  const int64_t nblk64 = has_old ? (hi_old >> 6) - bb + 1 : 0;
+  // the staged path: entries and old runs fit in LDS (and positions in int32)
+  const bool par = new_lds && nblk64 <= C::CAPW && (bb << 6) - RS < (1ll << 30);
+  const int nblk = par ? static_cast<int>(nblk64) : 0;
+  const int32_t obr = static_cast<int32_t>(par ? (bb << 6) - RS : 0);  // staged base - RS
 
   if (par && nblk > 0) {
     // 16-byte chunks of the staged blocks' slots, then their run-end words
@@ -719,127 +751,110 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs<T> a) {
       old_b[w] = v;
     }
   }
-  // lane ranges of the new entries; changed runs = groups of equal quotient
-  const int64_t QT = max(S >> 8, static_cast<int64_t>(1));
-  const int qshift = __builtin_ctzll(static_cast<uint64_t>(QT));
-  if (par) {
-    lane_start[tid] = static_cast<uint32_t>(ne);
-    if (tid == 0) lane_start[NT] = static_cast<uint32_t>(ne);
-  }
-  __syncthreads();
+  // changed runs = groups of equal quotient among the new entries: entries
+  // [2 tid, 2 tid + 2) per lane (ne <= NCAP <= 2 NT here)
   uint32_t nchg = 0;
-  if (par) {
-    for (uint64_t e = tid; e < ne; e += NT) {
-      const int le = static_cast<int>((static_cast<int64_t>(nfp_l[e] >> a.r) - RS) >> qshift);
-      const int lp = e == 0 ? -1 : static_cast<int>((static_cast<int64_t>(nfp_l[e - 1] >> a.r) - RS) >> qshift);
-      for (int l = lp + 1; l <= le; ++l) lane_start[l] = static_cast<uint32_t>(e);
-    }
-  }
   {
-    // heads of quotient groups: entries [2 tid, 2 tid + 2) per lane (ne <= 512
-    // here; more entries take the global path)
     uint32_t h0 = 0, h1 = 0;
-    const uint64_t e0 = 2ull * tid, e1 = e0 + 1;
-    if (par && e0 < ne) h0 = e0 == 0 || (nfp_l[e0] >> a.r) != (nfp_l[e0 - 1] >> a.r);
-    if (par && e1 < ne) h1 = (nfp_l[e1] >> a.r) != (nfp_l[e0] >> a.r);
+    const uint32_t e0 = 2u * tid, e1 = e0 + 1;
+    const uint32_t x0 = par && e0 < ne ? nfp_l[e0] >> r : 0u;
+    const uint32_t x1 = par && e1 < ne ? nfp_l[e1] >> r : 0u;
+    if (par && e0 < ne) h0 = e0 == 0 || x0 != (nfp_l[e0 - 1] >> r);
+    if (par && e1 < ne) h1 = x1 != x0;
     uint32_t tot;
     const uint32_t ex = block_exscan_u32(h0 + h1, sh_u, &tot);
     nchg = tot;
-    if (par && e0 < ne) {
-      chg_of[e0] = static_cast<uint16_t>(ex + h0 - 1);
-      if (h0) {
-        cxr[ex] = static_cast<uint16_t>((nfp_l[e0] >> a.r) - RS);
-        chead[ex] = static_cast<uint16_t>(e0);
-      }
+    if (h0) {
+      cxr[ex] = static_cast<uint16_t>(x0);
+      chead[ex] = static_cast<uint16_t>(e0);
+      atomicOr(reinterpret_cast<ull *>(&chg_l[x0 >> 6]), static_cast<ull>(1ull << (x0 & 63)));
     }
-    if (par && e1 < ne) {
-      chg_of[e1] = static_cast<uint16_t>(ex + h0 + h1 - 1);
-      if (h1) {
-        cxr[ex + h0] = static_cast<uint16_t>((nfp_l[e1] >> a.r) - RS);
-        chead[ex + h0] = static_cast<uint16_t>(e1);
-      }
+    if (h1) {
+      cxr[ex + h0] = static_cast<uint16_t>(x1);
+      chead[ex + h0] = static_cast<uint16_t>(e1);
+      atomicOr(reinterpret_cast<ull *>(&chg_l[x1 >> 6]), static_cast<ull>(1ull << (x1 & 63)));
     }
   }
-  // prefix counts of run ends per staged word and of occupied quotients per
-  // region word (for rank / select)
-  {
-    uint32_t tot;
-    const uint32_t pc = (par && tid < nblk) ? static_cast<uint32_t>(popc64(old_b[tid])) : 0u;
-    const uint32_t ex = block_exscan_u32(pc, sh_u, &tot);
-    if (par && tid < nblk) old_wp[tid] = ex;
-    if (par && tid == 0) old_wp[nblk] = tot;
-    const uint32_t po = (par && tid < nw_reg) ? static_cast<uint32_t>(popc64(occ_l[tid])) : 0u;
-    const uint32_t exo = block_exscan_u32(po, sh_u, &tot);
-    if (par && tid < nw_reg) occ_wp[tid] = exo;
-    if (par && tid == 0) occ_wp[nw_reg] = tot;
+  __syncthreads();
+  // the lane's chunk of quotients [t0, t0 + QT), its bits, and prefix counts:
+  // run ends per staged word (for select), occupied and changed quotients
+  // before the chunk (its first old run, its first changed run)
+  const int QT = max(S >> 8, 1);
+  const int32_t t0 = tid * QT;
+  const bool chunk = par && qreg && t0 < S;
+  uint32_t occ_c = 0, chg_c = 0;
+  if (chunk) {
+    const uint32_t m = QT >= 32 ? ~0u : ((1u << QT) - 1u);
+    occ_c = static_cast<uint32_t>(occ_l[t0 >> 6] >> (t0 & 63)) & m;
+    chg_c = static_cast<uint32_t>(chg_l[t0 >> 6] >> (t0 & 63)) & m;
   }
-
-  // lane chunk: quotients / slots [s0, s1)
-  int64_t s0, s1;
-  if (par) {
-    s0 = min(RS + tid * QT, send);
-    s1 = min(s0 + QT, send);
-  } else {
-    s0 = tid == 0 ? RS : send;
-    s1 = send;
-  }
-  const int64_t x0 = qreg ? s0 : 0, x1 = qreg ? s1 : 0;
-  // end of the last old run before the lane's chunk
-  int64_t ope = lo_old - 1;
-  uint32_t c0 = 0, c1 = 0;
-  auto select_end = [&](uint32_t k) -> int64_t {  // position of the k-th (0-based) staged run end
+  uint2 tot2;
+  const uint32_t pw = (par && tid < nblk) ? static_cast<uint32_t>(popc64(old_b[tid])) : 0u;
+  const uint2 ex2 = block_exscan2_u32(
+      make_uint2(pw, static_cast<uint32_t>(__popc(occ_c)) | (static_cast<uint32_t>(__popc(chg_c)) << 16)),
+      sh_u, &tot2);
+  if (par && tid < nblk) old_wp[tid] = ex2.x;
+  if (par && tid == 0) old_wp[nblk] = tot2.x;
+  const uint32_t kocc = ex2.y & 0xFFFFu, c0 = ex2.y >> 16;
+  const uint32_t c1 = c0 + static_cast<uint32_t>(__popc(chg_c));
+  __syncthreads();
+  // staged index of the end of the last old run before the chunk
+  int32_t ope0 = static_cast<int32_t>(lo_old - RS) - obr - 1;
+  if (chunk && occ_c && kocc > 0) {
+    const uint32_t k = kocc - 1;
     int lo = 0, hi = nblk - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (old_wp[mid] <= k) lo = mid; else hi = mid - 1;
     }
-    return obase + (static_cast<int64_t>(lo) << 6) + select64(old_b[lo], static_cast<int>(k - old_wp[lo]));
-  };
-  if (par && qreg && x0 < x1) {
-    const int64_t t0 = x0 - RS;
-    const uint32_t k = occ_wp[t0 >> 6] + static_cast<uint32_t>(popc64(occ_l[t0 >> 6] & ((1ull << (t0 & 63)) - 1ull)));
-    if (k > 0) ope = select_end(k - 1);
-    const uint32_t ea = lane_start[tid], eb = lane_start[tid + 1];
-    c0 = ea < ne ? chg_of[ea] : nchg;
-    c1 = eb < ne ? chg_of[eb] : nchg;
+    ope0 = (lo << 6) + select64_fast(old_b[lo], static_cast<int>(k - old_wp[lo]));
   }
-  __syncthreads();
 
   Acc acc{fn_id(), 0, 0, 0, 0, 0};
+  Fn Flane = fn_id();
   if (par) {
-    // ---- pass 1a: new lengths of the changed runs, one run per lane --------
-    OldLds<T> old{old_s, old_b, obase, hi_old};
-    NewLds nw{nfp_l, ncnt_l};
-    NoOut none;
-    for (uint32_t c = tid; c < nchg; c += NT) {
-      const int64_t x = RS + cxr[c];
-      const uint64_t ni = chead[c], nj = c + 1 < nchg ? chead[c + 1] : ne;
-      const int64_t t = x - RS;
-      int64_t op = 0, oe = -1;
-      if ((occ_l[t >> 6] >> (t & 63)) & 1ull) {
-        const uint32_t k = occ_wp[t >> 6] + static_cast<uint32_t>(popc64(occ_l[t >> 6] & ((1ull << (t & 63)) - 1ull)));
-        oe = select_end(k);
-        op = max(x, (k > 0 ? select_end(k - 1) : lo_old - 1) + 1);
-      }
-      // staged positions are < CAP, so 0xFFFF marks "no old run"
-      cop[c] = oe >= op ? static_cast<uint16_t>(op - obase) : 0;
-      coe[c] = oe >= op ? static_cast<uint16_t>(oe - obase) : 0xFFFF;
-      cL[c] = static_cast<uint32_t>(merge_run<false>(old, op, oe, nw, ni, nj, a.r, a.del, none, int64_t{0}, acc));
+    // ---- pass 1: the lane's unchanged runs, cut at its changed runs -------
+    Fn32 first = f32_id();
+    uint32_t used = 0;
+    if (chunk) {
+      EndCursor ec;
+      ec.init(old_b, nblk);
+      walk1(t0, occ_c, chg_c, obr, ope0, ec, c0, cop, coe, gaf, first, used);
     }
     __syncthreads();
-    // ---- pass 1b: the lane's run maps -------------------------------------
-    OutLds<T> dummy_out;
-    dummy_out.init(new_s, new_b, 0, -1);
-    walk_fast<T, false>(RS, occ_l, x0, x1, s0, s1, ope, old, c0, c1, cxr, cL, cstart, dummy_out, 0,
-                        acc.F, acc.used, nocc_l, noff);
+    // ---- pass 1a: new lengths of the changed runs, one run per lane --------
+    NewRel nw{nfp_l, ncnt_l};
+    OldStaged<T> old{old_s};
+    NoOut none;
+    for (uint32_t c = tid; c < nchg; c += NT) {
+      const uint32_t ni = chead[c], nj = c + 1 < nchg ? chead[c + 1] : static_cast<uint32_t>(ne);
+      const bool ho = coe[c] != 0xFFFF;
+      const int32_t L = merge_run<false>(old, ho ? static_cast<int32_t>(cop[c]) : 0,
+                                         ho ? static_cast<int32_t>(coe[c]) : -1, nw, ni, nj, r, a.del, none,
+                                         int32_t{0}, acc);
+      cL[c] = static_cast<uint32_t>(L);
+      used += static_cast<uint32_t>(L);
+    }
+    __syncthreads();
+    // ---- the lane's map: its segments and changed runs in quotient order ---
+    Fn32 F = first;
+    for (uint32_t c = c0; c < c1; ++c) {
+      const int32_t L = static_cast<int32_t>(cL[c]);
+      if (L > 0) F = f32_then(F, Fn32{static_cast<int32_t>(cxr[c]) + L - 1, L});
+      F = f32_then(F, gaf[c]);
+    }
+    Flane.A = F.A >= 0 ? RS + F.A : RS - 1;
+    Flane.B = F.B;
+    acc.used = used;
   } else if (tid == 0) {
     Acc ag{fn_id(), 0, 0, 0, 0, 0};
-    walk_global<T, false>(ob, nbk, a.nblocks, a.ufp, a.ucnt, a.r, a.del, RS, occ_l, x0, x1, s0, s1, ope,
-                          rb0, rb1, 0, 0, &ag, nocc_l, noff);
+    walk_global<T, false>(ob, nbk, a.nblocks, a.ufp, a.ucnt, a.r, a.del, RS, occ_l, qreg ? RS : 0,
+                          qreg ? send : 0, RS, send, lo_old - 1, rb0, rb1, 0, 0, &ag, chg_l, noff);
     acc = ag;
+    Flane = ag.F;
   }
   Fn Ftot;
-  const Fn Fex = block_exscan_fn(acc.F, sh_fn, &Ftot);
+  const Fn Fex = block_exscan_fn(Flane, sh_fn, &Ftot);
   const uint64_t used = block_sum_u64(acc.used, sh_r);
   const uint64_t dent = block_sum_u64(acc.dent, sh_r);
   const uint64_t dtot = block_sum_u64(acc.dtot, sh_r);
@@ -857,55 +872,68 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs<T> a) {
       tag_store(&a.tags[2ull * a.nregions + R], a.epoch, c_out);
       sh_i[3] = c_in;
       sh_i[4] = c_out;
+      // errors are rare and set one shared word; the statistics go to the
+      // region's own words and are summed after the launch
       if (c_out >= a.P) atomic_or_u64(&a.state[ST_BATCH], BATCH_FULL);
       if (ovf) atomic_or_u64(&a.state[ST_BATCH], BATCH_OVF);
-      if (used) atomic_add_u64(&a.state[ST_NUSED], used);
-      if (dent) atomic_add_u64(&a.state[ST_NDIST], dent);
-      if (dtot) atomic_add_u64(&a.state[ST_NTOTAL], dtot);
-      if (a.del && shortfall) atomic_add_u64(a.not_found, shortfall);
+      uint64_t *st = a.rstat + 4 * R;
+      st[0] = used;
+      st[1] = dent;
+      st[2] = dtot;
+      st[3] = shortfall;
     }
   }
   __syncthreads();
 
   // ---- pass 2: write the region's extent into the other copy --------------
+  // A region whose runs pass the last slot fails the whole batch (the other
+  // copy never becomes current), so it writes nothing; every other region's
+  // runs end below P, which bounds all writes below.
   const int64_t c_in = sh_i[3], c_out = sh_i[4];
+  const bool emit = c_out < a.P;
   const int64_t ext_lo = max(c_in + 1, RS);
-  const int64_t ext_hi = min(max(c_out, send - 1), a.P - 1);
+  const int64_t ext_hi = max(c_out, send - 1);
   const int64_t xbase = (ext_lo >> 6) << 6;
   const int nxb = ext_hi >= ext_lo ? static_cast<int>((ext_hi >> 6) - (ext_lo >> 6) + 1) : 0;
-  const bool lds_out = par && nxb <= C::CAPW;
-  const int64_t c_t = fn_apply(Fex, c_in);
+  const bool lds_out = emit && par && nxb <= C::CAPW && xbase - RS < (1ll << 30);
   if (lds_out) {
-    // 2a: unchanged runs, gaps, bits, offsets; reserve the changed runs
-    OldLds<T> old{old_s, old_b, obase, hi_old};
-    OutLds<T> out;
-    out.init(new_s, new_b, xbase, ext_hi);
-    Fn Fd = fn_id();
-    uint64_t ud = 0;
-    walk_fast<T, true>(RS, occ_l, x0, x1, s0, s1, ope, old, c0, c1, cxr, cL, cstart, out, c_t, Fd, ud,
-                       nocc_l, noff);
+    const int32_t xb = static_cast<int32_t>(xbase - RS);
+    uint32_t nocc = 0;
+    if (chunk) {
+      const int64_t c_t = fn_apply(Fex, c_in);
+      const int32_t carry = static_cast<int32_t>(max(c_t - RS, static_cast<int64_t>(-1)));
+      EndCursor ec;
+      ec.init(old_b, nblk);
+      const int32_t ct0 = walk2<T>(t0, occ_c, chg_c, obr, ope0, ec, c0, cL, cst, old_s, new_s, new_b, xb,
+                                   carry, nocc);
+      if ((t0 & 63) == 0) noff[(RS + t0) >> 6] = static_cast<uint32_t>(max(ct0 - t0, 0));
+    }
+    if (qreg) {
+      // the new occupied words: OR the chunks of each 64-quotient word into
+      // its first lane (all lanes take part in the shuffles)
+      uint64_t wv = chunk ? static_cast<uint64_t>(nocc) << (t0 & 63) : 0ull;
+      for (int d = 1; d < 64 / QT; d <<= 1) wv |= __shfl_down(wv, d);
+      if (chunk && (t0 & 63) == 0) nbk[(RS + t0) >> 6].occ = wv;
+    } else {
+      for (int w = tid; w < nw_reg; w += NT) {
+        nbk[(RS >> 6) + w].occ = 0ull;
+        noff[(RS >> 6) + w] = static_cast<uint32_t>(max(c_in - (RS + 64ll * w), static_cast<int64_t>(0)));
+      }
+    }
     __syncthreads();
     // 2b: the changed runs' slots, one run per lane
-    NewLds nw{nfp_l, ncnt_l};
-    SlotsLds<T> so{new_s, xbase, ext_hi};
+    NewRel nw{nfp_l, ncnt_l};
+    OldStaged<T> old{old_s};
+    SlotsRel<T> so{new_s};
     Acc dummy{fn_id(), 0, 0, 0, 0, 0};
     for (uint32_t c = tid; c < nchg; c += NT) {
       if (cL[c] == 0) continue;
-      const uint64_t ni = chead[c], nj = c + 1 < nchg ? chead[c + 1] : ne;
-      const int64_t op = coe[c] == 0xFFFF ? 0 : obase + cop[c];
-      const int64_t oe = coe[c] == 0xFFFF ? -1 : obase + coe[c];
-      merge_run<true>(old, op, oe, nw, ni, nj, a.r, a.del, so, static_cast<int64_t>(xbase + cstart[c]), dummy);
+      const uint32_t ni = chead[c], nj = c + 1 < nchg ? chead[c + 1] : static_cast<uint32_t>(ne);
+      const bool ho = coe[c] != 0xFFFF;
+      merge_run<true>(old, ho ? static_cast<int32_t>(cop[c]) : 0, ho ? static_cast<int32_t>(coe[c]) : -1, nw,
+                      ni, nj, r, a.del, so, static_cast<int32_t>(cst[c]), dummy);
     }
-  } else if (tid == 0) {
-    // one lane redoes the whole region from global memory
-    Acc dummy{fn_id(), 0, 0, 0, 0, 0};
-    walk_global<T, true>(ob, nbk, a.nblocks, a.ufp, a.ucnt, a.r, a.del, RS, occ_l, qreg ? RS : 0,
-                         qreg ? send : 0, RS, send, lo_old - 1, rb0, rb1, ext_hi, c_in, &dummy, nocc_l,
-                         noff);
-  }
-  __syncthreads();
-
-  if (lds_out && nxb > 0) {
+    __syncthreads();
     // slots: whole 16-byte chunks inside the extent, single slots at its ends
     for (int idx = tid; idx < nxb * C::CH; idx += NT) {
       const int b = idx / C::CH, c = idx % C::CH;
@@ -932,27 +960,49 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs<T> a) {
         atomic_or_u64(&nbk[w].rend, v);
       }
     }
-  }
-  for (int w = tid; w < nw_reg; w += NT) nbk[(RS >> 6) + w].occ = nocc_l[w];
-
-  __syncthreads();
-  if (tid == 0) {
-    __threadfence();
-    const uint64_t d = atomic_add_u64(&a.state[ST_DONE], 1);
-    if (d + 1 == a.nregions) {
-      __threadfence();
-      const uint64_t st = __hip_atomic_load(&a.state[ST_BATCH], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (st == 0) {
-        a.state[ST_USED] = __hip_atomic_load(&a.state[ST_NUSED], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        a.state[ST_DIST] += __hip_atomic_load(&a.state[ST_NDIST], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        a.state[ST_TOTAL] += __hip_atomic_load(&a.state[ST_NTOTAL], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        a.state[ST_CUR] = static_cast<uint64_t>(cur ^ 1);
-      } else {
-        const int64_t code = (st & BATCH_FULL) ? -2 : -5;
-        atomicCAS(reinterpret_cast<ull *>(&a.state[ST_ERR]), 0ull, static_cast<ull>(code));
-      }
-      a.state[ST_BATCHES] += 1;
+  } else if (emit) {
+    // one lane redoes the whole region from global memory; chg_l collects
+    // the new occupied bits
+    for (int w = tid; w < nw_reg; w += NT) chg_l[w] = 0ull;
+    __syncthreads();
+    if (tid == 0) {
+      Acc dummy{fn_id(), 0, 0, 0, 0, 0};
+      walk_global<T, true>(ob, nbk, a.nblocks, a.ufp, a.ucnt, a.r, a.del, RS, occ_l, qreg ? RS : 0,
+                           qreg ? send : 0, RS, send, lo_old - 1, rb0, rb1, ext_hi, c_in, &dummy, chg_l, noff);
     }
+    __syncthreads();
+    for (int w = tid; w < nw_reg; w += NT) nbk[(RS >> 6) + w].occ = chg_l[w];
+  }
+}
+
+// After the merge: sum the regions' statistics; flip the current copy if no
+// region failed, else record the error (all-or-nothing).  One work-group.
+__global__ __launch_bounds__(1024) void k_finish(uint64_t *state, const uint64_t *rstat, uint32_t nregions,
+                                                 int del, uint64_t *not_found) {
+  __shared__ uint64_t sh[4][16];
+  uint64_t v[4] = {0, 0, 0, 0};
+  for (uint32_t R = threadIdx.x; R < nregions; R += 1024)
+    for (int k = 0; k < 4; ++k) v[k] += rstat[4ull * R + k];
+  for (int k = 0; k < 4; ++k) {
+    for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o);
+    if ((threadIdx.x & 63) == 0) sh[k][threadIdx.x >> 6] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t t[4] = {0, 0, 0, 0};
+    for (int k = 0; k < 4; ++k)
+      for (int w = 0; w < 16; ++w) t[k] += sh[k][w];
+    const uint64_t st = state[ST_BATCH];
+    if (st == 0) {
+      state[ST_USED] = t[0];
+      state[ST_DIST] += t[1];
+      state[ST_TOTAL] += t[2];
+      state[ST_CUR] ^= 1ull;
+    } else if (state[ST_ERR] == 0) {
+      state[ST_ERR] = static_cast<uint64_t>((st & BATCH_FULL) ? -2 : -5);
+    }
+    if (del) *not_found += t[3];
+    state[ST_BATCHES] += 1;
   }
 }
 
@@ -978,8 +1028,10 @@ hipError_t launch_merge_t(qf_filter *f, const uint64_t *ufp, const uint64_t *ucn
   a.state = f->state;
   a.del = del;
   a.not_found = not_found ? not_found : f->state + ST_SCRATCH;
+  a.rstat = f->rstat;
   if (f->timer) f->timer->begin(QF_PROF_MERGE, s);
   k_merge<T><<<f->nregions, NT, 0, s>>>(a);
+  k_finish<<<1, 1024, 0, s>>>(f->state, f->rstat, f->nregions, del, a.not_found);
   if (f->timer) f->timer->end(QF_PROF_MERGE, s);
   return hipGetLastError();
 }
