@@ -50,7 +50,10 @@ enum {
   QF_ERR_FULL = -2,           /* a run would end past the last slot           */
   QF_ERR_OOM = -3,            /* device allocation failed                     */
   QF_ERR_DEVICE = -4,         /* a HIP runtime call failed                    */
-  QF_ERR_COUNT_OVERFLOW = -5  /* a count would exceed 2^64 - 1                */
+  QF_ERR_COUNT_OVERFLOW = -5, /* a count would exceed 2^64 - 1                */
+  QF_ERR_STALLED = -6         /* a merge region waited too long for the carry
+                                 of the regions before it (a safety bound
+                                 that should never trigger); batch not applied */
 };
 
 /* Logical layout of a table, as host arrays (qf_export / qf_import).

@@ -211,10 +211,10 @@ qf_t *qf_create(uint32_t q, uint32_t r) {
   f->hist_words = 256ull * 1024ull + 256ull * 8;  // histograms + per-pass digit totals
   ok = ok && hipMalloc(reinterpret_cast<void **>(&f->state), qf::ST_WORDS * sizeof(uint64_t)) == hipSuccess &&
        hipMalloc(reinterpret_cast<void **>(&f->rb), (f->nregions + 1ull) * sizeof(uint64_t)) == hipSuccess &&
-       hipMalloc(reinterpret_cast<void **>(&f->tags), 7ull * f->nregions * sizeof(uint64_t)) == hipSuccess &&
+       hipMalloc(reinterpret_cast<void **>(&f->tags), (8ull * f->nregions + 8) * sizeof(uint64_t)) == hipSuccess &&
        hipMalloc(reinterpret_cast<void **>(&f->hist), f->hist_words * sizeof(uint32_t)) == hipSuccess;
   ok = ok && hipMemset(f->state, 0, qf::ST_WORDS * sizeof(uint64_t)) == hipSuccess &&
-       hipMemset(f->tags, 0, 7ull * f->nregions * sizeof(uint64_t)) == hipSuccess &&
+       hipMemset(f->tags, 0, (8ull * f->nregions + 8) * sizeof(uint64_t)) == hipSuccess &&
        hipDeviceSynchronize() == hipSuccess;
   if (!ok) {
     qf_destroy(f);
@@ -222,8 +222,9 @@ qf_t *qf_create(uint32_t q, uint32_t r) {
     return nullptr;
   }
   f->rstat = f->tags + 3ull * f->nregions;
+  f->cb = reinterpret_cast<int64_t *>(f->tags + 7ull * f->nregions);
   f->device_bytes = 2 * qf::table_bytes(f->nblocks, r) + qf::ST_WORDS * 8 + (f->nregions + 1ull) * 8 +
-                    7ull * f->nregions * 8 + f->hist_words * 4;
+                    (8ull * f->nregions + 8) * 8 + f->hist_words * 4;
   return f;
 }
 

@@ -42,7 +42,7 @@ enum : int {
   ST_SCRATCH = 13,  // sink for a NULL not-found pointer
   ST_WORDS = 16
 };
-enum : uint64_t { BATCH_FULL = 1, BATCH_OVF = 2 };
+enum : uint64_t { BATCH_FULL = 1, BATCH_OVF = 2, BATCH_STALL = 4 };
 
 typedef unsigned long long ull;
 

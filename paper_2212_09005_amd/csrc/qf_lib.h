@@ -24,7 +24,8 @@ struct qf_filter {
   uint64_t *state;          // qf::ST_WORDS device words
   uint64_t *rb;             // nregions + 1 region bounds into the reduced batch
   uint64_t *tags;           // 3 * nregions look-back words, then
-  uint64_t *rstat;          // 4 * nregions per-region merge statistics
+  uint64_t *rstat;          // 4 * nregions per-region merge statistics, then
+  int64_t *cb;              // nqregions + 1 old carries at region boundaries
   uint32_t epoch;
   uint64_t batches;
   // grow-only scratch, capacity in keys

@@ -46,13 +46,14 @@ constexpr int64_t INF = INT64_MAX / 4;
 template <typename T>
 struct Cfg {
   // largest region: 8192 slots (r = 8), 4096 (r = 16); the LDS buffers hold
-  // 1.25 regions of slots (a region's runs plus what spills past its end)
+  // 1.125 regions of slots: a region's runs plus what spills past its end
+  // (at load 0.95 a region's runs end at most ~80 slots past it)
   static constexpr int SMAXLOG = sizeof(T) == 1 ? 13 : 12;
   static constexpr int SMAX = 1 << SMAXLOG;
-  static constexpr int CAP = SMAX + SMAX / 4;
+  static constexpr int CAP = SMAX + SMAX / 8;
   static constexpr int CAPW = CAP / 64;
   static constexpr int OW = SMAX / 64;
-  static constexpr int NCAP = 448;  // distinct new entries staged in LDS (<= 2 per lane)
+  static constexpr int NCAP = 304;  // distinct new entries staged in LDS (<= 2 per lane)
   static constexpr int CH = 64 * static_cast<int>(sizeof(T)) / 16;  // 16-byte chunks per block
   static constexpr int PER = 16 / static_cast<int>(sizeof(T));      // slots per chunk
 };
@@ -66,6 +67,7 @@ struct MergeArgs {
   const uint64_t *ufp, *ucnt, *rb;
   uint64_t *tags;
   uint64_t *rstat;  // 4 words per region: used, distinct, total, shortfall
+  const int64_t *cb;  // old carries at the quotient-region boundaries
   uint32_t epoch;
   uint64_t *state;
   int del;
@@ -194,6 +196,19 @@ __device__ int64_t carry_old(const Block<T> *b, const uint32_t *off, int64_t i, 
     --w;
     m = b[w].rend;
   }
+}
+
+// Old carry at every quotient-region boundary: cb[R] = carry_old(R S) for
+// R in [0, nq] (nq = number of quotient regions), one thread each, so that
+// the merge reads its region's bounds with one load instead of a chain.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_carries(const Block<T> *b0, const Block<T> *b1, const uint32_t *o0,
+                                                const uint32_t *o1, const uint64_t *state, int64_t N,
+                                                uint32_t rlog, uint32_t nq, int64_t *cb) {
+  const uint32_t R = blockIdx.x * NT + threadIdx.x;
+  if (R > nq) return;
+  const bool cur = state[ST_CUR] & 1ull;
+  cb[R] = carry_old(cur ? b1 : b0, cur ? o1 : o0, static_cast<int64_t>(R) << rlog, N);
 }
 
 // Merge of one quotient's old run [op, oe] with its new entries [ni, nj):
@@ -384,60 +399,60 @@ struct EndCursor {
   }
 };
 
-// Pass 1 over the lane's quotients [t0, t0 + QT): occ / chg are the chunk's
+// The lane's old run ends, in order, from a 128-bit window of the staged
+// run-end bits that starts after the end of the last old run before the chunk
+// (a lane's runs almost always fit; the others use EndCursor).
+struct WinEnds {
+  uint64_t cur, nxt;
+  int32_t base;
+  __device__ void init(const uint64_t *b, int32_t nw, int32_t from) {
+    const int32_t w = from >> 6, sh = from & 63;
+    const uint64_t b0 = w < nw ? b[w] : 0ull, b1 = w + 1 < nw ? b[w + 1] : 0ull,
+                   b2 = w + 2 < nw ? b[w + 2] : 0ull;
+    cur = sh ? (b0 >> sh) | (b1 << (64 - sh)) : b0;
+    nxt = sh ? (b1 >> sh) | (b2 << (64 - sh)) : b1;
+    base = from;
+    refill();
+  }
+  __device__ int count() const { return popc64(cur) + popc64(nxt); }
+  __device__ void refill() {
+    const bool empty = cur == 0;
+    cur = empty ? nxt : cur;
+    nxt = empty ? 0ull : nxt;
+    base = empty ? base + 64 : base;
+  }
+  __device__ int32_t pop(int32_t) {
+    const int32_t e = base + ctz64(cur);
+    cur &= cur - 1;
+    refill();
+    return e;
+  }
+};
+struct CurEnds {
+  EndCursor ec;
+  __device__ int32_t pop(int32_t o) { return ec.next(o); }
+};
+
+// One walk over the lane's quotients [t0, t0 + QT); occ / chg are the chunk's
 // old-occupied bits and its bits of quotients that receive new entries.
-// Unchanged runs keep their length and are composed into maps; the maps are
-// cut at every changed run, whose old extent is recorded for the merge:
-// first = the maps before the lane's first changed run, gaf[c] = those after
-// changed run c up to the next one (or the chunk's end).
-__device__ __forceinline__ void walk1(int32_t t0, uint32_t occ, uint32_t chg, int32_t ob, int32_t ope,
-                                      EndCursor &ec, uint32_t c, uint16_t *cop, uint16_t *coe, Fn32 *gaf,
-                                      Fn32 &first, uint32_t &used) {
+// Pass 1 (EMIT = false): unchanged runs keep their length and are composed
+// into maps, cut at every changed run, whose old extent is recorded for the
+// merge: first = the maps before the lane's first changed run, gaf[c] = those
+// after changed run c up to the next one (or the chunk's end).
+// Pass 2 (EMIT = true), from the lane's carry (relative end of all earlier
+// runs): copies unchanged runs to their new place, reserves the changed runs'
+// slots (cst), sets run-end bits (output buffers start zeroed, so gaps cost
+// nothing) and collects the chunk's new occupied bits.  Returns the carry
+// after quotient t0 (for the offset of a block starting there).
+template <bool EMIT, typename T, class Ends>
+__device__ __forceinline__ int32_t lane_walk(int32_t t0, uint32_t occ, uint32_t chg, int32_t ob, int32_t ope,
+                                             Ends ends, uint32_t c, uint16_t *cop, uint16_t *coe, Fn32 *gaf,
+                                             Fn32 &first, uint32_t &used, const uint32_t *cL, uint16_t *cst,
+                                             const T *old_s, T *new_s, uint64_t *new_b, int32_t xb,
+                                             int32_t carry, uint32_t &nocc) {
   uint32_t u = occ | chg;
   Fn32 G = f32_id();
   bool seen = false;
-  while (u) {
-    const int b = __builtin_ctz(u);
-    u &= u - 1;
-    const int32_t x = t0 + b;
-    int32_t o = 0, e = -1;
-    if ((occ >> b) & 1u) {
-      o = max(x - ob, ope + 1);
-      e = ec.next(o);
-      ope = e;
-    }
-    if ((chg >> b) & 1u) {
-      // staged indexes are < CAP < 0xFFFF, so 0xFFFF marks "no old run"
-      cop[c] = static_cast<uint16_t>(o);
-      coe[c] = e >= o ? static_cast<uint16_t>(e) : static_cast<uint16_t>(0xFFFF);
-      // (a value select, not a store through a pointer picked between LDS
-      // and the lane's own `first`)
-      first = seen ? first : G;
-      if (seen) gaf[c - 1] = G;
-      seen = true;
-      G = f32_id();
-      ++c;
-    } else {
-      const int32_t L = e - o + 1;
-      G = f32_then(G, Fn32{x + L - 1, L});
-      used += static_cast<uint32_t>(L);
-    }
-  }
-  first = seen ? first : G;
-  if (seen) gaf[c - 1] = G;
-}
-
-// Pass 2 over the same chunk, from the lane's carry (relative end of all
-// earlier runs): copies unchanged runs to their new place, reserves the
-// changed runs' slots (cst), sets run-end bits (output buffers start zeroed,
-// so gaps cost nothing) and collects the chunk's new occupied bits.  Returns
-// the carry after quotient t0 (for the offset of a block starting there).
-template <typename T>
-__device__ __forceinline__ int32_t walk2(int32_t t0, uint32_t occ, uint32_t chg, int32_t ob, int32_t ope,
-                                         EndCursor &ec, uint32_t c, const uint32_t *cL, uint16_t *cst,
-                                         const T *old_s, T *new_s, uint64_t *new_b, int32_t xb,
-                                         int32_t carry, uint32_t &nocc) {
-  uint32_t u = occ | chg;
   int32_t c_t0 = carry;
   int32_t cw = -1;
   uint64_t bits = 0;
@@ -445,35 +460,60 @@ __device__ __forceinline__ int32_t walk2(int32_t t0, uint32_t occ, uint32_t chg,
     const int b = __builtin_ctz(u);
     u &= u - 1;
     const int32_t x = t0 + b;
+    const bool ch = (chg >> b) & 1u;
     int32_t o = 0, e = -1;
     if ((occ >> b) & 1u) {
       o = max(x - ob, ope + 1);
-      e = ec.next(o);
+      e = ends.pop(o);
       ope = e;
     }
-    const bool ch = (chg >> b) & 1u;
-    const int32_t L = ch ? static_cast<int32_t>(cL[c]) : e - o + 1;
-    if (L > 0) {
-      const int32_t p = max(x, carry + 1) - xb;
+    if (!EMIT) {
       if (ch) {
-        cst[c] = static_cast<uint16_t>(p);
+        // staged indexes are < CAP < 0xFFFF, so 0xFFFF marks "no old run";
+        // `first` is a value select, not a store through a pointer picked
+        // between LDS and the lane's own variable
+        cop[c] = static_cast<uint16_t>(o);
+        coe[c] = e >= o ? static_cast<uint16_t>(e) : static_cast<uint16_t>(0xFFFF);
+        first = seen ? first : G;
+        if (seen) gaf[c - 1] = G;
+        seen = true;
+        G = f32_id();
+        ++c;
       } else {
-        for (int32_t k = 0; k < L; ++k) new_s[p + k] = old_s[o + k];
+        const int32_t L = e - o + 1;
+        G = f32_then(G, Fn32{x + L - 1, L});
+        used += static_cast<uint32_t>(L);
       }
-      const int32_t pe = p + L - 1;
-      carry = pe + xb;
-      if ((pe >> 6) != cw) {
-        if (bits) atomicOr(reinterpret_cast<ull *>(&new_b[cw]), static_cast<ull>(bits));
-        cw = pe >> 6;
-        bits = 0;
+    } else {
+      const int32_t L = ch ? static_cast<int32_t>(cL[c]) : e - o + 1;
+      if (L > 0) {
+        const int32_t p = max(x, carry + 1) - xb;
+        if (ch) {
+          cst[c] = static_cast<uint16_t>(p);
+        } else {
+          new_s[p] = old_s[o];
+          for (int32_t k = 1; k < L; ++k) new_s[p + k] = old_s[o + k];
+        }
+        const int32_t pe = p + L - 1;
+        carry = pe + xb;
+        if ((pe >> 6) != cw) {
+          if (bits) atomicOr(reinterpret_cast<ull *>(&new_b[cw]), static_cast<ull>(bits));
+          cw = pe >> 6;
+          bits = 0;
+        }
+        bits |= 1ull << (pe & 63);
+        nocc |= 1u << b;
       }
-      bits |= 1ull << (pe & 63);
-      nocc |= 1u << b;
+      if (ch) ++c;
+      c_t0 = b == 0 ? carry : c_t0;
     }
-    if (ch) ++c;
-    if (b == 0) c_t0 = carry;
   }
-  if (bits) atomicOr(reinterpret_cast<ull *>(&new_b[cw]), static_cast<ull>(bits));
+  if (!EMIT) {
+    first = seen ? first : G;
+    if (seen) gaf[c - 1] = G;
+  } else if (bits) {
+    atomicOr(reinterpret_cast<ull *>(&new_b[cw]), static_cast<ull>(bits));
+  }
   return c_t0;
 }
 
@@ -609,50 +649,89 @@ __device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t *sh) {
 }
 
 // Carry-in of region R (called by the 64 lanes of one wave): lane l looks at
-// region hi - l; the nearest region with a known inclusive carry ends the walk,
-// the aggregates of the regions in between are composed in order.  One memory
-// round trip covers 64 predecessors.
-__device__ int64_t look_back_wave(const uint64_t *tags, uint32_t nreg, uint32_t epoch, int64_t R) {
+// regions hi - 4l - k, k = 0..3; the nearest region with a known inclusive
+// carry ends the walk, the aggregates of the regions in between are composed
+// in order (per lane, then across the wave by an ordered tree).  One memory
+// round trip covers 256 predecessors.
+// Work-groups are dispatched in index order on each XCD, so a region's
+// predecessors have all started; the spin is still bounded: after LB_IDLE
+// consecutive rounds without progress the wave gives up, flags the batch
+// (which then is not applied) and returns a carry of -1.
+constexpr int LBK = 1;
+constexpr uint32_t LB_IDLE = 1u << 20;
+__device__ int64_t look_back_wave(const uint64_t *tags, uint32_t nreg, uint32_t epoch, int64_t R,
+                                  bool *stalled) {
   const int lane = threadIdx.x & 63;
   Fn acc = fn_id();  // regions (hi, R-1], applied in order
   int64_t hi = R - 1;
+  uint32_t idle = 0;
   for (;;) {
-    const int64_t j = hi - lane;
-    int kind = 0;  // 0 not ready, 1 aggregate, 2 inclusive, 3 before region 0
-    int64_t v = -1, A = -1, B = 0;
-    if (j < 0) {
-      kind = 3;
-    } else {
-      int64_t tv = 0, tA = 0, tB = 0;
-      const bool hv = tag_load(&tags[2ull * nreg + j], epoch, &tv);
-      const bool hA = tag_load(&tags[j], epoch, &tA);
-      const bool hB = tag_load(&tags[static_cast<uint64_t>(nreg) + j], epoch, &tB);
-      if (hv) {
-        kind = 2;
-        v = tv;
-      } else if (hA && hB) {
-        kind = 1;
-        A = tA;
-        B = tB;
+    Fn g[LBK];
+    int64_t v[LBK];
+    int first_inc = LBK, first_miss = LBK;  // within the lane, nearest first
+#pragma unroll
+    for (int k = LBK - 1; k >= 0; --k) {
+      const int64_t j = hi - LBK * lane - k;
+      g[k] = fn_id();
+      v[k] = -1;
+      if (j < 0) {
+        first_inc = k;  // before region 0 the carry is -1
+      } else {
+        int64_t tv = 0, tA = 0, tB = 0;
+        const bool hv = tag_load(&tags[2ull * nreg + j], epoch, &tv);
+        const bool hA = tag_load(&tags[j], epoch, &tA);
+        const bool hB = tag_load(&tags[static_cast<uint64_t>(nreg) + j], epoch, &tB);
+        if (hv) {
+          first_inc = k;
+          v[k] = tv;
+        } else if (hA && hB) {
+          g[k] = Fn{tA, tB};
+        } else {
+          first_miss = k;
+        }
       }
     }
-    const uint64_t stop_m = __ballot(kind >= 2);
-    const uint64_t miss_m = __ballot(kind == 0);
-    const int stop = stop_m ? ctz64(stop_m) : 64;
-    const int miss = miss_m ? ctz64(miss_m) : 64;
-    const int take = min(stop, miss);  // lanes [0, take) hold usable aggregates
-    for (int l = 0; l < take; ++l) {
-      Fn g;
-      g.A = __shfl(A, l);
-      g.B = __shfl(B, l);
-      acc = fn_then(g, acc);  // region hi - l is applied before the ones already in acc
+    const uint64_t im = __ballot(first_inc < LBK), mm = __ballot(first_miss < LBK);
+    const int il = im ? ctz64(im) : 0, ml = mm ? ctz64(mm) : 0;
+    const int fi = __shfl(first_inc, il), fm = __shfl(first_miss, ml);
+    const int stop = im ? LBK * il + fi : 64 * LBK;
+    const int miss = mm ? LBK * ml + fm : 64 * LBK;
+    const int take = min(stop, miss);  // positions [0, take) hold usable aggregates
+    // the lane's aggregates below `take`, farthest first
+    Fn M = fn_id();
+#pragma unroll
+    for (int k = LBK - 1; k >= 0; --k)
+      if (LBK * lane + k < take) M = fn_then(M, g[k]);
+    // ordered tree over the lanes: higher lanes hold earlier regions
+    for (int d = 1; d < 64; d <<= 1) {
+      Fn o;
+      o.A = __shfl_down(M.A, d);
+      o.B = __shfl_down(M.B, d);
+      if ((lane & (2 * d - 1)) == 0 && lane + d < 64) M = fn_then(o, M);
     }
-    if (stop < 64 && stop <= miss) {
-      const int64_t c = __shfl(v, stop);
+    Fn T;
+    T.A = __shfl(M.A, 0);
+    T.B = __shfl(M.B, 0);
+    acc = fn_then(T, acc);
+    if (stop < 64 * LBK && stop <= miss) {
+      const int k = stop % LBK;
+      int64_t vk = v[0];
+#pragma unroll
+      for (int q = 1; q < LBK; ++q)
+        if (k == q) vk = v[q];
+      const int64_t c = __shfl(vk, stop / LBK);
       return fn_apply(acc, c);
     }
     hi -= take;
-    if (take == 0) __builtin_amdgcn_s_sleep(2);
+    if (take == 0) {
+      if (++idle > LB_IDLE) {
+        *stalled = true;
+        return -1;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    } else {
+      idle = 0;
+    }
   }
 }
 
@@ -684,12 +763,9 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs<T> a) {
   __shared__ uint64_t sh_r[NT / 64];
 
   const int tid = threadIdx.x;
-  // tickets hand out regions in order, so every region's predecessors belong
-  // to running or finished work-groups (the look-back cannot wait on a
-  // work-group that has not started)
-  if (tid == 0) sh_i[0] = static_cast<int64_t>(atomic_add_u64(&a.state[ST_TILE], 1));
-  __syncthreads();
-  const int64_t R = sh_i[0];
+  // region = work-group index (no shared ticket counter: one atomic per
+  // work-group on one address serialises the whole launch)
+  const int64_t R = blockIdx.x;
   const int32_t S = 1 << a.rlog;
   const int64_t RS = R << a.rlog;
   // (selects, not a dynamic index into the argument struct, which would put
@@ -697,7 +773,6 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs<T> a) {
   const int cur = static_cast<int>(a.state[ST_CUR] & 1ull);
   const Block<T> *ob = cur ? a.blk[1] : a.blk[0];
   Block<T> *nbk = cur ? a.blk[0] : a.blk[1];
-  const uint32_t *ooff = cur ? a.off[1] : a.off[0];
   uint32_t *noff = cur ? a.off[0] : a.off[1];
   const bool qreg = RS < a.N;
   const int64_t send = min(RS + S, a.P);
@@ -713,10 +788,6 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs<T> a) {
   for (int w = tid; w < C::CAPW; w += NT) new_b[w] = 0ull;
   for (int i = tid; i < C::CAP * static_cast<int>(sizeof(T)) / 16; i += NT)
     reinterpret_cast<uint4 *>(new_s)[i] = make_uint4(0u, 0u, 0u, 0u);
-  if (qreg) {
-    if (tid == 0) sh_i[1] = carry_old(ob, ooff, RS, a.N);
-    if (tid == 64) sh_i[2] = carry_old(ob, ooff, RS + S, a.N);
-  }
   const bool new_lds = ne <= static_cast<uint64_t>(C::NCAP);
   if (new_lds) {
     const uint64_t rmask = (1ull << r) - 1ull;
@@ -727,8 +798,8 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs<T> a) {
     }
   }
   __syncthreads();
-  const int64_t lo_old = qreg ? sh_i[1] + 1 : RS;
-  const int64_t hi_old = qreg ? sh_i[2] : RS - 1;
+  const int64_t lo_old = qreg ? a.cb[R] + 1 : RS;
+  const int64_t hi_old = qreg ? a.cb[R + 1] : RS - 1;
   const bool has_old = hi_old >= lo_old;
   const int64_t bb = has_old ? (lo_old >> 6) : (RS >> 6);
   const int64_t nblk64 = has_old ? (hi_old >> 6) - bb + 1 : 0;
@@ -817,9 +888,19 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs<T> a) {
     Fn32 first = f32_id();
     uint32_t used = 0;
     if (chunk) {
-      EndCursor ec;
-      ec.init(old_b, nblk);
-      walk1(t0, occ_c, chg_c, obr, ope0, ec, c0, cop, coe, gaf, first, used);
+      uint32_t dn = 0;
+      T *dt = nullptr;
+      WinEnds we;
+      we.init(old_b, nblk, ope0 + 1);
+      if (we.count() >= __popc(occ_c)) {
+        lane_walk<false, T>(t0, occ_c, chg_c, obr, ope0, we, c0, cop, coe, gaf, first, used, cL, cst, old_s,
+                            dt, new_b, 0, 0, dn);
+      } else {
+        CurEnds ce;
+        ce.ec.init(old_b, nblk);
+        lane_walk<false, T>(t0, occ_c, chg_c, obr, ope0, ce, c0, cop, coe, gaf, first, used, cL, cst, old_s,
+                            dt, new_b, 0, 0, dn);
+      }
     }
     __syncthreads();
     // ---- pass 1a: new lengths of the changed runs, one run per lane --------
@@ -866,8 +947,10 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs<T> a) {
     tag_store(&a.tags[static_cast<uint64_t>(a.nregions) + R], a.epoch, Ftot.B);
   }
   if (tid < 64) {
-    const int64_t c_in = look_back_wave(a.tags, a.nregions, a.epoch, R);
+    bool stalled = false;
+    const int64_t c_in = look_back_wave(a.tags, a.nregions, a.epoch, R, &stalled);
     if (tid == 0) {
+      if (stalled) atomic_or_u64(&a.state[ST_BATCH], BATCH_STALL);
       const int64_t c_out = fn_apply(Ftot, c_in);
       tag_store(&a.tags[2ull * a.nregions + R], a.epoch, c_out);
       sh_i[3] = c_in;
@@ -902,10 +985,20 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs<T> a) {
     if (chunk) {
       const int64_t c_t = fn_apply(Fex, c_in);
       const int32_t carry = static_cast<int32_t>(max(c_t - RS, static_cast<int64_t>(-1)));
-      EndCursor ec;
-      ec.init(old_b, nblk);
-      const int32_t ct0 = walk2<T>(t0, occ_c, chg_c, obr, ope0, ec, c0, cL, cst, old_s, new_s, new_b, xb,
-                                   carry, nocc);
+      Fn32 df = f32_id();
+      uint32_t du = 0;
+      int32_t ct0;
+      WinEnds we;
+      we.init(old_b, nblk, ope0 + 1);
+      if (we.count() >= __popc(occ_c)) {
+        ct0 = lane_walk<true, T>(t0, occ_c, chg_c, obr, ope0, we, c0, cop, coe, gaf, df, du, cL, cst, old_s,
+                                 new_s, new_b, xb, carry, nocc);
+      } else {
+        CurEnds ce;
+        ce.ec.init(old_b, nblk);
+        ct0 = lane_walk<true, T>(t0, occ_c, chg_c, obr, ope0, ce, c0, cop, coe, gaf, df, du, cL, cst, old_s,
+                                 new_s, new_b, xb, carry, nocc);
+      }
       if ((t0 & 63) == 0) noff[(RS + t0) >> 6] = static_cast<uint32_t>(max(ct0 - t0, 0));
     }
     if (qreg) {
@@ -999,7 +1092,9 @@ __global__ __launch_bounds__(1024) void k_finish(uint64_t *state, const uint64_t
       state[ST_TOTAL] += t[2];
       state[ST_CUR] ^= 1ull;
     } else if (state[ST_ERR] == 0) {
-      state[ST_ERR] = static_cast<uint64_t>((st & BATCH_FULL) ? -2 : -5);
+      state[ST_ERR] = static_cast<uint64_t>((st & BATCH_STALL) ? QF_ERR_STALLED
+                                            : (st & BATCH_FULL) ? QF_ERR_FULL
+                                                                : QF_ERR_COUNT_OVERFLOW);
     }
     if (del) *not_found += t[3];
     state[ST_BATCHES] += 1;
@@ -1029,7 +1124,10 @@ hipError_t launch_merge_t(qf_filter *f, const uint64_t *ufp, const uint64_t *ucn
   a.del = del;
   a.not_found = not_found ? not_found : f->state + ST_SCRATCH;
   a.rstat = f->rstat;
+  a.cb = f->cb;
   if (f->timer) f->timer->begin(QF_PROF_MERGE, s);
+  k_carries<T><<<(f->nqregions + 1 + NT - 1) / NT, NT, 0, s>>>(a.blk[0], a.blk[1], a.off[0], a.off[1], f->state,
+                                                             a.N, f->rlog, f->nqregions, f->cb);
   k_merge<T><<<f->nregions, NT, 0, s>>>(a);
   k_finish<<<1, 1024, 0, s>>>(f->state, f->rstat, f->nregions, del, a.not_found);
   if (f->timer) f->timer->end(QF_PROF_MERGE, s);

@@ -24,12 +24,14 @@ QF_ERR_FULL = -2
 QF_ERR_OOM = -3
 QF_ERR_DEVICE = -4
 QF_ERR_COUNT_OVERFLOW = -5
+QF_ERR_STALLED = -6
 ERRORS = {
     QF_ERR_ARG: "QF_ERR_ARG",
     QF_ERR_FULL: "QF_ERR_FULL",
     QF_ERR_OOM: "QF_ERR_OOM",
     QF_ERR_DEVICE: "QF_ERR_DEVICE",
     QF_ERR_COUNT_OVERFLOW: "QF_ERR_COUNT_OVERFLOW",
+    QF_ERR_STALLED: "QF_ERR_STALLED",
 }
 
 
