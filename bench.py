@@ -68,6 +68,25 @@ def algorithmic_bytes(kind: str, w, consts: dict | None, lookup_count_share: flo
     return None
 
 
+def measured_traffic(kernel: str) -> float | None:
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None when
+    the kernel's source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_q28_r8_load0.9_batch2p22.md")
+    if not os.path.exists(path):
+        return None
+    line = next((l for l in open(path) if l.startswith("traffic-json:")), None)
+    if line is None:
+        return None
+    rec = json.loads(line.split(":", 1)[1]).get(kernel)
+    if rec is None:
+        return None
+    src = os.path.join(ROOT, "paper_2212_09005_amd", "csrc", rec["src"])
+    if hashlib.sha1(open(src, "rb").read()).hexdigest() != rec["sha1"]:
+        return None
+    return float(rec["bytes"])
+
+
 def cpu_baseline(w, budget_s: float = 20.0) -> dict:
     """The CPU oracle (single thread) on the same step at a smaller table with
     the same load and the same batch-to-table ratio."""
@@ -120,6 +139,9 @@ def main() -> int:
     ap.add_argument("--load", type=float, default=0.9)
     ap.add_argument("--batch-log2", type=int, default=22)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one plain device-to-device copy of this many MiB before the fill, as the "
+                         "reference kernel for HBM byte counters (FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the filter's multi-GPU sharding is a "
@@ -134,6 +156,15 @@ def main() -> int:
     w = LoadSweep(q=args.q, load=args.load, batch=1 << args.batch_log2)
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration_mib:
+        nb = args.copy_calibration_mib << 20
+        src = torch.ones(nb // 8, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {nb} bytes device to device (counter calibration)")
+        del src, dst
     log(f"workload: {w.name()}")
 
     t0 = time.time()
@@ -224,8 +255,9 @@ def main() -> int:
     rk = dom if dom in timed else max(timed, key=lambda k: timed[k]["ms_total"]) if timed else None
     roofline = None
     if rk is not None:
+        traffic = (measured_traffic("k_" + rk) if (w.q, w.r, w.load, w.batch) == (28, 8, 0.9, 1 << 22) else None)
         roofline = {"kernel": rk, "bound": "hbm", "achieved": kinds[rk]["alg_GBs"], "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": kinds[rk]["frac"], "traffic": None,
+                    "unit": "GB/s", "frac": kinds[rk]["frac"], "traffic": traffic,
                     "time_share": round(kinds[rk]["ms_total"] / sum(v["ms_total"] for v in kinds.values()), 3)}
     out = {
         "metric": METRIC,
