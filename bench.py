@@ -130,6 +130,123 @@ def cpu_baseline(w, budget_s: float = 20.0) -> dict:
     }
 
 
+def bench_sets(args) -> dict:
+    """Many filters (4096, 2^10..2^20 quotients, r = 8): fill each to load 0.85, then query 2^24 keys
+    spread over the filters in proportion to their size (half present, half absent).  The same work
+    runs through one filter set (one pipeline of launches for all filters) and through a plain loop
+    of per-filter calls on the same GPU; the tables must come out identical."""
+    import torch
+
+    from paper_2212_09005_amd import inputs, qf
+
+    rng = np.random.Generator(np.random.PCG64(5))
+    nf = args.sets_filters
+    qs = rng.integers(10, 21, size=nf)
+    fill_n = np.array([int(0.85 * (1 << int(q))) for q in qs], dtype=np.int64)
+    off = np.concatenate([[0], np.cumsum(fill_n)])
+    total = int(off[-1])
+    log(f"c4: {nf} filters, {total} fill keys, {int(sum(1 << int(q) for q in qs))} quotients")
+    keys = inputs.uniform_keys(5, total)
+    fid = np.repeat(np.arange(nf, dtype=np.int32), fill_n)
+    d_keys = torch.from_numpy(keys.view(np.int64)).to("cuda")
+    d_fid = torch.from_numpy(fid).to("cuda")
+    # queries: filter drawn in proportion to 2^q, half present, half absent
+    m = 1 << args.sets_query_log2
+    w = np.array([2.0 ** int(q) for q in qs])
+    qfid = rng.choice(nf, size=m, p=w / w.sum()).astype(np.int32)
+    present = rng.random(m) < 0.5
+    qkeys = inputs.absent_keys(6, m)
+    pidx = off[qfid] + (rng.random(m) * fill_n[qfid]).astype(np.int64)
+    qkeys[present] = keys[pidx[present]]
+    d_qkeys = torch.from_numpy(qkeys.view(np.int64)).to("cuda")
+    d_qfid = torch.from_numpy(qfid).to("cuda")
+    # the per-filter loop gets its queries already grouped by filter (untimed)
+    order = np.argsort(qfid, kind="stable")
+    qoff = np.concatenate([[0], np.cumsum(np.bincount(qfid, minlength=nf))])
+    d_qkeys_grouped = torch.from_numpy(qkeys[order].view(np.int64)).to("cuda")
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    sample = sorted(set(rng.integers(0, nf, size=8).tolist()) | {int(np.argmax(qs)), int(np.argmin(qs))})
+    # the set (scratch reserved beforehand, so no allocation is timed)
+    fs_set = [qf.CQF(int(q), 8) for q in qs]
+    st = qf.CQFSet(fs_set)
+    st.reserve(total)
+    t_set_fill = timed(lambda: st.insert(d_fid, d_keys))
+    assert st.sync() == 0
+    out_set = torch.empty(m, dtype=torch.uint8, device="cuda")
+    st.query(d_qfid, d_qkeys, out_set)  # warm-up
+    t_set_query = timed(lambda: st.query(d_qfid, d_qkeys, out_set))
+    got_set = out_set.cpu().numpy()
+    lay_set = {i: fs_set[i].export() for i in sample}
+    st.close()
+    for f in fs_set:
+        f.close()
+    del fs_set, st
+    log(f"c4 set: fill {t_set_fill:.3f}s, query {t_set_query * 1e3:.2f} ms")
+    # the loop of per-filter calls (scratch reserved beforehand)
+    fs_loop = [qf.CQF(int(q), 8) for q in qs]
+    for i, f in enumerate(fs_loop):
+        f.reserve(int(fill_n[i]))
+
+    def loop_fill():
+        for i, f in enumerate(fs_loop):
+            f.insert(d_keys[int(off[i]):int(off[i + 1])])
+
+    t_loop_fill = timed(loop_fill)
+    out_loop = torch.empty(m, dtype=torch.uint8, device="cuda")
+
+    def loop_query():
+        for i, f in enumerate(fs_loop):
+            a, b = int(qoff[i]), int(qoff[i + 1])
+            if b > a:
+                f.query(d_qkeys_grouped[a:b], out_loop[a:b])
+
+    loop_query()  # warm-up
+    t_loop_query = timed(loop_query)
+    for f in fs_loop:
+        assert f.sync() == 0
+    log(f"c4 loop: fill {t_loop_fill:.3f}s, query {t_loop_query * 1e3:.2f} ms")
+    # same answers, same tables (a sample of filters, every size)
+    got_loop = np.empty(m, np.uint8)
+    got_loop[order] = out_loop.cpu().numpy()
+    assert np.array_equal(got_set, got_loop), "set and loop answers differ"
+    assert got_set[present].all(), "a present key was not found"
+    for i in sample:
+        rc1, l1 = lay_set[i]
+        rc2, l2 = fs_loop[i].export()
+        assert rc1 == 0 and rc2 == 0
+        for name in ("occ_words", "runend_words", "slots", "offsets", "header"):
+            assert np.array_equal(getattr(l1, name), getattr(l2, name)), f"filter {i}: {name} differs"
+    fp_rate = float(got_set[~present].mean())
+    for f in fs_loop:
+        f.close()
+    res = {
+        "metric": "filter-set fill and query throughput (4096 filters of 2^10..2^20 quotients, r=8, load 0.85)",
+        "value": round(total / t_set_fill / 1e9, 4),
+        "unit": "B inserts/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"c4_sets_{nf}filters_q10to20_r8_load0.85", "filters": nf, "fill_keys": total,
+                   "queries": m},
+        "set": {"fill_s": round(t_set_fill, 4), "fill_Bps": round(total / t_set_fill / 1e9, 4),
+                "query_ms": round(t_set_query * 1e3, 3), "query_Bps": round(m / t_set_query / 1e9, 4)},
+        "loop": {"fill_s": round(t_loop_fill, 4), "fill_Bps": round(total / t_loop_fill / 1e9, 4),
+                 "query_ms": round(t_loop_query * 1e3, 3), "query_Bps": round(m / t_loop_query / 1e9, 4)},
+        "speedup": {"fill": round(t_loop_fill / t_set_fill, 2), "query": round(t_loop_query / t_set_query, 2)},
+        "absent_positive_rate": round(fp_rate, 6),
+    }
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,6 +256,10 @@ def main() -> int:
     ap.add_argument("--load", type=float, default=0.9)
     ap.add_argument("--batch-log2", type=int, default=22)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["c2", "c4"], default="c2",
+                    help="c2: the single-filter step (default); c4: many filters, set vs per-filter loop")
+    ap.add_argument("--sets-filters", type=int, default=4096)
+    ap.add_argument("--sets-query-log2", type=int, default=24)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this many MiB before the fill, as the "
                          "reference kernel for HBM byte counters (FETCH_SIZE / WRITE_SIZE)")
@@ -152,6 +273,12 @@ def main() -> int:
 
     from paper_2212_09005_amd import qf
     from paper_2212_09005_amd.workloads import LoadSweep
+
+    if args.workload == "c4":
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
+        torch.cuda.set_device(0)
+        print(json.dumps(bench_sets(args)), flush=True)
+        return 0
 
     w = LoadSweep(q=args.q, load=args.load, batch=1 << args.batch_log2)
     assert torch.cuda.is_available(), "bench.py needs a GPU"

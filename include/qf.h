@@ -119,6 +119,11 @@ int qf_import(qf_t *f, const qf_layout_t *in, void *stream);
 /* Error code of the last failed call in this thread. */
 int qf_last_error(void);
 
+/* Grows the filter's scratch area (grow-only, 64 bytes per key) to hold
+ * batches of n keys, so that later calls with batches up to n allocate
+ * nothing.  May wait for `stream` when the area grows. */
+int qf_reserve(qf_t *f, uint64_t n, void *stream);
+
 /* Device bytes of one table copy of a (q, r) filter (blocks + offsets). */
 uint64_t qf_table_bytes(uint32_t q, uint32_t r);
 
@@ -145,6 +150,48 @@ enum {
 };
 int qf_profile_enable(qf_t *f, int enable);
 int qf_profile_read(qf_t *f, double *ms, uint64_t *n);
+
+/* ---- filter sets: many filters, one pipeline of launches ------------------
+ * A set groups nf existing filters with the same r (sizes may differ) so that
+ * one batch of keys, each tagged with the index of its filter in the set,
+ * is hashed, sorted, reduced and merged into all of them by one sequence of
+ * launches (one merge launch covers every region of every filter), and one
+ * lookup launch answers a mixed query batch.  Per filter the effect is that
+ * of the single-filter call on the keys tagged with it, in batch order
+ * (Sec. 5.3-5.4 and 6.2 per filter; grouping many filters in one launch is
+ * this library's design for workloads of thousands of small filters, where
+ * a loop of per-filter calls is bound by launch count).
+ * Conventions: d_fid (device, n uint32) holds each key's filter index in
+ * [0, nf); an index out of range drops that key (a lookup returns 0 for it)
+ * and makes qf_set_sync return QF_ERR_ARG.  Errors of a filter (FULL,
+ * COUNT_OVERFLOW) are all-or-nothing for that filter's share of the batch
+ * and surface at qf_set_sync (or qf_sync of that filter).  The set does not
+ * own its filters; they must outlive it, and per-filter calls must be stream
+ * ordered with set calls.  qf_set_create is synchronous and fails with
+ * QF_ERR_ARG for nf == 0, a NULL filter, mixed r, or more than 2^31 regions. */
+typedef struct qf_set qf_set_t;
+qf_set_t *qf_set_create(qf_t *const *filters, uint32_t nf);
+void qf_set_destroy(qf_set_t *s); /* NULL-safe; waits for the device */
+int qf_set_insert_batch(qf_set_t *s, const uint32_t *d_fid, const uint64_t *d_keys, uint64_t n,
+                        void *stream);
+/* d_not_found: device, nf uint64 (the shortfall of filter i is ADDED to
+ * d_not_found[i]), or NULL. */
+int qf_set_delete_batch(qf_set_t *s, const uint32_t *d_fid, const uint64_t *d_keys, uint64_t n,
+                        uint64_t *d_not_found, void *stream);
+int qf_set_query_batch(qf_set_t *s, const uint32_t *d_fid, const uint64_t *d_keys, uint64_t n,
+                       uint8_t *d_out, void *stream);
+int qf_set_count_batch(qf_set_t *s, const uint32_t *d_fid, const uint64_t *d_keys, uint64_t n,
+                       uint64_t *d_out, void *stream);
+/* Waits for `stream`; returns (and clears) the set's own deferred error, else
+ * the first deferred error of its filters (all of them are cleared). */
+int qf_set_sync(qf_set_t *s, void *stream);
+/* qf_reserve for the set's pipeline. */
+int qf_set_reserve(qf_set_t *s, uint64_t n, void *stream);
+/* info[0..7] = nf, r, total regions, largest region log2, device bytes held by
+ * the set's pipeline, batches run, bits of the composite sort key, 0. */
+int qf_set_info(const qf_set_t *s, uint64_t *info);
+int qf_set_profile_enable(qf_set_t *s, int enable);
+int qf_set_profile_read(qf_set_t *s, double *ms, uint64_t *n);
 
 #ifdef __cplusplus
 }

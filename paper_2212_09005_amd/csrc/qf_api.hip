@@ -55,30 +55,146 @@ uint64_t extra_slots(uint32_t q) {
   return (e + 63) / 64 * 64;
 }
 
-void free_scratch(qf_filter *f) {
-  (void)hipFree(f->bufA);
-  (void)hipFree(f->bufB);
-  (void)hipFree(f->bufC);
-  (void)hipFree(f->bufD);
-  f->bufA = f->bufB = f->bufC = f->bufD = nullptr;
-  f->cap = 0;
+void free_scratch(qf::Pipe &p) {
+  (void)hipFree(p.bufA);
+  (void)hipFree(p.bufB);
+  (void)hipFree(p.bufC);
+  (void)hipFree(p.bufD);
+  (void)hipFree(p.bufE);
+  p.bufA = p.bufB = p.bufC = p.bufD = p.bufE = nullptr;
+  p.cap = 0;
 }
 
-int ensure_scratch(qf_filter *f, uint64_t n, hipStream_t s) {
-  if (n <= f->cap) return QF_OK;
+int ensure_scratch(qf::Pipe &p, uint64_t n, hipStream_t s) {
+  if (n <= p.cap) return QF_OK;
   uint64_t cap = 1ull << 16;
   while (cap < n) cap <<= 1;
-  if (f->cap) QF_HIP(hipStreamSynchronize(s));
-  f->device_bytes -= 4 * f->cap * sizeof(uint64_t);
-  free_scratch(f);
+  if (p.cap) QF_HIP(hipStreamSynchronize(s));
+  p.device_bytes -= 8 * p.cap * sizeof(uint64_t);
+  free_scratch(p);
   const size_t bytes = cap * sizeof(uint64_t);
-  if (hipMalloc(&f->bufA, bytes) != hipSuccess || hipMalloc(&f->bufB, bytes) != hipSuccess ||
-      hipMalloc(&f->bufC, bytes) != hipSuccess || hipMalloc(&f->bufD, bytes) != hipSuccess) {
-    free_scratch(f);
+  if (hipMalloc(&p.bufA, bytes) != hipSuccess || hipMalloc(&p.bufB, bytes) != hipSuccess ||
+      hipMalloc(&p.bufC, bytes) != hipSuccess || hipMalloc(&p.bufD, bytes) != hipSuccess ||
+      hipMalloc(&p.bufE, 4 * bytes) != hipSuccess) {
+    free_scratch(p);
     return fail(QF_ERR_OOM);
   }
-  f->cap = cap;
-  f->device_bytes += 4 * bytes;
+  p.cap = cap;
+  p.device_bytes += 8 * bytes;
+  return QF_OK;
+}
+
+void pipe_free(qf::Pipe &p) {
+  (void)hipFree(p.d_desc);
+  (void)hipFree(p.d_rmap);
+  (void)hipFree(p.rb);
+  (void)hipFree(p.tags);
+  (void)hipFree(p.pst);
+  (void)hipFree(p.hist);
+  free_scratch(p);
+  delete p.timer;
+  p = qf::Pipe();
+}
+
+qf::FDesc desc_of(const qf_filter *f, uint32_t rbase) {
+  qf::FDesc d;
+  std::memset(&d, 0, sizeof(d));
+  d.blk[0] = f->blk[0];
+  d.blk[1] = f->blk[1];
+  d.off[0] = f->off[0];
+  d.off[1] = f->off[1];
+  d.state = f->state;
+  d.N = static_cast<int64_t>(f->N);
+  d.P = static_cast<int64_t>(f->P);
+  d.nblocks = static_cast<int64_t>(f->nblocks);
+  d.q = f->q;
+  d.r = f->r;
+  d.rlog = f->rlog;
+  d.nregions = f->nregions;
+  d.nqregions = f->nqregions;
+  d.rbase = rbase;
+  return d;
+}
+
+uint32_t bits_for(uint64_t v) {  // bits of the values 0..v
+  uint32_t b = 0;
+  while ((1ull << b) <= v) ++b;
+  return b;
+}
+
+// The update pipeline of nf filters (same r): descriptors, region map, bounds,
+// look-back words, statistics, old carries, histograms.  Synchronous.
+int pipe_init(qf::Pipe &p, qf_filter *const *fs, uint32_t nf) {
+  p = qf::Pipe();
+  p.nf = nf;
+  p.r = fs[0]->r;
+  (void)hipGetDevice(&p.device);
+  std::vector<qf::FDesc> desc(nf);
+  uint64_t G = 0;
+  for (uint32_t i = 0; i < nf; ++i) {
+    if (fs[i]->r != p.r) return fail(QF_ERR_ARG);
+    p.RL = std::max(p.RL, fs[i]->rlog);
+    desc[i] = desc_of(fs[i], static_cast<uint32_t>(G));
+    G += fs[i]->nregions;
+  }
+  if (G >= (1ull << 31)) return fail(QF_ERR_ARG);
+  p.G = static_cast<uint32_t>(G);
+  // region indices 0..G-1 stay below 2^gbits - 1, so no valid composite key
+  // shares its sorted bits with the all-ones key of a dropped (bad index) key
+  p.gbits = bits_for(G);
+  if (nf > 1 && p.gbits + p.RL + p.r > 62) return fail(QF_ERR_ARG);
+  std::vector<uint32_t> rmap(G);
+  for (uint32_t i = 0; i < nf; ++i)
+    for (uint32_t k = 0; k < fs[i]->nregions; ++k) rmap[desc[i].rbase + k] = i;
+  p.hist_words = 256ull * 1024ull + 256ull * 8;  // histograms + per-pass digit totals
+  const uint64_t tag_words = 8ull * G + 8;        // 3 G tags, 4 G statistics, G carries
+  bool ok = hipMalloc(reinterpret_cast<void **>(&p.d_desc), nf * sizeof(qf::FDesc)) == hipSuccess &&
+            hipMalloc(reinterpret_cast<void **>(&p.d_rmap), G * sizeof(uint32_t)) == hipSuccess &&
+            hipMalloc(reinterpret_cast<void **>(&p.rb), (G + 1) * sizeof(uint64_t)) == hipSuccess &&
+            hipMalloc(reinterpret_cast<void **>(&p.tags), tag_words * sizeof(uint64_t)) == hipSuccess &&
+            hipMalloc(reinterpret_cast<void **>(&p.pst), qf::ST_WORDS * sizeof(uint64_t)) == hipSuccess &&
+            hipMalloc(reinterpret_cast<void **>(&p.hist), p.hist_words * sizeof(uint32_t)) == hipSuccess;
+  ok = ok && hipMemcpy(p.d_desc, desc.data(), nf * sizeof(qf::FDesc), hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(p.d_rmap, rmap.data(), G * sizeof(uint32_t), hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemset(p.tags, 0, tag_words * sizeof(uint64_t)) == hipSuccess &&
+       hipMemset(p.pst, 0, qf::ST_WORDS * sizeof(uint64_t)) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+  if (!ok) {
+    pipe_free(p);
+    return fail(QF_ERR_OOM);
+  }
+  p.rstat = p.tags + 3ull * G;
+  p.cb = reinterpret_cast<int64_t *>(p.tags + 7ull * G);
+  p.device_bytes = nf * sizeof(qf::FDesc) + G * 4 + (G + 1) * 8 + tag_words * 8 + qf::ST_WORDS * 8 +
+                   p.hist_words * 4;
+  return QF_OK;
+}
+
+// hash -> radix sort -> reduction -> region bounds -> merge, on stream s.
+// fid == nullptr: the pipeline has one filter and keys are its own.
+int pipe_update(qf::Pipe &p, const uint64_t *keys, const uint32_t *fid, uint64_t n, int del,
+                uint64_t *not_found, hipStream_t s, uint32_t single_q) {
+  int rc = ensure_scratch(p, n, s);
+  if (rc) return rc;
+  uint32_t bits;
+  if (fid) {
+    QF_HIP(qf::launch_hash_multi(keys, fid, n, p, p.bufA, s, p.timer));
+    bits = p.gbits + p.RL + p.r;
+  } else {
+    // one filter: its composite key is the fingerprint itself
+    bits = single_q + p.r;
+    const uint64_t pmask = bits >= 64 ? ~0ull : ((1ull << bits) - 1ull);
+    QF_HIP(qf::launch_hash(keys, n, pmask, p.bufA, s, p.timer));
+  }
+  uint64_t *sorted = nullptr;
+  QF_HIP(qf::launch_sort(p.bufA, p.bufB, n, bits, p.hist, &sorted, s, p.timer));
+  uint64_t *other = sorted == p.bufA ? p.bufB : p.bufA;
+  QF_HIP(qf::launch_rle(sorted, n, other, p.bufC, p.bufD, p.hist, p.pst, s, p.timer));
+  QF_HIP(qf::launch_bounds(p.bufC, p, s));
+  const bool wrap = p.epoch == 65535;
+  if (wrap) p.epoch = 0;
+  p.epoch += 1;
+  QF_HIP(qf::launch_merge(p, p.bufC, p.bufD, del, not_found, wrap, s));
+  p.batches += 1;
   return QF_OK;
 }
 
@@ -89,25 +205,7 @@ int update(qf_filter *f, const uint64_t *keys, uint64_t n, int del, uint64_t *no
   if (!f || (n && !keys)) return fail(QF_ERR_ARG);
   if (n == 0) return QF_OK;
   if (n > 0xFFFFFFFFull) return fail(QF_ERR_ARG);
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  int rc = ensure_scratch(f, n, s);
-  if (rc) return rc;
-  const uint32_t p = f->q + f->r;
-  const uint64_t pmask = p >= 64 ? ~0ull : ((1ull << p) - 1ull);
-  QF_HIP(qf::launch_hash(keys, n, pmask, f->bufA, s, f->timer));
-  uint64_t *sorted = nullptr;
-  QF_HIP(qf::launch_sort(f->bufA, f->bufB, n, p, f->hist, &sorted, s, f->timer));
-  uint64_t *other = sorted == f->bufA ? f->bufB : f->bufA;
-  QF_HIP(qf::launch_rle(sorted, n, other, f->bufC, f->bufD, f->hist, f->state, s, f->timer));
-  QF_HIP(qf::launch_bounds(f->bufC, f->state, f, s));
-  if (f->epoch == 65535) {
-    QF_HIP(qf::launch_fill_u64(f->tags, 3ull * f->nregions, 0, s));
-    f->epoch = 0;
-  }
-  f->epoch += 1;
-  QF_HIP(qf::launch_merge(f, f->bufC, f->bufD, del, not_found, s));
-  f->batches += 1;
-  return QF_OK;
+  return pipe_update(f->pipe, keys, nullptr, n, del, not_found, static_cast<hipStream_t>(stream), f->q);
 }
 
 int read_clear_error(qf_filter *f) {
@@ -172,6 +270,36 @@ struct EventTimer : qf::Timer {
   }
 };
 
+int profile_enable(qf::Pipe &p, int enable) {
+  if (enable && !p.timer) p.timer = new (std::nothrow) EventTimer();
+  if (enable && !p.timer) return fail(QF_ERR_OOM);
+  if (!enable && p.timer) {
+    (void)static_cast<EventTimer *>(p.timer)->collect();
+    delete p.timer;
+    p.timer = nullptr;
+  }
+  return QF_OK;
+}
+
+int profile_read(qf::Pipe &p, double *ms, uint64_t *n) {
+  if (!p.timer) {
+    for (int k = 0; k < QF_PROF_KINDS; ++k) {
+      ms[k] = 0.0;
+      n[k] = 0;
+    }
+    return QF_OK;
+  }
+  EventTimer *t = static_cast<EventTimer *>(p.timer);
+  const int rc = t->collect();
+  for (int k = 0; k < QF_PROF_KINDS; ++k) {
+    ms[k] = t->ms[k];
+    n[k] = t->n[k];
+    t->ms[k] = 0.0;
+    t->n[k] = 0;
+  }
+  return rc ? fail(rc) : QF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -181,12 +309,11 @@ qf_t *qf_create(uint32_t q, uint32_t r) {
     fail(QF_ERR_ARG);
     return nullptr;
   }
-  qf_filter *f = new (std::nothrow) qf_filter();
+  qf_filter *f = new (std::nothrow) qf_filter();  // value-initialised: all zero
   if (!f) {
     fail(QF_ERR_OOM);
     return nullptr;
   }
-  std::memset(f, 0, sizeof(*f));
   f->q = q;
   f->r = r;
   f->N = 1ull << q;
@@ -208,23 +335,20 @@ qf_t *qf_create(uint32_t q, uint32_t r) {
            hipMemset(f->off[c], 0, f->nblocks * sizeof(uint32_t)) == hipSuccess;
     }
   }
-  f->hist_words = 256ull * 1024ull + 256ull * 8;  // histograms + per-pass digit totals
   ok = ok && hipMalloc(reinterpret_cast<void **>(&f->state), qf::ST_WORDS * sizeof(uint64_t)) == hipSuccess &&
-       hipMalloc(reinterpret_cast<void **>(&f->rb), (f->nregions + 1ull) * sizeof(uint64_t)) == hipSuccess &&
-       hipMalloc(reinterpret_cast<void **>(&f->tags), (8ull * f->nregions + 8) * sizeof(uint64_t)) == hipSuccess &&
-       hipMalloc(reinterpret_cast<void **>(&f->hist), f->hist_words * sizeof(uint32_t)) == hipSuccess;
-  ok = ok && hipMemset(f->state, 0, qf::ST_WORDS * sizeof(uint64_t)) == hipSuccess &&
-       hipMemset(f->tags, 0, (8ull * f->nregions + 8) * sizeof(uint64_t)) == hipSuccess &&
-       hipDeviceSynchronize() == hipSuccess;
+       hipMemset(f->state, 0, qf::ST_WORDS * sizeof(uint64_t)) == hipSuccess;
   if (!ok) {
     qf_destroy(f);
     fail(QF_ERR_OOM);
     return nullptr;
   }
-  f->rstat = f->tags + 3ull * f->nregions;
-  f->cb = reinterpret_cast<int64_t *>(f->tags + 7ull * f->nregions);
-  f->device_bytes = 2 * qf::table_bytes(f->nblocks, r) + qf::ST_WORDS * 8 + (f->nregions + 1ull) * 8 +
-                    (8ull * f->nregions + 8) * 8 + f->hist_words * 4;
+  qf_filter *self[1] = {f};
+  if (pipe_init(f->pipe, self, 1) != QF_OK) {
+    qf_destroy(f);
+    fail(QF_ERR_OOM);
+    return nullptr;
+  }
+  f->table_device_bytes = 2 * qf::table_bytes(f->nblocks, r) + qf::ST_WORDS * 8;
   return f;
 }
 
@@ -236,11 +360,7 @@ void qf_destroy(qf_t *f) {
     (void)hipFree(f->off[c]);
   }
   (void)hipFree(f->state);
-  (void)hipFree(f->rb);
-  (void)hipFree(f->tags);
-  (void)hipFree(f->hist);
-  free_scratch(f);
-  delete f->timer;
+  pipe_free(f->pipe);
   delete f;
 }
 
@@ -362,6 +482,133 @@ int qf_import(qf_t *f, const qf_layout_t *in, void *stream) {
 
 int qf_last_error(void) { return g_last_error; }
 
+int qf_reserve(qf_t *f, uint64_t n, void *stream) {
+  if (!f || n > 0xFFFFFFFFull) return fail(QF_ERR_ARG);
+  return ensure_scratch(f->pipe, n, static_cast<hipStream_t>(stream));
+}
+
+int qf_set_reserve(qf_set_t *st, uint64_t n, void *stream) {
+  if (!st || n > 0xFFFFFFFFull) return fail(QF_ERR_ARG);
+  return ensure_scratch(st->pipe, n, static_cast<hipStream_t>(stream));
+}
+
+qf_set_t *qf_set_create(qf_t *const *filters, uint32_t nf) {
+  if (!filters || nf == 0) {
+    fail(QF_ERR_ARG);
+    return nullptr;
+  }
+  for (uint32_t i = 0; i < nf; ++i) {
+    if (!filters[i] || filters[i]->r != filters[0]->r) {
+      fail(QF_ERR_ARG);
+      return nullptr;
+    }
+  }
+  qf_set *st = new (std::nothrow) qf_set();
+  if (!st) {
+    fail(QF_ERR_OOM);
+    return nullptr;
+  }
+  st->nf = nf;
+  st->fs = new (std::nothrow) qf_filter *[nf];
+  if (!st->fs) {
+    delete st;
+    fail(QF_ERR_OOM);
+    return nullptr;
+  }
+  for (uint32_t i = 0; i < nf; ++i) st->fs[i] = filters[i];
+  const int rc = pipe_init(st->pipe, st->fs, nf);
+  if (rc != QF_OK) {
+    delete[] st->fs;
+    delete st;
+    fail(rc);
+    return nullptr;
+  }
+  return st;
+}
+
+void qf_set_destroy(qf_set_t *st) {
+  if (!st) return;
+  (void)hipDeviceSynchronize();
+  pipe_free(st->pipe);
+  delete[] st->fs;
+  delete st;
+}
+
+int qf_set_insert_batch(qf_set_t *st, const uint32_t *d_fid, const uint64_t *d_keys, uint64_t n,
+                        void *stream) {
+  if (!st || (n && (!d_keys || !d_fid))) return fail(QF_ERR_ARG);
+  if (n == 0) return QF_OK;
+  if (n > 0xFFFFFFFFull) return fail(QF_ERR_ARG);
+  return pipe_update(st->pipe, d_keys, d_fid, n, 0, nullptr, static_cast<hipStream_t>(stream), 0);
+}
+
+int qf_set_delete_batch(qf_set_t *st, const uint32_t *d_fid, const uint64_t *d_keys, uint64_t n,
+                        uint64_t *d_not_found, void *stream) {
+  if (!st || (n && (!d_keys || !d_fid))) return fail(QF_ERR_ARG);
+  if (n == 0) return QF_OK;
+  if (n > 0xFFFFFFFFull) return fail(QF_ERR_ARG);
+  return pipe_update(st->pipe, d_keys, d_fid, n, 1, d_not_found, static_cast<hipStream_t>(stream), 0);
+}
+
+int qf_set_query_batch(qf_set_t *st, const uint32_t *d_fid, const uint64_t *d_keys, uint64_t n,
+                       uint8_t *d_out, void *stream) {
+  if (!st || (n && (!d_keys || !d_fid || !d_out))) return fail(QF_ERR_ARG);
+  if (n == 0) return QF_OK;
+  QF_HIP(qf::launch_lookup_multi(st->pipe, d_keys, d_fid, n, d_out, nullptr, static_cast<hipStream_t>(stream)));
+  return QF_OK;
+}
+
+int qf_set_count_batch(qf_set_t *st, const uint32_t *d_fid, const uint64_t *d_keys, uint64_t n,
+                       uint64_t *d_out, void *stream) {
+  if (!st || (n && (!d_keys || !d_fid || !d_out))) return fail(QF_ERR_ARG);
+  if (n == 0) return QF_OK;
+  QF_HIP(qf::launch_lookup_multi(st->pipe, d_keys, d_fid, n, nullptr, d_out, static_cast<hipStream_t>(stream)));
+  return QF_OK;
+}
+
+int qf_set_sync(qf_set_t *st, void *stream) {
+  if (!st) return fail(QF_ERR_ARG);
+  QF_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+  // the set's own flag (a filter index out of range), then each filter's
+  // deferred error; all are cleared, the first one is returned
+  uint64_t w = 0;
+  QF_HIP(hipMemcpy(&w, st->pipe.pst + qf::ST_ERR, sizeof(w), hipMemcpyDeviceToHost));
+  int first = QF_OK;
+  if (w != 0) {
+    const uint64_t zero = 0;
+    QF_HIP(hipMemcpy(st->pipe.pst + qf::ST_ERR, &zero, sizeof(zero), hipMemcpyHostToDevice));
+    first = static_cast<int>(static_cast<int64_t>(w));
+  }
+  for (uint32_t i = 0; i < st->nf; ++i) {
+    const int rc = read_clear_error(st->fs[i]);
+    if (first == QF_OK && rc != QF_OK) first = rc;
+  }
+  return first == QF_OK ? QF_OK : fail(first);
+}
+
+int qf_set_info(const qf_set_t *st, uint64_t *info) {
+  if (!st || !info) return fail(QF_ERR_ARG);
+  info[0] = st->nf;
+  info[1] = st->pipe.r;
+  info[2] = st->pipe.G;
+  info[3] = st->pipe.RL;
+  info[4] = st->pipe.device_bytes;
+  info[5] = st->pipe.batches;
+  info[6] = st->pipe.gbits + st->pipe.RL + st->pipe.r;
+  info[7] = 0;
+  return QF_OK;
+}
+
+int qf_set_profile_enable(qf_set_t *st, int enable) {
+  if (!st) return fail(QF_ERR_ARG);
+  return profile_enable(st->pipe, enable);
+}
+
+int qf_set_profile_read(qf_set_t *st, double *ms, uint64_t *n) {
+  if (!st || !ms || !n) return fail(QF_ERR_ARG);
+  return profile_read(st->pipe, ms, n);
+}
+
 uint64_t qf_table_bytes(uint32_t q, uint32_t r) {
   if (q < 6 || q > 31 || (r != 8 && r != 16)) return 0;
   const uint64_t P = (1ull << q) + extra_slots(q);
@@ -376,41 +623,19 @@ int qf_info(const qf_t *f, uint64_t *info) {
   info[3] = f->E;
   info[4] = f->P;
   info[5] = 1ull << f->rlog;
-  info[6] = f->device_bytes;
-  info[7] = f->batches;
+  info[6] = f->table_device_bytes + f->pipe.device_bytes;
+  info[7] = f->pipe.batches;
   return QF_OK;
 }
 
 int qf_profile_enable(qf_t *f, int enable) {
   if (!f) return fail(QF_ERR_ARG);
-  if (enable && !f->timer) f->timer = new (std::nothrow) EventTimer();
-  if (enable && !f->timer) return fail(QF_ERR_OOM);
-  if (!enable && f->timer) {
-    (void)static_cast<EventTimer *>(f->timer)->collect();
-    delete f->timer;
-    f->timer = nullptr;
-  }
-  return QF_OK;
+  return profile_enable(f->pipe, enable);
 }
 
 int qf_profile_read(qf_t *f, double *ms, uint64_t *n) {
   if (!f || !ms || !n) return fail(QF_ERR_ARG);
-  if (!f->timer) {
-    for (int k = 0; k < QF_PROF_KINDS; ++k) {
-      ms[k] = 0.0;
-      n[k] = 0;
-    }
-    return QF_OK;
-  }
-  EventTimer *t = static_cast<EventTimer *>(f->timer);
-  const int rc = t->collect();
-  for (int k = 0; k < QF_PROF_KINDS; ++k) {
-    ms[k] = t->ms[k];
-    n[k] = t->n[k];
-    t->ms[k] = 0.0;
-    t->n[k] = 0;
-  }
-  return rc ? fail(rc) : QF_OK;
+  return profile_read(f->pipe, ms, n);
 }
 
 }  // extern "C"

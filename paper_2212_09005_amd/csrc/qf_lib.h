@@ -1,4 +1,5 @@
-// qf_lib.h -- host-side state of a filter and the kernel launchers the C ABI uses.
+// qf_lib.h -- host-side state of a filter and of a filter set, and the kernel
+// launchers the C ABI uses.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -11,6 +12,46 @@ struct Timer {
   virtual void end(int kind, hipStream_t s) = 0;
   virtual ~Timer() {}
 };
+
+// One filter as the kernels see it (an array of these lives in device memory
+// for every pipeline; a single filter's pipeline has one).
+struct FDesc {
+  void *blk[2];       // the two table copies (blocks)
+  uint32_t *off[2];   // and their offsets
+  uint64_t *state;    // ST_WORDS device words of the filter
+  int64_t N, P, nblocks;
+  uint32_t q, r, rlog, nregions, nqregions;
+  uint32_t rbase;     // first region of this filter in its pipeline's region numbering
+};
+
+// The machinery of bulk updates over nf filters with the same r: regions of
+// all filters are numbered 0..G-1 (filter f owns [rbase_f, rbase_f +
+// nregions_f)); keys are grouped by the composite key
+//   (global region << (RL + r)) | fingerprint bits inside the region,
+// RL = the largest region log2.  For one filter the composite key is the
+// fingerprint itself.
+struct Pipe {
+  uint32_t nf = 0, G = 0, RL = 0, r = 0;
+  uint32_t gbits = 0;         // bits of a global region index
+  FDesc *d_desc = nullptr;    // nf
+  uint32_t *d_rmap = nullptr; // G: global region -> filter
+  uint64_t *rb = nullptr;     // G + 1 region bounds into the reduced batch
+  uint64_t *tags = nullptr;   // 3 G look-back words, then
+  uint64_t *rstat = nullptr;  // 4 G per-region merge statistics, then
+  int64_t *cb = nullptr;      // G old carries (region boundaries)
+  uint64_t *pst = nullptr;    // ST_WORDS pipeline words (unique count)
+  uint32_t epoch = 0;
+  int device = 0;
+  // grow-only scratch, capacity in keys
+  uint64_t cap = 0;
+  uint64_t *bufA = nullptr, *bufB = nullptr, *bufC = nullptr, *bufD = nullptr;
+  uint64_t *bufE = nullptr;   // 32 bytes per key: the merge's per-entry scratch
+  uint32_t *hist = nullptr;   // radix histograms / tile counts
+  uint64_t hist_words = 0;
+  uint64_t device_bytes = 0;
+  uint64_t batches = 0;
+  Timer *timer = nullptr;     // non-null while profiling is enabled
+};
 }  // namespace qf
 
 struct qf_filter {
@@ -22,19 +63,14 @@ struct qf_filter {
   void *blk[2];             // two table copies (blocks)
   uint32_t *off[2];         // and their offsets
   uint64_t *state;          // qf::ST_WORDS device words
-  uint64_t *rb;             // nregions + 1 region bounds into the reduced batch
-  uint64_t *tags;           // 3 * nregions look-back words, then
-  uint64_t *rstat;          // 4 * nregions per-region merge statistics, then
-  int64_t *cb;              // nqregions + 1 old carries at region boundaries
-  uint32_t epoch;
-  uint64_t batches;
-  // grow-only scratch, capacity in keys
-  uint64_t cap;
-  uint64_t *bufA, *bufB, *bufC, *bufD;
-  uint32_t *hist;           // radix histograms / tile counts
-  uint64_t hist_words;
-  uint64_t device_bytes;
-  qf::Timer *timer;         // non-null while profiling is enabled
+  uint64_t table_device_bytes;
+  qf::Pipe pipe;            // the single-filter update pipeline
+};
+
+struct qf_set {
+  uint32_t nf;
+  qf_filter **fs;           // host copies of the handles (not owned)
+  qf::Pipe pipe;
 };
 
 namespace qf {
@@ -44,19 +80,28 @@ uint64_t table_bytes(uint64_t nblocks, uint32_t r);
 
 hipError_t launch_hash(const uint64_t *keys, uint64_t n, uint64_t pmask, uint64_t *fp,
                        hipStream_t s, Timer *t);
+// composite keys of a filter set: key i belongs to filter fid[i]
+hipError_t launch_hash_multi(const uint64_t *keys, const uint32_t *fid, uint64_t n, const Pipe &p,
+                             uint64_t *out, hipStream_t s, Timer *t);
 // LSD radix sort of n keys over the low `bits` bits; returns the buffer that
 // holds the result (a or b).
 hipError_t launch_sort(uint64_t *a, uint64_t *b, uint64_t n, uint32_t bits, uint32_t *hist,
                        uint64_t **result, hipStream_t s, Timer *t);
-// run-length reduction of the sorted fingerprints: ufp/ucnt, count in state
+// run-length reduction of the sorted keys: ufp/ucnt, count in state[ST_NUNIQ]
 hipError_t launch_rle(const uint64_t *sorted, uint64_t n, uint64_t *scratch_start,
                       uint64_t *ufp, uint64_t *ucnt, uint32_t *tile_counts, uint64_t *state,
                       hipStream_t s, Timer *t);
-hipError_t launch_bounds(const uint64_t *ufp, uint64_t *state, qf_filter *f, hipStream_t s);
-hipError_t launch_merge(qf_filter *f, const uint64_t *ufp, const uint64_t *ucnt, int del,
-                        uint64_t *not_found, hipStream_t s);
+// region bounds of the pipeline's G regions
+hipError_t launch_bounds(const uint64_t *ufp, Pipe &p, hipStream_t s);
+// old carries, per-filter batch flags, tag reset on epoch wrap, region merge
+// into the other table copies, finish (statistics, flip or deferred error).
+// not_found: nullptr or one word per filter of the pipeline.
+hipError_t launch_merge(Pipe &p, const uint64_t *ufp, const uint64_t *ucnt, int del,
+                        uint64_t *not_found, bool wrap, hipStream_t s);
 hipError_t launch_lookup(qf_filter *f, const uint64_t *keys, uint64_t n, uint8_t *out8,
                          uint64_t *out64, hipStream_t s);
+hipError_t launch_lookup_multi(const Pipe &p, const uint64_t *keys, const uint32_t *fid, uint64_t n,
+                               uint8_t *out8, uint64_t *out64, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_export(qf_filter *f, uint64_t *occ, uint64_t *rend, uint16_t *slots,
                          uint32_t *offs, hipStream_t s);
@@ -65,5 +110,6 @@ hipError_t launch_import(qf_filter *f, const uint64_t *occ, const uint64_t *rend
 
 // sort tiling: G work-groups each own a contiguous chunk of the keys
 uint32_t sort_groups(uint64_t n);
+int max_region_log2(uint32_t r);
 
 }  // namespace qf

@@ -100,6 +100,35 @@ __global__ __launch_bounds__(NT) void k_lookup(const Block<T> *b0, const Block<T
   }
 }
 
+// Lookups over a filter set: key i is looked up in filter fid[i] (0 for a
+// filter index out of range, which also flags the call in pst[ST_ERR]).
+template <typename T, bool COUNT>
+__global__ __launch_bounds__(NT) void k_lookup_multi(const FDesc *__restrict__ desc, uint32_t nf,
+                                                     const uint64_t *__restrict__ keys,
+                                                     const uint32_t *__restrict__ fid, uint64_t n,
+                                                     uint8_t *__restrict__ out8, uint64_t *__restrict__ out64,
+                                                     uint64_t *pst) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * NT;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * NT + threadIdx.x; i < n; i += stride) {
+    const uint32_t f = fid[i];
+    uint64_t c = 0;
+    if (f < nf) {
+      const FDesc &d = desc[f];
+      const bool cur = d.state[ST_CUR] & 1ull;
+      const uint32_t p = d.q + d.r;
+      const uint64_t fp = mix64(keys[i]) & ((1ull << p) - 1ull);
+      c = lookup_one(static_cast<const Block<T> *>(cur ? d.blk[1] : d.blk[0]), cur ? d.off[1] : d.off[0],
+                     d.nblocks, static_cast<int64_t>(fp >> d.r), fp & ((1ull << d.r) - 1ull), d.r);
+    } else {
+      pst[ST_ERR] = static_cast<uint64_t>(static_cast<int64_t>(QF_ERR_ARG));
+    }
+    if (COUNT)
+      out64[i] = c;
+    else
+      out8[i] = c != 0;
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(NT) void k_export(const Block<T> *b0, const Block<T> *b1,
                                                const uint32_t *o0, const uint32_t *o1,
@@ -152,7 +181,8 @@ hipError_t lookup_t(qf_filter *f, const uint64_t *keys, uint64_t n, uint8_t *out
                     uint64_t *out64, hipStream_t s) {
   const Block<T> *b0 = static_cast<const Block<T> *>(f->blk[0]);
   const Block<T> *b1 = static_cast<const Block<T> *>(f->blk[1]);
-  if (f->timer) f->timer->begin(QF_PROF_LOOKUP, s);
+  Timer *t = f->pipe.timer;
+  if (t) t->begin(QF_PROF_LOOKUP, s);
   if (out64)
     k_lookup<T, true><<<grid_for(n), NT, 0, s>>>(b0, b1, f->off[0], f->off[1], f->state, keys, n,
                                                  f->q, f->r, static_cast<int64_t>(f->nblocks),
@@ -161,11 +191,29 @@ hipError_t lookup_t(qf_filter *f, const uint64_t *keys, uint64_t n, uint8_t *out
     k_lookup<T, false><<<grid_for(n), NT, 0, s>>>(b0, b1, f->off[0], f->off[1], f->state, keys, n,
                                                   f->q, f->r, static_cast<int64_t>(f->nblocks),
                                                   out8, nullptr);
-  if (f->timer) f->timer->end(QF_PROF_LOOKUP, s);
+  if (t) t->end(QF_PROF_LOOKUP, s);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t lookup_multi_t(const Pipe &p, const uint64_t *keys, const uint32_t *fid, uint64_t n, uint8_t *out8,
+                          uint64_t *out64, hipStream_t s) {
+  if (p.timer) p.timer->begin(QF_PROF_LOOKUP, s);
+  if (out64)
+    k_lookup_multi<T, true><<<grid_for(n), NT, 0, s>>>(p.d_desc, p.nf, keys, fid, n, nullptr, out64, p.pst);
+  else
+    k_lookup_multi<T, false><<<grid_for(n), NT, 0, s>>>(p.d_desc, p.nf, keys, fid, n, out8, nullptr, p.pst);
+  if (p.timer) p.timer->end(QF_PROF_LOOKUP, s);
   return hipGetLastError();
 }
 
 }  // namespace
+
+hipError_t launch_lookup_multi(const Pipe &p, const uint64_t *keys, const uint32_t *fid, uint64_t n,
+                               uint8_t *out8, uint64_t *out64, hipStream_t s) {
+  if (p.r == 8) return lookup_multi_t<uint8_t>(p, keys, fid, n, out8, out64, s);
+  return lookup_multi_t<uint16_t>(p, keys, fid, n, out8, out64, s);
+}
 
 uint64_t table_bytes(uint64_t nblocks, uint32_t r) {
   const uint64_t bb = r == 8 ? sizeof(Block<uint8_t>) : sizeof(Block<uint16_t>);

@@ -58,20 +58,31 @@ struct Cfg {
   static constexpr int PER = 16 / static_cast<int>(sizeof(T));      // slots per chunk
 };
 
-template <typename T>
+// max-plus maps relative to a region's first quotient (-1 = "none")
+struct Fn32 {
+  int32_t A, B;
+};
+__device__ __forceinline__ Fn32 f32_id() { return Fn32{-1, 0}; }
+__device__ __forceinline__ Fn32 f32_then(Fn32 g, Fn32 h) { return Fn32{max(h.A, g.A + h.B), g.B + h.B}; }
+
+// One merge launch over the G regions of a pipeline (all filters of a set, or
+// one filter); a work-group finds its filter through rmap and desc.
 struct MergeArgs {
-  Block<T> *blk[2];
-  uint32_t *off[2];
-  int64_t N, P, nblocks;
-  uint32_t r, rlog, nregions;
-  const uint64_t *ufp, *ucnt, *rb;
-  uint64_t *tags;
-  uint64_t *rstat;  // 4 words per region: used, distinct, total, shortfall
-  const int64_t *cb;  // old carries at the quotient-region boundaries
-  uint32_t epoch;
-  uint64_t *state;
+  const FDesc *desc;
+  const uint32_t *rmap;
+  const uint64_t *ufp, *ucnt, *rb;  // composite keys, counts, region bounds
+  uint64_t *tags;                   // 3 G look-back words
+  uint64_t *rstat;                  // 4 words per region: used, distinct, total, shortfall
+  const int64_t *cb;                // old carries at region boundaries
+  uint32_t G, epoch;
   int del;
-  uint64_t *not_found;
+  // per-entry scratch (indexed like the reduced batch) for regions with more
+  // entries than the LDS holds: region-relative fingerprints and counts, and
+  // the changed-run arrays (a region has at most as many changed runs as
+  // entries, so run c of the region starting at entry rb0 sits at rb0 + c)
+  uint32_t *g_fp, *g_cnt, *g_head, *g_L;
+  uint16_t *g_xr, *g_op, *g_oe, *g_st;
+  Fn32 *g_gaf;
 };
 
 // ---- readers of the current (old) table -------------------------------------
@@ -99,9 +110,12 @@ struct NewRel {
   __device__ uint64_t f(uint32_t i) const { return fp[i]; }
   __device__ uint64_t c(uint32_t i) const { return cnt[i]; }
 };
+// the region's entries straight from the reduced batch: the composite key's
+// low bits are the fingerprint inside the region, `base` its high part
 struct NewGlb {
   const uint64_t *fp, *cnt;
-  __device__ uint64_t f(uint64_t i) const { return fp[i]; }
+  uint64_t base, mask;
+  __device__ uint64_t f(uint64_t i) const { return base | (fp[i] & mask); }
   __device__ uint64_t c(uint64_t i) const { return cnt[i]; }
 };
 
@@ -198,17 +212,28 @@ __device__ int64_t carry_old(const Block<T> *b, const uint32_t *off, int64_t i, 
   }
 }
 
-// Old carry at every quotient-region boundary: cb[R] = carry_old(R S) for
-// R in [0, nq] (nq = number of quotient regions), one thread each, so that
-// the merge reads its region's bounds with one load instead of a chain.
+// Before the merge, one thread per region g of the pipeline: the old carry at
+// the region's first slot (cb[g] = carry_old(R S) for local regions R up to
+// the first extra-slot region), the filter's batch flags (by its region 0),
+// and, when the launch epoch wraps, the region's look-back words.
 template <typename T>
-__global__ __launch_bounds__(NT) void k_carries(const Block<T> *b0, const Block<T> *b1, const uint32_t *o0,
-                                                const uint32_t *o1, const uint64_t *state, int64_t N,
-                                                uint32_t rlog, uint32_t nq, int64_t *cb) {
-  const uint32_t R = blockIdx.x * NT + threadIdx.x;
-  if (R > nq) return;
-  const bool cur = state[ST_CUR] & 1ull;
-  cb[R] = carry_old(cur ? b1 : b0, cur ? o1 : o0, static_cast<int64_t>(R) << rlog, N);
+__global__ __launch_bounds__(NT) void k_carries(const FDesc *__restrict__ desc, const uint32_t *__restrict__ rmap,
+                                                uint32_t G, bool wrap, uint64_t *tags, int64_t *cb) {
+  const uint32_t g = blockIdx.x * NT + threadIdx.x;
+  if (g >= G) return;
+  const FDesc &d = desc[rmap[g]];
+  const uint32_t R = g - d.rbase;
+  if (R == 0) d.state[ST_BATCH] = 0;
+  if (wrap) {
+    tags[g] = 0;
+    tags[static_cast<uint64_t>(G) + g] = 0;
+    tags[2ull * G + g] = 0;
+  }
+  if (R <= d.nqregions) {
+    const bool cur = d.state[ST_CUR] & 1ull;
+    cb[g] = carry_old(static_cast<const Block<T> *>(cur ? d.blk[1] : d.blk[0]), cur ? d.off[1] : d.off[0],
+                      static_cast<int64_t>(R) << d.rlog, d.N);
+  }
 }
 
 // Merge of one quotient's old run [op, oe] with its new entries [ni, nj):
@@ -353,11 +378,6 @@ __device__ __forceinline__ void walk(uint32_t r, int del, int64_t RS, const uint
 // Positions are int32: quotients relative to the region start, old slots as
 // indexes into the staged blocks, new slots as indexes into the assembled
 // output.  Maps are kept relative to the region start too (-1 = "none").
-struct Fn32 {
-  int32_t A, B;
-};
-__device__ __forceinline__ Fn32 f32_id() { return Fn32{-1, 0}; }
-__device__ __forceinline__ Fn32 f32_then(Fn32 g, Fn32 h) { return Fn32{max(h.A, g.A + h.B), g.B + h.B}; }
 
 template <typename T>
 struct OldStaged {
@@ -544,13 +564,14 @@ __device__ __forceinline__ int select64_fast(uint64_t v, int k) {
 // out-of-line call would cost the whole kernel a call frame and registers)
 template <typename T, bool EMIT>
 __device__ __forceinline__ void walk_global(const Block<T> *ob, Block<T> *nbk, int64_t nblocks,
-                                         const uint64_t *ufp, const uint64_t *ucnt, uint32_t r,
+                                         const uint64_t *ufp, const uint64_t *ucnt, uint64_t fbase,
+                                         uint64_t fmask, uint32_t r,
                                          int del, int64_t RS, const uint64_t *occ_l, int64_t x0,
                                          int64_t x1, int64_t s0, int64_t s1, int64_t ope,
                                          uint64_t ni, uint64_t nb, int64_t hi, int64_t carry,
                                          Acc *acc, uint64_t *nocc_l, uint32_t *noff) {
   OldGlb<T> old{ob, nblocks};
-  NewGlb nw{ufp, ucnt};
+  NewGlb nw{ufp, ucnt, fbase, fmask};
   Acc a = *acc;
   if (EMIT) {
     OutGlb<T> out;
@@ -648,11 +669,12 @@ __device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t *sh) {
   return t;
 }
 
-// Carry-in of region R (called by the 64 lanes of one wave): lane l looks at
-// regions hi - 4l - k, k = 0..3; the nearest region with a known inclusive
-// carry ends the walk, the aggregates of the regions in between are composed
-// in order (per lane, then across the wave by an ordered tree).  One memory
-// round trip covers 256 predecessors.
+// Carry-in of region R (called by the 64 lanes of one wave) of a filter whose
+// first region is R0: lane l looks at regions hi - LBK l - k, k < LBK; the
+// nearest region with a known inclusive carry ends the walk (before R0 the
+// carry is -1), the aggregates of the regions in between are composed in
+// order (per lane, then across the wave by an ordered tree).  One memory
+// round trip covers 64 LBK predecessors.
 // Work-groups are dispatched in index order on each XCD, so a region's
 // predecessors have all started; the spin is still bounded: after LB_IDLE
 // consecutive rounds without progress the wave gives up, flags the batch
@@ -660,7 +682,7 @@ __device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t *sh) {
 constexpr int LBK = 1;
 constexpr uint32_t LB_IDLE = 1u << 20;
 __device__ int64_t look_back_wave(const uint64_t *tags, uint32_t nreg, uint32_t epoch, int64_t R,
-                                  bool *stalled) {
+                                  int64_t R0, bool *stalled) {
   const int lane = threadIdx.x & 63;
   Fn acc = fn_id();  // regions (hi, R-1], applied in order
   int64_t hi = R - 1;
@@ -674,8 +696,8 @@ __device__ int64_t look_back_wave(const uint64_t *tags, uint32_t nreg, uint32_t 
       const int64_t j = hi - LBK * lane - k;
       g[k] = fn_id();
       v[k] = -1;
-      if (j < 0) {
-        first_inc = k;  // before region 0 the carry is -1
+      if (j < R0) {
+        first_inc = k;  // before the filter's first region the carry is -1
       } else {
         int64_t tv = 0, tA = 0, tB = 0;
         const bool hv = tag_load(&tags[2ull * nreg + j], epoch, &tv);
@@ -736,7 +758,7 @@ __device__ int64_t look_back_wave(const uint64_t *tags, uint32_t nreg, uint32_t 
 }
 
 template <typename T>
-__global__ __launch_bounds__(NT) void k_merge(MergeArgs<T> a) {
+__global__ __launch_bounds__(NT) void k_merge(MergeArgs a) {
   using C = Cfg<T>;
   __shared__ __align__(16) T old_s[C::CAP];
   __shared__ __align__(16) T new_s[C::CAP];
@@ -747,39 +769,48 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs<T> a) {
   // quotients that receive new entries; reused for the new occupied bits of
   // the one-lane path
   __shared__ uint64_t chg_l[C::OW];
-  // the region's new entries, and its changed runs (one per distinct quotient)
+  // the region's new entries, and its changed runs (one per distinct
+  // quotient), in LDS when there are at most NCAP entries, else in the
+  // launch's per-entry scratch
   __shared__ uint32_t nfp_l[C::NCAP];
   __shared__ uint32_t ncnt_l[C::NCAP];
-  __shared__ uint16_t cxr[C::NCAP];    // quotient - RS
-  __shared__ uint16_t chead[C::NCAP];  // first entry
-  __shared__ uint16_t cop[C::NCAP];    // old run, staged indexes (coe 0xFFFF: none)
-  __shared__ uint16_t coe[C::NCAP];
-  __shared__ uint32_t cL[C::NCAP];     // new length
-  __shared__ uint16_t cst[C::NCAP];    // new first slot, output index
-  __shared__ Fn32 gaf[C::NCAP];        // maps of the unchanged runs after it
+  __shared__ uint16_t cxr_l[C::NCAP];   // quotient - RS
+  __shared__ uint32_t chead_l[C::NCAP]; // first entry
+  __shared__ uint16_t cop_l[C::NCAP];   // old run, staged indexes (coe 0xFFFF: none)
+  __shared__ uint16_t coe_l[C::NCAP];
+  __shared__ uint32_t cL_l[C::NCAP];    // new length
+  __shared__ uint16_t cst_l[C::NCAP];   // new first slot, output index
+  __shared__ Fn32 gaf_l[C::NCAP];       // maps of the unchanged runs after it
   __shared__ int64_t sh_i[8];
   __shared__ Fn sh_fn[NT / 64];
   __shared__ uint32_t sh_u[2 * NT / 64];
   __shared__ uint64_t sh_r[NT / 64];
 
   const int tid = threadIdx.x;
-  // region = work-group index (no shared ticket counter: one atomic per
-  // work-group on one address serialises the whole launch)
-  const int64_t R = blockIdx.x;
-  const int32_t S = 1 << a.rlog;
-  const int64_t RS = R << a.rlog;
-  // (selects, not a dynamic index into the argument struct, which would put
-  // the struct in scratch memory)
-  const int cur = static_cast<int>(a.state[ST_CUR] & 1ull);
-  const Block<T> *ob = cur ? a.blk[1] : a.blk[0];
-  Block<T> *nbk = cur ? a.blk[0] : a.blk[1];
-  uint32_t *noff = cur ? a.off[0] : a.off[1];
-  const bool qreg = RS < a.N;
-  const int64_t send = min(RS + S, a.P);
+  // global region = work-group index (no shared ticket counter: one atomic
+  // per work-group on one address serialises the whole launch); the filter
+  // and its local region R follow from the pipeline's region map
+  const uint32_t gR = blockIdx.x;
+  const FDesc &fd = a.desc[a.rmap[gR]];
+  const int64_t R = gR - fd.rbase;
+  const uint32_t rlog = fd.rlog;
+  const int64_t FN = fd.N, FP = fd.P, FNB = fd.nblocks;
+  uint64_t *const fstate = fd.state;
+  const int32_t S = 1 << rlog;
+  const int64_t RS = R << rlog;
+  // (selects, not a dynamic index into a struct, which would put it in
+  // scratch memory)
+  const int cur = static_cast<int>(fstate[ST_CUR] & 1ull);
+  const Block<T> *ob = static_cast<const Block<T> *>(cur ? fd.blk[1] : fd.blk[0]);
+  Block<T> *nbk = static_cast<Block<T> *>(cur ? fd.blk[0] : fd.blk[1]);
+  uint32_t *noff = cur ? fd.off[0] : fd.off[1];
+  const bool qreg = RS < FN;
+  const int64_t send = min(RS + S, FP);
   const int nw_reg = static_cast<int>((send - RS + 63) >> 6);
-  const uint64_t rb0 = a.rb[R], rb1 = a.rb[R + 1];
+  const uint64_t rb0 = a.rb[gR], rb1 = a.rb[gR + 1];
   const uint64_t ne = rb1 - rb0;
-  const uint32_t r = a.r;
+  const uint32_t r = fd.r;
+  const uint64_t lmask = (1ull << (rlog + r)) - 1ull;  // fingerprint bits inside the region
 
   for (int w = tid; w < nw_reg; w += NT) {
     occ_l[w] = qreg ? ob[(RS >> 6) + w].occ : 0ull;
@@ -788,23 +819,30 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs<T> a) {
   for (int w = tid; w < C::CAPW; w += NT) new_b[w] = 0ull;
   for (int i = tid; i < C::CAP * static_cast<int>(sizeof(T)) / 16; i += NT)
     reinterpret_cast<uint4 *>(new_s)[i] = make_uint4(0u, 0u, 0u, 0u);
-  const bool new_lds = ne <= static_cast<uint64_t>(C::NCAP);
-  if (new_lds) {
-    const uint64_t rmask = (1ull << r) - 1ull;
+  const bool small = ne <= static_cast<uint64_t>(C::NCAP);
+  uint32_t *const nfp = small ? nfp_l : a.g_fp + rb0;
+  uint32_t *const ncnt = small ? ncnt_l : a.g_cnt + rb0;
+  uint16_t *const cxr = small ? cxr_l : a.g_xr + rb0;
+  uint32_t *const chead = small ? chead_l : a.g_head + rb0;
+  uint16_t *const cop = small ? cop_l : a.g_op + rb0;
+  uint16_t *const coe = small ? coe_l : a.g_oe + rb0;
+  uint32_t *const cL = small ? cL_l : a.g_L + rb0;
+  uint16_t *const cst = small ? cst_l : a.g_st + rb0;
+  Fn32 *const gaf = small ? gaf_l : a.g_gaf + rb0;
+  if (ne < (1ull << 31)) {
     for (uint32_t i = tid; i < ne; i += NT) {
-      const uint64_t fp = a.ufp[rb0 + i];
-      nfp_l[i] = static_cast<uint32_t>((((fp >> r) - static_cast<uint64_t>(RS)) << r) | (fp & rmask));
-      ncnt_l[i] = static_cast<uint32_t>(a.ucnt[rb0 + i]);
+      nfp[i] = static_cast<uint32_t>(a.ufp[rb0 + i] & lmask);
+      ncnt[i] = static_cast<uint32_t>(a.ucnt[rb0 + i]);
     }
   }
   __syncthreads();
-  const int64_t lo_old = qreg ? a.cb[R] + 1 : RS;
-  const int64_t hi_old = qreg ? a.cb[R + 1] : RS - 1;
+  const int64_t lo_old = qreg ? a.cb[gR] + 1 : RS;
+  const int64_t hi_old = qreg ? a.cb[gR + 1] : RS - 1;
   const bool has_old = hi_old >= lo_old;
   const int64_t bb = has_old ? (lo_old >> 6) : (RS >> 6);
   const int64_t nblk64 = has_old ? (hi_old >> 6) - bb + 1 : 0;
-  // the staged path: entries and old runs fit in LDS (and positions in int32)
-  const bool par = new_lds && nblk64 <= C::CAPW && (bb << 6) - RS < (1ll << 30);
+  // the staged path: the old runs fit in LDS (and positions in int32)
+  const bool par = ne < (1ull << 31) && nblk64 <= C::CAPW && (bb << 6) - RS < (1ll << 30);
   const int nblk = par ? static_cast<int>(nblk64) : 0;
   const int32_t obr = static_cast<int32_t>(par ? (bb << 6) - RS : 0);  // staged base - RS
 
@@ -822,27 +860,29 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs<T> a) {
       old_b[w] = v;
     }
   }
-  // changed runs = groups of equal quotient among the new entries: entries
-  // [2 tid, 2 tid + 2) per lane (ne <= NCAP <= 2 NT here)
+  // changed runs = groups of equal quotient among the new entries, found in
+  // rounds of 2 NT entries ([2 tid, 2 tid + 2) per lane; one round unless the
+  // region has more than NCAP entries)
   uint32_t nchg = 0;
-  {
+  const uint32_t ne32 = par ? static_cast<uint32_t>(ne) : 0u;
+  for (uint32_t base = 0; base < ne32; base += 2 * NT) {
     uint32_t h0 = 0, h1 = 0;
-    const uint32_t e0 = 2u * tid, e1 = e0 + 1;
-    const uint32_t x0 = par && e0 < ne ? nfp_l[e0] >> r : 0u;
-    const uint32_t x1 = par && e1 < ne ? nfp_l[e1] >> r : 0u;
-    if (par && e0 < ne) h0 = e0 == 0 || x0 != (nfp_l[e0 - 1] >> r);
-    if (par && e1 < ne) h1 = x1 != x0;
+    const uint32_t e0 = base + 2u * tid, e1 = e0 + 1;
+    const uint32_t x0 = e0 < ne32 ? nfp[e0] >> r : 0u;
+    const uint32_t x1 = e1 < ne32 ? nfp[e1] >> r : 0u;
+    if (e0 < ne32) h0 = e0 == 0 || x0 != (nfp[e0 - 1] >> r);
+    if (e1 < ne32) h1 = x1 != x0;
     uint32_t tot;
-    const uint32_t ex = block_exscan_u32(h0 + h1, sh_u, &tot);
-    nchg = tot;
+    const uint32_t ex = nchg + block_exscan_u32(h0 + h1, sh_u, &tot);
+    nchg += tot;
     if (h0) {
       cxr[ex] = static_cast<uint16_t>(x0);
-      chead[ex] = static_cast<uint16_t>(e0);
+      chead[ex] = e0;
       atomicOr(reinterpret_cast<ull *>(&chg_l[x0 >> 6]), static_cast<ull>(1ull << (x0 & 63)));
     }
     if (h1) {
       cxr[ex + h0] = static_cast<uint16_t>(x1);
-      chead[ex + h0] = static_cast<uint16_t>(e1);
+      chead[ex + h0] = e1;
       atomicOr(reinterpret_cast<ull *>(&chg_l[x1 >> 6]), static_cast<ull>(1ull << (x1 & 63)));
     }
   }
@@ -904,7 +944,7 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs<T> a) {
     }
     __syncthreads();
     // ---- pass 1a: new lengths of the changed runs, one run per lane --------
-    NewRel nw{nfp_l, ncnt_l};
+    NewRel nw{nfp, ncnt};
     OldStaged<T> old{old_s};
     NoOut none;
     for (uint32_t c = tid; c < nchg; c += NT) {
@@ -929,7 +969,7 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs<T> a) {
     acc.used = used;
   } else if (tid == 0) {
     Acc ag{fn_id(), 0, 0, 0, 0, 0};
-    walk_global<T, false>(ob, nbk, a.nblocks, a.ufp, a.ucnt, a.r, a.del, RS, occ_l, qreg ? RS : 0,
+    walk_global<T, false>(ob, nbk, FNB, a.ufp, a.ucnt, static_cast<uint64_t>(RS) << r, lmask, r, a.del, RS, occ_l, qreg ? RS : 0,
                           qreg ? send : 0, RS, send, lo_old - 1, rb0, rb1, 0, 0, &ag, chg_l, noff);
     acc = ag;
     Flane = ag.F;
@@ -943,23 +983,23 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs<T> a) {
   const uint64_t ovf = block_sum_u64(acc.ovf, sh_r);
 
   if (tid == 0) {
-    tag_store(&a.tags[R], a.epoch, Ftot.A);
-    tag_store(&a.tags[static_cast<uint64_t>(a.nregions) + R], a.epoch, Ftot.B);
+    tag_store(&a.tags[gR], a.epoch, Ftot.A);
+    tag_store(&a.tags[static_cast<uint64_t>(a.G) + gR], a.epoch, Ftot.B);
   }
   if (tid < 64) {
     bool stalled = false;
-    const int64_t c_in = look_back_wave(a.tags, a.nregions, a.epoch, R, &stalled);
+    const int64_t c_in = look_back_wave(a.tags, a.G, a.epoch, gR, fd.rbase, &stalled);
     if (tid == 0) {
-      if (stalled) atomic_or_u64(&a.state[ST_BATCH], BATCH_STALL);
+      if (stalled) atomic_or_u64(&fstate[ST_BATCH], BATCH_STALL);
       const int64_t c_out = fn_apply(Ftot, c_in);
-      tag_store(&a.tags[2ull * a.nregions + R], a.epoch, c_out);
+      tag_store(&a.tags[2ull * a.G + gR], a.epoch, c_out);
       sh_i[3] = c_in;
       sh_i[4] = c_out;
       // errors are rare and set one shared word; the statistics go to the
       // region's own words and are summed after the launch
-      if (c_out >= a.P) atomic_or_u64(&a.state[ST_BATCH], BATCH_FULL);
-      if (ovf) atomic_or_u64(&a.state[ST_BATCH], BATCH_OVF);
-      uint64_t *st = a.rstat + 4 * R;
+      if (c_out >= FP) atomic_or_u64(&fstate[ST_BATCH], BATCH_FULL);
+      if (ovf) atomic_or_u64(&fstate[ST_BATCH], BATCH_OVF);
+      uint64_t *st = a.rstat + 4ull * gR;
       st[0] = used;
       st[1] = dent;
       st[2] = dtot;
@@ -973,7 +1013,7 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs<T> a) {
   // copy never becomes current), so it writes nothing; every other region's
   // runs end below P, which bounds all writes below.
   const int64_t c_in = sh_i[3], c_out = sh_i[4];
-  const bool emit = c_out < a.P;
+  const bool emit = c_out < FP;
   const int64_t ext_lo = max(c_in + 1, RS);
   const int64_t ext_hi = max(c_out, send - 1);
   const int64_t xbase = (ext_lo >> 6) << 6;
@@ -1015,7 +1055,7 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs<T> a) {
     }
     __syncthreads();
     // 2b: the changed runs' slots, one run per lane
-    NewRel nw{nfp_l, ncnt_l};
+    NewRel nw{nfp, ncnt};
     OldStaged<T> old{old_s};
     SlotsRel<T> so{new_s};
     Acc dummy{fn_id(), 0, 0, 0, 0, 0};
@@ -1060,7 +1100,7 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs<T> a) {
     __syncthreads();
     if (tid == 0) {
       Acc dummy{fn_id(), 0, 0, 0, 0, 0};
-      walk_global<T, true>(ob, nbk, a.nblocks, a.ufp, a.ucnt, a.r, a.del, RS, occ_l, qreg ? RS : 0,
+      walk_global<T, true>(ob, nbk, FNB, a.ufp, a.ucnt, static_cast<uint64_t>(RS) << r, lmask, r, a.del, RS, occ_l, qreg ? RS : 0,
                            qreg ? send : 0, RS, send, lo_old - 1, rb0, rb1, ext_hi, c_in, &dummy, chg_l, noff);
     }
     __syncthreads();
@@ -1068,14 +1108,16 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs<T> a) {
   }
 }
 
-// After the merge: sum the regions' statistics; flip the current copy if no
-// region failed, else record the error (all-or-nothing).  One work-group.
-__global__ __launch_bounds__(1024) void k_finish(uint64_t *state, const uint64_t *rstat, uint32_t nregions,
-                                                 int del, uint64_t *not_found) {
+// After the merge, one work-group per filter: sum its regions' statistics;
+// flip its current copy if none of its regions failed, else record the error
+// (all-or-nothing per filter); add its delete shortfall to not_found[f].
+__global__ __launch_bounds__(1024) void k_finish(const FDesc *__restrict__ desc, const uint64_t *rstat, int del,
+                                                 uint64_t *not_found) {
   __shared__ uint64_t sh[4][16];
+  const FDesc &d = desc[blockIdx.x];
   uint64_t v[4] = {0, 0, 0, 0};
-  for (uint32_t R = threadIdx.x; R < nregions; R += 1024)
-    for (int k = 0; k < 4; ++k) v[k] += rstat[4ull * R + k];
+  for (uint32_t R = threadIdx.x; R < d.nregions; R += 1024)
+    for (int k = 0; k < 4; ++k) v[k] += rstat[4ull * (d.rbase + R) + k];
   for (int k = 0; k < 4; ++k) {
     for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o);
     if ((threadIdx.x & 63) == 0) sh[k][threadIdx.x >> 6] = v[k];
@@ -1085,6 +1127,7 @@ __global__ __launch_bounds__(1024) void k_finish(uint64_t *state, const uint64_t
     uint64_t t[4] = {0, 0, 0, 0};
     for (int k = 0; k < 4; ++k)
       for (int w = 0; w < 16; ++w) t[k] += sh[k][w];
+    uint64_t *state = d.state;
     const uint64_t st = state[ST_BATCH];
     if (st == 0) {
       state[ST_USED] = t[0];
@@ -1096,50 +1139,52 @@ __global__ __launch_bounds__(1024) void k_finish(uint64_t *state, const uint64_t
                                             : (st & BATCH_FULL) ? QF_ERR_FULL
                                                                 : QF_ERR_COUNT_OVERFLOW);
     }
-    if (del) *not_found += t[3];
+    if (del && not_found) not_found[blockIdx.x] += t[3];
     state[ST_BATCHES] += 1;
   }
 }
 
 template <typename T>
-hipError_t launch_merge_t(qf_filter *f, const uint64_t *ufp, const uint64_t *ucnt, int del,
-                          uint64_t *not_found, hipStream_t s) {
-  MergeArgs<T> a;
-  a.blk[0] = static_cast<Block<T> *>(f->blk[0]);
-  a.blk[1] = static_cast<Block<T> *>(f->blk[1]);
-  a.off[0] = f->off[0];
-  a.off[1] = f->off[1];
-  a.N = static_cast<int64_t>(f->N);
-  a.P = static_cast<int64_t>(f->P);
-  a.nblocks = static_cast<int64_t>(f->nblocks);
-  a.r = f->r;
-  a.rlog = f->rlog;
-  a.nregions = f->nregions;
+hipError_t launch_merge_t(Pipe &p, const uint64_t *ufp, const uint64_t *ucnt, int del, uint64_t *not_found,
+                          bool wrap, hipStream_t s) {
+  MergeArgs a;
+  a.desc = p.d_desc;
+  a.rmap = p.d_rmap;
   a.ufp = ufp;
   a.ucnt = ucnt;
-  a.rb = f->rb;
-  a.tags = f->tags;
-  a.epoch = f->epoch;
-  a.state = f->state;
+  a.rb = p.rb;
+  a.tags = p.tags;
+  a.rstat = p.rstat;
+  a.cb = p.cb;
+  a.G = p.G;
+  a.epoch = p.epoch;
   a.del = del;
-  a.not_found = not_found ? not_found : f->state + ST_SCRATCH;
-  a.rstat = f->rstat;
-  a.cb = f->cb;
-  if (f->timer) f->timer->begin(QF_PROF_MERGE, s);
-  k_carries<T><<<(f->nqregions + 1 + NT - 1) / NT, NT, 0, s>>>(a.blk[0], a.blk[1], a.off[0], a.off[1], f->state,
-                                                             a.N, f->rlog, f->nqregions, f->cb);
-  k_merge<T><<<f->nregions, NT, 0, s>>>(a);
-  k_finish<<<1, 1024, 0, s>>>(f->state, f->rstat, f->nregions, del, a.not_found);
-  if (f->timer) f->timer->end(QF_PROF_MERGE, s);
+  // per-entry scratch: bufE holds cap entries of 32 bytes
+  uint8_t *e = reinterpret_cast<uint8_t *>(p.bufE);
+  const uint64_t cap = p.cap;
+  a.g_fp = reinterpret_cast<uint32_t *>(e);
+  a.g_cnt = reinterpret_cast<uint32_t *>(e + 4 * cap);
+  a.g_head = reinterpret_cast<uint32_t *>(e + 8 * cap);
+  a.g_L = reinterpret_cast<uint32_t *>(e + 12 * cap);
+  a.g_gaf = reinterpret_cast<Fn32 *>(e + 16 * cap);
+  a.g_xr = reinterpret_cast<uint16_t *>(e + 24 * cap);
+  a.g_op = reinterpret_cast<uint16_t *>(e + 26 * cap);
+  a.g_oe = reinterpret_cast<uint16_t *>(e + 28 * cap);
+  a.g_st = reinterpret_cast<uint16_t *>(e + 30 * cap);
+  if (p.timer) p.timer->begin(QF_PROF_MERGE, s);
+  k_carries<T><<<(p.G + NT - 1) / NT, NT, 0, s>>>(p.d_desc, p.d_rmap, p.G, wrap, p.tags, p.cb);
+  k_merge<T><<<p.G, NT, 0, s>>>(a);
+  k_finish<<<p.nf, 1024, 0, s>>>(p.d_desc, p.rstat, del, not_found);
+  if (p.timer) p.timer->end(QF_PROF_MERGE, s);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_merge(qf_filter *f, const uint64_t *ufp, const uint64_t *ucnt, int del,
-                        uint64_t *not_found, hipStream_t s) {
-  if (f->r == 8) return launch_merge_t<uint8_t>(f, ufp, ucnt, del, not_found, s);
-  return launch_merge_t<uint16_t>(f, ufp, ucnt, del, not_found, s);
+hipError_t launch_merge(Pipe &p, const uint64_t *ufp, const uint64_t *ucnt, int del, uint64_t *not_found,
+                        bool wrap, hipStream_t s) {
+  if (p.r == 8) return launch_merge_t<uint8_t>(p, ufp, ucnt, del, not_found, wrap, s);
+  return launch_merge_t<uint16_t>(p, ufp, ucnt, del, not_found, wrap, s);
 }
 
 int max_region_log2(uint32_t r) { return r == 8 ? Cfg<uint8_t>::SMAXLOG : Cfg<uint16_t>::SMAXLOG; }

@@ -34,6 +34,32 @@ __global__ __launch_bounds__(NT) void k_hash(const uint64_t *__restrict__ keys, 
     fp[i] = mix64(keys[i]) & pmask;
 }
 
+// Composite keys of a filter set: key i goes to filter fid[i]; its
+// fingerprint's region becomes a global region index in the high bits, the
+// fingerprint bits inside the region stay in the low RL + r bits.  A filter
+// index out of range gives the key ~0 (past every region, so it is dropped)
+// and flags the call (pst[ST_ERR]).
+__global__ __launch_bounds__(NT) void k_hash_multi(const uint64_t *__restrict__ keys,
+                                                   const uint32_t *__restrict__ fid, uint64_t n,
+                                                   const FDesc *__restrict__ desc, uint32_t nf,
+                                                   uint32_t RL, uint64_t *__restrict__ out,
+                                                   uint64_t *pst) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * NT;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * NT + threadIdx.x; i < n; i += stride) {
+    const uint32_t f = fid[i];
+    if (f >= nf) {
+      out[i] = ~0ull;
+      pst[ST_ERR] = static_cast<uint64_t>(static_cast<int64_t>(QF_ERR_ARG));
+      continue;
+    }
+    const FDesc &d = desc[f];
+    const uint32_t p = d.q + d.r, lb = d.rlog + d.r;
+    const uint64_t fp = mix64(keys[i]) & ((1ull << p) - 1ull);
+    const uint64_t g = d.rbase + (fp >> lb);
+    out[i] = (g << (RL + d.r)) | (fp & ((1ull << lb) - 1ull));
+  }
+}
+
 __global__ __launch_bounds__(NT) void k_fill(uint64_t *p, uint64_t n, uint64_t v) {
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * NT;
   for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * NT + threadIdx.x; i < n; i += stride)
@@ -246,29 +272,15 @@ __global__ __launch_bounds__(NT) void k_rle_counts(const uint64_t *__restrict__ 
     ucnt[j] = (j + 1 < u ? ustart[j + 1] : n) - ustart[j];
 }
 
-// Successor search (Sec. 5.3): rb[R] = first reduced entry whose quotient is
-// >= the first quotient of region R; regions past the quotients get u.  Also
-// resets the per-launch words of the merge that follows.
+// Successor search (Sec. 5.3): rb[g] = first reduced entry whose (composite)
+// key is >= the first key of region g, for the G regions of a pipeline.
 __global__ __launch_bounds__(NT) void k_bounds(const uint64_t *__restrict__ ufp,
-                                               uint64_t *state, uint32_t nregions,
-                                               uint32_t nqregions, uint32_t shift,
+                                               const uint64_t *pst, uint32_t G, uint32_t shift,
                                                uint64_t *__restrict__ rb) {
-  const uint32_t R = blockIdx.x * NT + threadIdx.x;
-  if (R == 0) {
-    state[ST_TILE] = 0;
-    state[ST_DONE] = 0;
-    state[ST_BATCH] = 0;
-    state[ST_NUSED] = 0;
-    state[ST_NDIST] = 0;
-    state[ST_NTOTAL] = 0;
-  }
-  if (R > nregions) return;
-  const uint64_t u = state[ST_NUNIQ];
-  if (R >= nqregions) {
-    rb[R] = u;
-    return;
-  }
-  const uint64_t key = static_cast<uint64_t>(R) << shift;
+  const uint32_t g = blockIdx.x * NT + threadIdx.x;
+  if (g > G) return;
+  const uint64_t u = pst[ST_NUNIQ];
+  const uint64_t key = static_cast<uint64_t>(g) << shift;
   uint64_t lo = 0, hi = u;
   while (lo < hi) {
     const uint64_t mid = (lo + hi) >> 1;
@@ -277,7 +289,7 @@ __global__ __launch_bounds__(NT) void k_bounds(const uint64_t *__restrict__ ufp,
     else
       hi = mid;
   }
-  rb[R] = lo;
+  rb[g] = lo;
 }
 
 inline uint32_t blocks_for(uint64_t n, uint32_t cap = 65535u * 4u) {
@@ -298,6 +310,14 @@ hipError_t launch_hash(const uint64_t *keys, uint64_t n, uint64_t pmask, uint64_
                        hipStream_t s, Timer *t) {
   if (t) t->begin(QF_PROF_HASH, s);
   k_hash<<<blocks_for(n), NT, 0, s>>>(keys, n, pmask, fp);
+  if (t) t->end(QF_PROF_HASH, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_hash_multi(const uint64_t *keys, const uint32_t *fid, uint64_t n, const Pipe &p,
+                             uint64_t *out, hipStream_t s, Timer *t) {
+  if (t) t->begin(QF_PROF_HASH, s);
+  k_hash_multi<<<blocks_for(n), NT, 0, s>>>(keys, fid, n, p.d_desc, p.nf, p.RL, out, p.pst);
   if (t) t->end(QF_PROF_HASH, s);
   return hipGetLastError();
 }
@@ -348,12 +368,11 @@ hipError_t launch_rle(const uint64_t *sorted, uint64_t n, uint64_t *scratch_star
   return hipGetLastError();
 }
 
-hipError_t launch_bounds(const uint64_t *ufp, uint64_t *state, qf_filter *f, hipStream_t s) {
-  const uint32_t nthreads = f->nregions + 1;
-  if (f->timer) f->timer->begin(QF_PROF_BOUNDS, s);
-  k_bounds<<<(nthreads + NT - 1) / NT, NT, 0, s>>>(ufp, state, f->nregions, f->nqregions,
-                                                   f->rlog + f->r, f->rb);
-  if (f->timer) f->timer->end(QF_PROF_BOUNDS, s);
+hipError_t launch_bounds(const uint64_t *ufp, Pipe &p, hipStream_t s) {
+  const uint32_t nthreads = p.G + 1;
+  if (p.timer) p.timer->begin(QF_PROF_BOUNDS, s);
+  k_bounds<<<(nthreads + NT - 1) / NT, NT, 0, s>>>(ufp, p.pst, p.G, p.RL + p.r, p.rb);
+  if (p.timer) p.timer->end(QF_PROF_BOUNDS, s);
   return hipGetLastError();
 }
 

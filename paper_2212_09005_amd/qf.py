@@ -98,6 +98,18 @@ def lib() -> ctypes.CDLL:
         "qf_info": (i32, [vp, ctypes.POINTER(ctypes.c_uint64)]),
         "qf_profile_enable": (i32, [vp, i32]),
         "qf_profile_read": (i32, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64)]),
+        "qf_reserve": (i32, [vp, u64, vp]),
+        "qf_set_reserve": (i32, [vp, u64, vp]),
+        "qf_set_create": (vp, [ctypes.POINTER(vp), u32]),
+        "qf_set_destroy": (None, [vp]),
+        "qf_set_insert_batch": (i32, [vp, vp, vp, u64, vp]),
+        "qf_set_delete_batch": (i32, [vp, vp, vp, u64, vp, vp]),
+        "qf_set_query_batch": (i32, [vp, vp, vp, u64, vp, vp]),
+        "qf_set_count_batch": (i32, [vp, vp, vp, u64, vp, vp]),
+        "qf_set_sync": (i32, [vp, vp]),
+        "qf_set_info": (i32, [vp, ctypes.POINTER(ctypes.c_uint64)]),
+        "qf_set_profile_enable": (i32, [vp, i32]),
+        "qf_set_profile_read": (i32, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -285,3 +297,123 @@ class CQF:
 
     def info(self) -> dict:
         return qf_info(self.h)
+
+    def reserve(self, n: int, stream=None):
+        _check(lib().qf_reserve(self.h, n, _stream(stream)), "qf_reserve")
+
+
+# ---- filter sets ----------------------------------------------------------
+def qf_set_create(filters) -> int:
+    hs = (ctypes.c_void_p * len(filters))(*[int(f) for f in filters])
+    h = lib().qf_set_create(hs, len(filters))
+    if not h:
+        raise QFError(lib().qf_last_error(), f"qf_set_create({len(filters)} filters)")
+    return h
+
+
+def qf_set_destroy(s: int) -> None:
+    lib().qf_set_destroy(s)
+
+
+def qf_set_insert_batch(s: int, fid, keys, stream=None) -> int:
+    n = keys.numel()
+    if not n:
+        return QF_OK
+    return lib().qf_set_insert_batch(s, _dev_ptr(fid, n, 4), _dev_ptr(keys, n, 8), n, _stream(stream))
+
+
+def qf_set_delete_batch(s: int, fid, keys, not_found=None, stream=None) -> int:
+    n = keys.numel()
+    if not n:
+        return QF_OK
+    nf = _dev_ptr(not_found, None, 8) if not_found is not None else None
+    return lib().qf_set_delete_batch(s, _dev_ptr(fid, n, 4), _dev_ptr(keys, n, 8), n, nf, _stream(stream))
+
+
+def qf_set_query_batch(s: int, fid, keys, out, stream=None) -> int:
+    n = keys.numel()
+    if not n:
+        return QF_OK
+    return lib().qf_set_query_batch(s, _dev_ptr(fid, n, 4), _dev_ptr(keys, n, 8), n, _dev_ptr(out, n, 1),
+                                    _stream(stream))
+
+
+def qf_set_count_batch(s: int, fid, keys, out, stream=None) -> int:
+    n = keys.numel()
+    if not n:
+        return QF_OK
+    return lib().qf_set_count_batch(s, _dev_ptr(fid, n, 4), _dev_ptr(keys, n, 8), n, _dev_ptr(out, n, 8),
+                                    _stream(stream))
+
+
+def qf_set_sync(s: int, stream=None) -> int:
+    return lib().qf_set_sync(s, _stream(stream))
+
+
+def qf_set_info(s: int) -> dict:
+    buf = (ctypes.c_uint64 * 8)()
+    _check(lib().qf_set_info(s, buf), "qf_set_info")
+    keys = ("nf", "r", "regions", "region_log2_max", "device_bytes", "batches", "key_bits", "_")
+    return dict(zip(keys, (int(v) for v in buf)))
+
+
+def qf_set_profile_enable(s: int, enable: bool = True) -> int:
+    return lib().qf_set_profile_enable(s, 1 if enable else 0)
+
+
+def qf_set_profile_read(s: int) -> dict:
+    ms = (ctypes.c_double * len(PROF_KINDS))()
+    n = (ctypes.c_uint64 * len(PROF_KINDS))()
+    _check(lib().qf_set_profile_read(s, ms, n), "qf_set_profile_read")
+    return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(PROF_KINDS)}
+
+
+class CQFSet:
+    """A set of CQF filters (same r) updated and queried by one pipeline of launches.
+    Keys are tagged with int32 filter indices into `filters`; the filters must outlive the set."""
+
+    def __init__(self, filters):
+        self.filters = list(filters)
+        self.h = qf_set_create([f.h for f in self.filters])
+
+    def close(self):
+        if getattr(self, "h", None):
+            qf_set_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def insert(self, fid, keys, stream=None):
+        _check(qf_set_insert_batch(self.h, fid, keys, stream), "qf_set_insert_batch")
+
+    def delete(self, fid, keys, not_found=None, stream=None):
+        _check(qf_set_delete_batch(self.h, fid, keys, not_found, stream), "qf_set_delete_batch")
+
+    def query(self, fid, keys, out=None, stream=None):
+        import torch
+
+        if out is None:
+            out = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device)
+        _check(qf_set_query_batch(self.h, fid, keys, out, stream), "qf_set_query_batch")
+        return out
+
+    def count(self, fid, keys, out=None, stream=None):
+        import torch
+
+        if out is None:
+            out = torch.empty(keys.numel(), dtype=torch.int64, device=keys.device)
+        _check(qf_set_count_batch(self.h, fid, keys, out, stream), "qf_set_count_batch")
+        return out
+
+    def sync(self, stream=None) -> int:
+        return qf_set_sync(self.h, stream)
+
+    def info(self) -> dict:
+        return qf_set_info(self.h)
+
+    def reserve(self, n: int, stream=None):
+        _check(lib().qf_set_reserve(self.h, n, _stream(stream)), "qf_set_reserve")
