@@ -247,6 +247,111 @@ def bench_sets(args) -> dict:
     return res
 
 
+def bench_sweep(args) -> dict:
+    """Load sweep (2^28 quotients, r = 8): fill in batches of 2^22 keys to load 0.95; the batch that
+    crosses each 0.05 step is split so the steps are exact.  After each step one query batch of 2^22
+    keys (half present, half absent).  Insert rate per step = keys of the step / time of its batches."""
+    import torch
+
+    from paper_2212_09005_amd import inputs, qf
+
+    q, r, m = args.q, 8, 1 << args.batch_log2
+    N = 1 << q
+    top = int(0.95 * N)
+    keys = inputs.uniform_keys(1, top)
+    f = qf.CQF(q, r)
+    f.reserve(m)
+    qout = torch.empty(m, dtype=torch.uint8, device="cuda")
+    steps = []
+    done = 0
+    for k in range(1, 20):
+        target = int(round(0.05 * k * N)) if k < 19 else top
+        target = min(target, top)
+        n_step = target - done
+        d = torch.from_numpy(keys[done:target].view(np.int64)).to("cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for a in range(0, n_step, m):
+            f.insert(d[a:a + m])
+        torch.cuda.synchronize()
+        t_ins = time.perf_counter() - t0
+        assert f.sync() == 0
+        done = target
+        qk = inputs.mixed_queries(2000 + k, keys[:done], m // 2, m - m // 2)
+        dq = torch.from_numpy(qk.view(np.int64)).to("cuda")
+        f.query(dq, qout)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f.query(dq, qout)
+        torch.cuda.synchronize()
+        t_q = time.perf_counter() - t0
+        steps.append({"load": round(done / N, 4), "insert_Bps": round(n_step / t_ins / 1e9, 4),
+                      "query_Bps": round(m / t_q / 1e9, 4)})
+        log(f"sweep load {done / N:.2f}: insert {n_step / t_ins / 1e9:.3f} B/s, query {m / t_q / 1e9:.3f} B/s")
+        del d, dq
+    f.close()
+    at9 = next(s_ for s_ in steps if abs(s_["load"] - 0.9) < 1e-3)
+    return {"metric": METRIC + " (load sweep)", "value": at9["insert_Bps"], "unit": "B inserts/s at load 0.9",
+            "n_gpus": 1, "higher_is_better": True, "dtype": "u64", "data": "synthetic",
+            "config": {"workload": f"cqf_q{q}_r8_sweep_to_0.95_batch{m}", "q": q, "r": r, "batch": m},
+            "steps": steps}
+
+
+def bench_zipf(args) -> dict:
+    """Counting with skew (2^30 quotients, r = 16): insert 0.9 * 2^30 Zipf(1.1) instances over 2^28
+    distinct values as one batch, count 2^26 keys uniform over the 2^28 values, then delete a
+    random 25 % of the inserted instances.  --zipf-scale shrinks every size by 2^-scale."""
+    import torch
+
+    from paper_2212_09005_amd import inputs, qf
+
+    sc = args.zipf_scale
+    q, r = 30 - sc, 16
+    n = int(0.9 * (1 << q))
+    universe = 1 << (28 - sc)
+    t0 = time.time()
+    keys = inputs.zipf_keys(3, n, 1.1, universe)
+    log(f"zipf: {n} instances generated in {time.time() - t0:.1f}s")
+    f = qf.CQF(q, r)
+    f.reserve(n)
+    d = torch.from_numpy(keys.view(np.int64)).to("cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f.insert(d)
+    torch.cuda.synchronize()
+    t_ins = time.perf_counter() - t0
+    rc = f.sync()
+    assert rc == 0, f"insert failed {rc}"
+    mc = 1 << (26 - sc)
+    ranks = np.random.Generator(np.random.PCG64(4)).integers(1, universe + 1, size=mc)
+    ck = inputs.rank_to_key(ranks)
+    dc = torch.from_numpy(ck.view(np.int64)).to("cuda")
+    cout = torch.empty(mc, dtype=torch.int64, device="cuda")
+    f.count(dc, cout)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f.count(dc, cout)
+    torch.cuda.synchronize()
+    t_cnt = time.perf_counter() - t0
+    dk = keys[inputs.bernoulli_mask(5, n, 0.25)]
+    ddel = torch.from_numpy(dk.view(np.int64)).to("cuda")
+    nf = torch.zeros(1, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f.delete(ddel, nf)
+    torch.cuda.synchronize()
+    t_del = time.perf_counter() - t0
+    assert f.sync() == 0 and int(nf.item()) == 0
+    info = f.info()
+    f.close()
+    return {"metric": "counting insert / count / delete throughput with Zipf(1.1) keys", "value": round(n / t_ins / 1e9, 4),
+            "unit": "B inserts/s", "n_gpus": 1, "higher_is_better": True, "dtype": "u64", "data": "synthetic",
+            "config": {"workload": f"cqf_q{q}_r16_zipf1.1_universe2^{28 - sc}_one_batch", "q": q, "r": r,
+                       "instances": n, "count_keys": mc, "delete_instances": int(len(dk))},
+            "insert_Bps": round(n / t_ins / 1e9, 4), "count_Bps": round(mc / t_cnt / 1e9, 4),
+            "delete_Bps": round(len(dk) / t_del / 1e9, 4), "device_bytes": info["device_bytes"]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -256,8 +361,10 @@ def main() -> int:
     ap.add_argument("--load", type=float, default=0.9)
     ap.add_argument("--batch-log2", type=int, default=22)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["c2", "c4"], default="c2",
-                    help="c2: the single-filter step (default); c4: many filters, set vs per-filter loop")
+    ap.add_argument("--workload", choices=["c2", "sweep", "zipf", "c4"], default="c2",
+                    help="c2: the single-filter step (default); sweep: load sweep to 0.95; zipf: one-batch "
+                         "counting with skew (2^30, r=16); c4: many filters, set vs per-filter loop")
+    ap.add_argument("--zipf-scale", type=int, default=0)
     ap.add_argument("--sets-filters", type=int, default=4096)
     ap.add_argument("--sets-query-log2", type=int, default=24)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -274,10 +381,11 @@ def main() -> int:
     from paper_2212_09005_amd import qf
     from paper_2212_09005_amd.workloads import LoadSweep
 
-    if args.workload == "c4":
+    if args.workload != "c2":
         assert torch.cuda.is_available(), "bench.py needs a GPU"
         torch.cuda.set_device(0)
-        print(json.dumps(bench_sets(args)), flush=True)
+        fn = {"c4": bench_sets, "sweep": bench_sweep, "zipf": bench_zipf}[args.workload]
+        print(json.dumps(fn(args)), flush=True)
         return 0
 
     w = LoadSweep(q=args.q, load=args.load, batch=1 << args.batch_log2)

@@ -51,9 +51,10 @@ enum {
   QF_ERR_OOM = -3,            /* device allocation failed                     */
   QF_ERR_DEVICE = -4,         /* a HIP runtime call failed                    */
   QF_ERR_COUNT_OVERFLOW = -5, /* a count would exceed 2^64 - 1                */
-  QF_ERR_STALLED = -6         /* a merge region waited too long for the carry
+  QF_ERR_STALLED = -6,        /* a merge region waited too long for the carry
                                  of the regions before it (a safety bound
                                  that should never trigger); batch not applied */
+  QF_ERR_BUDGET = -7          /* serving: a filter larger than the HBM budget */
 };
 
 /* Logical layout of a table, as host arrays (qf_export / qf_import).
@@ -185,6 +186,9 @@ int qf_set_count_batch(qf_set_t *s, const uint32_t *d_fid, const uint64_t *d_key
 /* Waits for `stream`; returns (and clears) the set's own deferred error, else
  * the first deferred error of its filters (all of them are cleared). */
 int qf_set_sync(qf_set_t *s, void *stream);
+/* Waits for `stream`; writes each filter's deferred error (0 = none) to
+ * codes[0..nf) (host) and clears them; returns how many are nonzero. */
+int qf_set_errors(qf_set_t *s, int32_t *codes, void *stream);
 /* qf_reserve for the set's pipeline. */
 int qf_set_reserve(qf_set_t *s, uint64_t n, void *stream);
 /* info[0..7] = nf, r, total regions, largest region log2, device bytes held by
@@ -192,6 +196,44 @@ int qf_set_reserve(qf_set_t *s, uint64_t n, void *stream);
 int qf_set_info(const qf_set_t *s, uint64_t *info);
 int qf_set_profile_enable(qf_set_t *s, int enable);
 int qf_set_profile_read(qf_set_t *s, double *ms, uint64_t *n);
+
+/* ---- serving: device-resident filters, requests batched as they arrive ----
+ * A server keeps filters in HBM and answers requests submitted from any host
+ * thread.  A loop thread batches whatever is waiting into rounds: per filter,
+ * the leading run of its waiting requests with one operation; all filters'
+ * shares of one operation (and r) run as one filter-set batch, so requests
+ * that arrive while others are on the device join the next round, and the
+ * next round is assembled and launched while the current one runs.  Per
+ * filter the effects and answers are those of executing its requests one by
+ * one in submission order (linearizable in admission order); requests on
+ * different filters are independent.  Filters are admitted in open order
+ * while the device bytes they need fit the budget (their requests wait until
+ * then); a close frees its bytes once the filter's earlier requests are done.
+ * Keys are host arrays copied at submission; a query (count) writes n bytes
+ * (n uint64) to h_out before its completion is reported by qfs_poll.  Delete
+ * shortfalls are not reported per request.  A request's status is QF_OK or its
+ * filter's deferred error for the round it ran in (QF_ERR_FULL: that filter's
+ * updates of the round were not applied). */
+typedef struct qf_server qfs_t;
+enum { QFS_INSERT = 0, QFS_DELETE = 1, QFS_QUERY = 2, QFS_COUNT = 3 };
+/* max_round_keys bounds the keys of one round and of one request; the two
+ * pinned staging buffers and the batch scratch it implies count against the
+ * budget.  NULL on error. */
+qfs_t *qfs_create(uint64_t budget_bytes, uint64_t max_round_keys);
+void qfs_destroy(qfs_t *s); /* drains the queue, stops the loop, frees all */
+/* Returns the filter id (>= 0), QF_ERR_BUDGET if it can never fit, or
+ * QF_ERR_ARG (q, r as for qf_create). */
+int qfs_open(qfs_t *s, uint32_t q, uint32_t r);
+int qfs_submit(qfs_t *s, int op, int id, const uint64_t *h_keys, uint64_t n, void *h_out, uint64_t tag);
+/* Closes a filter after its earlier requests; its completion is reported with
+ * `tag` like a request's.  Later submissions to it fail with QF_ERR_ARG. */
+int qfs_close(qfs_t *s, int id, uint64_t tag);
+/* Writes up to max completions (tag, status); waits up to wait_us for one if
+ * none is ready.  Returns how many were written. */
+int qfs_poll(qfs_t *s, uint64_t *tags, int32_t *status, uint32_t max, int wait_us);
+/* st[0..7] = rounds, requests completed, keys processed, filters open,
+ * filters waiting for admission, bytes in use, budget, requests waiting. */
+int qfs_stats(qfs_t *s, uint64_t *st);
 
 #ifdef __cplusplus
 }

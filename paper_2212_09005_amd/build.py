@@ -23,6 +23,7 @@ FLAGS = [
     # keep the compiler from emitting packed fp32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
+    "-pthread",
     "-Wno-unused-function",
 ]
 

@@ -91,6 +91,7 @@ void pipe_free(qf::Pipe &p) {
   (void)hipFree(p.tags);
   (void)hipFree(p.pst);
   (void)hipFree(p.hist);
+  (void)hipFree(p.d_err);
   free_scratch(p);
   delete p.timer;
   p = qf::Pipe();
@@ -153,7 +154,8 @@ int pipe_init(qf::Pipe &p, qf_filter *const *fs, uint32_t nf) {
             hipMalloc(reinterpret_cast<void **>(&p.rb), (G + 1) * sizeof(uint64_t)) == hipSuccess &&
             hipMalloc(reinterpret_cast<void **>(&p.tags), tag_words * sizeof(uint64_t)) == hipSuccess &&
             hipMalloc(reinterpret_cast<void **>(&p.pst), qf::ST_WORDS * sizeof(uint64_t)) == hipSuccess &&
-            hipMalloc(reinterpret_cast<void **>(&p.hist), p.hist_words * sizeof(uint32_t)) == hipSuccess;
+            hipMalloc(reinterpret_cast<void **>(&p.hist), p.hist_words * sizeof(uint32_t)) == hipSuccess &&
+            hipMalloc(reinterpret_cast<void **>(&p.d_err), nf * sizeof(int64_t)) == hipSuccess;
   ok = ok && hipMemcpy(p.d_desc, desc.data(), nf * sizeof(qf::FDesc), hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(p.d_rmap, rmap.data(), G * sizeof(uint32_t), hipMemcpyHostToDevice) == hipSuccess &&
        hipMemset(p.tags, 0, tag_words * sizeof(uint64_t)) == hipSuccess &&
@@ -175,18 +177,17 @@ int pipe_update(qf::Pipe &p, const uint64_t *keys, const uint32_t *fid, uint64_t
                 uint64_t *not_found, hipStream_t s, uint32_t single_q) {
   int rc = ensure_scratch(p, n, s);
   if (rc) return rc;
-  uint32_t bits;
+  uint64_t *sorted = nullptr;
   if (fid) {
     QF_HIP(qf::launch_hash_multi(keys, fid, n, p, p.bufA, s, p.timer));
-    bits = p.gbits + p.RL + p.r;
+    QF_HIP(qf::launch_sort(p.bufA, p.bufB, n, p.gbits + p.RL + p.r, p.hist, &sorted, s, p.timer));
   } else {
-    // one filter: its composite key is the fingerprint itself
-    bits = single_q + p.r;
+    // one filter: its composite key is the fingerprint itself, and the first
+    // sort pass hashes the keys
+    const uint32_t bits = single_q + p.r;
     const uint64_t pmask = bits >= 64 ? ~0ull : ((1ull << bits) - 1ull);
-    QF_HIP(qf::launch_hash(keys, n, pmask, p.bufA, s, p.timer));
+    QF_HIP(qf::launch_sort(p.bufA, p.bufB, n, bits, p.hist, &sorted, s, p.timer, keys, pmask));
   }
-  uint64_t *sorted = nullptr;
-  QF_HIP(qf::launch_sort(p.bufA, p.bufB, n, bits, p.hist, &sorted, s, p.timer));
   uint64_t *other = sorted == p.bufA ? p.bufB : p.bufA;
   QF_HIP(qf::launch_rle(sorted, n, other, p.bufC, p.bufD, p.hist, p.pst, s, p.timer));
   QF_HIP(qf::launch_bounds(p.bufC, p, s));
@@ -584,6 +585,21 @@ int qf_set_sync(qf_set_t *st, void *stream) {
     if (first == QF_OK && rc != QF_OK) first = rc;
   }
   return first == QF_OK ? QF_OK : fail(first);
+}
+
+int qf_set_errors(qf_set_t *st, int32_t *codes, void *stream) {
+  if (!st || !codes) return fail(QF_ERR_ARG);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::vector<int64_t> e(st->nf);
+  QF_HIP(qf::launch_take_errors(st->pipe, st->pipe.d_err, s));
+  QF_HIP(hipMemcpyAsync(e.data(), st->pipe.d_err, st->nf * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  QF_HIP(hipStreamSynchronize(s));
+  int bad = 0;
+  for (uint32_t i = 0; i < st->nf; ++i) {
+    codes[i] = static_cast<int32_t>(e[i]);
+    bad += e[i] != 0;
+  }
+  return bad;
 }
 
 int qf_set_info(const qf_set_t *st, uint64_t *info) {

@@ -40,6 +40,7 @@ struct Pipe {
   uint64_t *rstat = nullptr;  // 4 G per-region merge statistics, then
   int64_t *cb = nullptr;      // G old carries (region boundaries)
   uint64_t *pst = nullptr;    // ST_WORDS pipeline words (unique count)
+  int64_t *d_err = nullptr;   // nf: per-filter deferred errors gathered by qf_set_errors
   uint32_t epoch = 0;
   int device = 0;
   // grow-only scratch, capacity in keys
@@ -84,9 +85,11 @@ hipError_t launch_hash(const uint64_t *keys, uint64_t n, uint64_t pmask, uint64_
 hipError_t launch_hash_multi(const uint64_t *keys, const uint32_t *fid, uint64_t n, const Pipe &p,
                              uint64_t *out, hipStream_t s, Timer *t);
 // LSD radix sort of n keys over the low `bits` bits; returns the buffer that
-// holds the result (a or b).
+// holds the result (a or b).  With raw != nullptr the input is raw keys
+// (a is not read): the first pass sorts mix64(raw[i]) & pmask.
 hipError_t launch_sort(uint64_t *a, uint64_t *b, uint64_t n, uint32_t bits, uint32_t *hist,
-                       uint64_t **result, hipStream_t s, Timer *t);
+                       uint64_t **result, hipStream_t s, Timer *t, const uint64_t *raw = nullptr,
+                       uint64_t pmask = 0);
 // run-length reduction of the sorted keys: ufp/ucnt, count in state[ST_NUNIQ]
 hipError_t launch_rle(const uint64_t *sorted, uint64_t n, uint64_t *scratch_start,
                       uint64_t *ufp, uint64_t *ucnt, uint32_t *tile_counts, uint64_t *state,
@@ -103,6 +106,8 @@ hipError_t launch_lookup(qf_filter *f, const uint64_t *keys, uint64_t n, uint8_t
 hipError_t launch_lookup_multi(const Pipe &p, const uint64_t *keys, const uint32_t *fid, uint64_t n,
                                uint8_t *out8, uint64_t *out64, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
+// copy each filter's deferred error word to err[f] and clear it
+hipError_t launch_take_errors(const Pipe &p, int64_t *err, hipStream_t s);
 hipError_t launch_export(qf_filter *f, uint64_t *occ, uint64_t *rend, uint16_t *slots,
                          uint32_t *offs, hipStream_t s);
 hipError_t launch_import(qf_filter *f, const uint64_t *occ, const uint64_t *rend,

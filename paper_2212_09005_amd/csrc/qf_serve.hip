@@ -1,0 +1,559 @@
+// qf_serve.hip -- serving: device-resident filters answering a stream of mixed
+// requests with continuous batching (declared in include/qf.h, qfs_*).
+//
+// A loop thread owns every HIP call of the server.  Requests are admitted in
+// submission order; each round takes, per filter, the longest prefix of its
+// waiting requests that share one operation (so per filter the effects follow
+// admission order), packs the round's keys of each (r, operation) into pinned
+// buffers and runs them as filter-set batches (one pipeline of launches for
+// all filters with that r).  While the device runs round k the thread forms and
+// launches round k + 1 on the same stream (two sets of pinned buffers), then
+// completes round k: outputs are copied to the callers' buffers and each
+// request's status is its filter's deferred error for that round, if any.
+// Filters are admitted while the device bytes they need fit the budget; later
+// ones wait (their requests too) until a close frees room.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "qf.h"
+#include "qf_lib.h"
+
+namespace {
+
+enum { OP_INSERT = QFS_INSERT, OP_DELETE = QFS_DELETE, OP_QUERY = QFS_QUERY, OP_COUNT = QFS_COUNT, OP_CLOSE = 4 };
+
+struct Req {
+  uint64_t seq;  // submission order
+  int op;
+  int id;
+  std::vector<uint64_t> keys;  // copied at submission
+  void *out;
+  uint64_t tag;
+  int status;
+};
+
+struct Slot {
+  uint32_t q, r;
+  uint64_t bytes;  // device bytes reserved against the budget
+  qf_t *f = nullptr;
+  enum { PENDING, OPEN, CLOSED } state = PENDING;
+  bool closing = false;  // a close was submitted: no further requests
+};
+
+// Pinned staging for one round: keys, filter indexes and outputs.
+struct Stage {
+  uint64_t cap = 0;
+  uint64_t *keys = nullptr;
+  uint32_t *fid = nullptr;
+  uint64_t *out64 = nullptr;
+  uint8_t *out8 = nullptr;
+  uint64_t *d_keys = nullptr;
+  uint32_t *d_fid = nullptr;
+  uint64_t *d_out64 = nullptr;
+  uint8_t *d_out8 = nullptr;
+  hipEvent_t done = nullptr;
+  // per-filter deferred errors of the round, gathered on the stream after
+  // the round's launches (nerr words per set, sets in order of r)
+  int64_t *d_err = nullptr, *h_err = nullptr;
+  uint32_t nerr = 0;
+  bool alloc_err(uint32_t n) {
+    (void)hipFree(d_err);
+    (void)hipHostFree(h_err);
+    d_err = h_err = nullptr;
+    nerr = n;
+    return n == 0 || (hipMalloc(reinterpret_cast<void **>(&d_err), n * 8) == hipSuccess &&
+                      hipHostMalloc(reinterpret_cast<void **>(&h_err), n * 8, 0) == hipSuccess);
+  }
+  bool alloc(uint64_t n) {
+    cap = n;
+    return hipHostMalloc(reinterpret_cast<void **>(&keys), n * 8, 0) == hipSuccess &&
+           hipHostMalloc(reinterpret_cast<void **>(&fid), n * 4, 0) == hipSuccess &&
+           hipHostMalloc(reinterpret_cast<void **>(&out64), n * 8, 0) == hipSuccess &&
+           hipHostMalloc(reinterpret_cast<void **>(&out8), n, 0) == hipSuccess &&
+           hipMalloc(reinterpret_cast<void **>(&d_keys), n * 8) == hipSuccess &&
+           hipMalloc(reinterpret_cast<void **>(&d_fid), n * 4) == hipSuccess &&
+           hipMalloc(reinterpret_cast<void **>(&d_out64), n * 8) == hipSuccess &&
+           hipMalloc(reinterpret_cast<void **>(&d_out8), n) == hipSuccess &&
+           hipEventCreateWithFlags(&done, hipEventDisableTiming) == hipSuccess;
+  }
+  void release() {
+    (void)hipHostFree(keys);
+    (void)hipHostFree(fid);
+    (void)hipHostFree(out64);
+    (void)hipHostFree(out8);
+    (void)hipFree(d_keys);
+    (void)hipFree(d_fid);
+    (void)hipFree(d_out64);
+    (void)hipFree(d_out8);
+    if (done) (void)hipEventDestroy(done);
+    (void)hipFree(d_err);
+    (void)hipHostFree(h_err);
+  }
+};
+
+// One (r, operation) batch of a round: the requests and their key offsets.
+struct Part {
+  uint32_t r;
+  int op;
+  std::vector<Req *> reqs;
+  std::vector<uint64_t> off;  // offset of each request's keys in the stage
+  uint64_t n = 0;
+};
+
+struct Round {
+  std::vector<Part> parts;
+  std::vector<Req *> closes;
+  bool empty() const { return parts.empty() && closes.empty(); }
+};
+
+// A filter set per r over the open filters, rebuilt when membership changes.
+struct SetOf {
+  qf_set_t *set = nullptr;
+  std::vector<int> ids;        // set index -> server id
+  std::map<int, uint32_t> idx; // server id -> set index
+};
+
+}  // namespace
+
+struct qf_server {
+  uint64_t budget, used = 0, max_round;
+  std::vector<Slot> slots;
+  std::deque<Req *> queue;   // admitted requests, submission order
+  std::vector<Req *> done;   // completed, not yet polled
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  bool stop = false;
+  std::thread loop;
+  hipStream_t stream = nullptr;
+  Stage stage[2];
+  std::map<uint32_t, SetOf> sets;  // by r
+  bool sets_dirty = true;
+  uint64_t rounds = 0, requests = 0, keys = 0, seq = 0;
+  int device = 0;
+};
+
+namespace {
+
+// device bytes a filter holds: two table copies, its state words and its
+// one-filter pipeline's per-region words (the server never uses that
+// pipeline's scratch), plus a margin for its share of the filter sets
+uint64_t filter_bytes(uint32_t q, uint32_t r) {
+  const uint64_t regions = ((1ull << q) >> std::min<uint32_t>(q, r == 8 ? 13 : 12)) + 64;
+  return 2 * qf_table_bytes(q, r) + regions * 72 + (1ull << 20) * 2;
+}
+
+void admit_locked(qf_server *s) {
+  for (size_t i = 0; i < s->slots.size(); ++i) {
+    Slot &sl = s->slots[i];
+    if (sl.state != Slot::PENDING || sl.f) continue;
+    if (s->used + sl.bytes > s->budget) break;  // admission in open order
+    sl.f = qf_create(sl.q, sl.r);
+    if (!sl.f) break;
+    s->used += sl.bytes;
+    sl.state = Slot::OPEN;
+    s->sets_dirty = true;
+  }
+}
+
+int rebuild_sets(qf_server *s) {
+  for (auto &kv : s->sets) qf_set_destroy(kv.second.set);
+  s->sets.clear();
+  std::map<uint32_t, std::vector<qf_t *>> by_r;
+  for (size_t i = 0; i < s->slots.size(); ++i) {
+    const Slot &sl = s->slots[i];
+    if (sl.state != Slot::OPEN) continue;
+    SetOf &so = s->sets[sl.r];
+    so.idx[static_cast<int>(i)] = static_cast<uint32_t>(so.ids.size());
+    so.ids.push_back(static_cast<int>(i));
+    by_r[sl.r].push_back(sl.f);
+  }
+  for (auto &kv : by_r) {
+    SetOf &so = s->sets[kv.first];
+    so.set = qf_set_create(kv.second.data(), static_cast<uint32_t>(kv.second.size()));
+    if (!so.set) return qf_last_error();
+    const int rc = qf_set_reserve(so.set, s->max_round, s->stream);
+    if (rc) return rc;
+  }
+  uint32_t nopen = 0;
+  for (auto &kv : s->sets) nopen += static_cast<uint32_t>(kv.second.ids.size());
+  if (!s->stage[0].alloc_err(nopen) || !s->stage[1].alloc_err(nopen)) return QF_ERR_OOM;
+  s->sets_dirty = false;
+  return QF_OK;
+}
+
+// Take the next round from the queue (lock held): per filter the leading run
+// of requests with one operation; a filter with a skipped request takes no
+// later request in this round; requests of pending filters wait.
+Round form_round_locked(qf_server *s) {
+  Round rd;
+  std::map<int, int> fop;        // id -> operation taken this round
+  std::map<int, bool> blocked;   // id -> a request of it was skipped
+  std::map<std::pair<uint32_t, int>, size_t> part_of;
+  std::deque<Req *> rest;
+  for (Req *q : s->queue) {
+    Slot &sl = s->slots[q->id];
+    bool take = false;
+    if (q->op == OP_CLOSE) {
+      // after every earlier request of the filter has completed
+      take = !blocked[q->id] && fop.find(q->id) == fop.end();
+      if (take) rd.closes.push_back(q);
+      blocked[q->id] = true;
+      if (!take) rest.push_back(q);
+      continue;
+    }
+    if (sl.state == Slot::OPEN && !blocked[q->id]) {
+      auto it = fop.find(q->id);
+      take = it == fop.end() || it->second == q->op;
+      if (take) {
+        const auto key = std::make_pair(sl.r, q->op);
+        auto pit = part_of.find(key);
+        if (pit == part_of.end()) {
+          part_of[key] = rd.parts.size();
+          Part p;
+          p.r = sl.r;
+          p.op = q->op;
+          rd.parts.push_back(p);
+          pit = part_of.find(key);
+        }
+        Part &p = rd.parts[pit->second];
+        if (p.n + q->keys.size() > s->max_round) {
+          take = false;  // round full for this batch
+        } else {
+          fop[q->id] = q->op;
+          p.off.push_back(p.n);
+          p.reqs.push_back(q);
+          p.n += q->keys.size();
+        }
+      }
+    }
+    if (!take) {
+      blocked[q->id] = true;
+      rest.push_back(q);
+    }
+  }
+  // a stage holds all parts of a round back to back
+  uint64_t total = 0;
+  for (Part &p : rd.parts) total += p.n;
+  if (total > s->max_round) {
+    // keep whole parts while they fit; the rest goes back in order
+    uint64_t acc = 0;
+    std::vector<Part> keep;
+    std::vector<Req *> back;
+    for (Part &p : rd.parts) {
+      if (acc + p.n <= s->max_round) {
+        acc += p.n;
+        keep.push_back(p);
+      } else {
+        for (Req *q : p.reqs) back.push_back(q);
+      }
+    }
+    rd.parts = keep;
+    // requests put back keep their submission order relative to the rest
+    std::deque<Req *> merged;
+    std::vector<Req *> all(rest.begin(), rest.end());
+    all.insert(all.end(), back.begin(), back.end());
+    std::sort(all.begin(), all.end(), [](Req *a, Req *b) { return a->seq < b->seq; });
+    rest.assign(all.begin(), all.end());
+  }
+  s->queue.swap(rest);
+  // a round that closes filters is completed (and the sets rebuilt) before
+  // the next one is formed
+  if (!rd.closes.empty()) s->sets_dirty = true;
+  return rd;
+}
+
+// Enqueue a round on the stream (no waiting).
+int launch_round(qf_server *s, Round &rd, Stage &st) {
+  uint64_t base = 0;
+  for (Part &p : rd.parts) {
+    SetOf &so = s->sets[p.r];
+    for (size_t k = 0; k < p.reqs.size(); ++k) {
+      Req *q = p.reqs[k];
+      const uint64_t o = base + p.off[k];
+      std::memcpy(st.keys + o, q->keys.data(), q->keys.size() * 8);
+      std::fill(st.fid + o, st.fid + o + q->keys.size(), so.idx[q->id]);
+    }
+    base += p.n;
+  }
+  if (base) {
+    if (hipMemcpyAsync(st.d_keys, st.keys, base * 8, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipMemcpyAsync(st.d_fid, st.fid, base * 4, hipMemcpyHostToDevice, s->stream) != hipSuccess)
+      return QF_ERR_DEVICE;
+  }
+  base = 0;
+  for (Part &p : rd.parts) {
+    qf_set_t *set = s->sets[p.r].set;
+    const uint64_t *k = st.d_keys + base;
+    const uint32_t *f = st.d_fid + base;
+    int rc = QF_OK;
+    if (p.op == OP_INSERT) rc = qf_set_insert_batch(set, f, k, p.n, s->stream);
+    if (p.op == OP_DELETE) rc = qf_set_delete_batch(set, f, k, p.n, nullptr, s->stream);
+    if (p.op == OP_QUERY) {
+      rc = qf_set_query_batch(set, f, k, p.n, st.d_out8 + base, s->stream);
+      if (!rc && hipMemcpyAsync(st.out8 + base, st.d_out8 + base, p.n, hipMemcpyDeviceToHost, s->stream))
+        rc = QF_ERR_DEVICE;
+    }
+    if (p.op == OP_COUNT) {
+      rc = qf_set_count_batch(set, f, k, p.n, st.d_out64 + base, s->stream);
+      if (!rc && hipMemcpyAsync(st.out64 + base, st.d_out64 + base, p.n * 8, hipMemcpyDeviceToHost, s->stream))
+        rc = QF_ERR_DEVICE;
+    }
+    if (rc) return rc;
+    base += p.n;
+  }
+  // this round's per-filter errors, taken on the stream behind its updates
+  bool updates = false;
+  for (Part &p : rd.parts) updates |= p.op == OP_INSERT || p.op == OP_DELETE;
+  if (updates && st.nerr) {
+    uint32_t o = 0;
+    for (auto &kv : s->sets) {
+      if (qf::launch_take_errors(kv.second.set->pipe, st.d_err + o, s->stream) != hipSuccess) return QF_ERR_DEVICE;
+      o += static_cast<uint32_t>(kv.second.ids.size());
+    }
+    if (hipMemcpyAsync(st.h_err, st.d_err, st.nerr * 8, hipMemcpyDeviceToHost, s->stream) != hipSuccess)
+      return QF_ERR_DEVICE;
+  }
+  return hipEventRecord(st.done, s->stream) == hipSuccess ? QF_OK : QF_ERR_DEVICE;
+}
+
+// Wait for a launched round, copy outputs, set statuses, run its closes.
+void complete_round(qf_server *s, Round &rd, Stage &st, int launch_rc) {
+  if (!rd.parts.empty()) (void)hipEventSynchronize(st.done);
+  // per-filter errors of this round (updates only)
+  std::map<int, int> err;
+  bool updates = false;
+  for (Part &p : rd.parts) updates |= p.op == OP_INSERT || p.op == OP_DELETE;
+  if (updates && launch_rc == QF_OK && st.nerr) {
+    uint32_t o = 0;
+    for (auto &kv : s->sets) {
+      for (size_t i = 0; i < kv.second.ids.size(); ++i)
+        if (st.h_err[o + i]) err[kv.second.ids[i]] = static_cast<int>(st.h_err[o + i]);
+      o += static_cast<uint32_t>(kv.second.ids.size());
+    }
+  }
+  uint64_t base = 0;
+  for (Part &p : rd.parts) {
+    for (size_t k = 0; k < p.reqs.size(); ++k) {
+      Req *q = p.reqs[k];
+      const uint64_t o = base + p.off[k];
+      if (q->out && p.op == OP_QUERY) std::memcpy(q->out, st.out8 + o, q->keys.size());
+      if (q->out && p.op == OP_COUNT) std::memcpy(q->out, st.out64 + o, q->keys.size() * 8);
+      auto e = err.find(q->id);
+      q->status = launch_rc ? launch_rc : (e != err.end() && (p.op == OP_INSERT || p.op == OP_DELETE) ? e->second : QF_OK);
+    }
+    base += p.n;
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  for (Req *c : rd.closes) {
+    Slot &sl = s->slots[c->id];
+    if (sl.f) {
+      qf_destroy(sl.f);
+      sl.f = nullptr;
+      s->used -= sl.bytes;
+    }
+    sl.state = Slot::CLOSED;
+    c->status = QF_OK;
+    s->sets_dirty = true;
+  }
+  if (!rd.closes.empty()) admit_locked(s);
+  for (Part &p : rd.parts)
+    for (Req *q : p.reqs) {
+      s->done.push_back(q);
+      s->keys += q->keys.size();
+    }
+  for (Req *c : rd.closes) s->done.push_back(c);
+  s->requests += rd.closes.size();
+  for (Part &p : rd.parts) s->requests += p.reqs.size();
+  s->rounds += 1;
+  s->cv_done.notify_all();
+}
+
+void serve(qf_server *s) {
+  (void)hipSetDevice(s->device);
+  Round inflight;
+  int inflight_rc = QF_OK;
+  int cur = 0;
+  bool have = false;
+  for (;;) {
+    Round rd;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      if (!have)
+        s->cv_work.wait_for(lk, std::chrono::milliseconds(50), [s] { return s->stop || !s->queue.empty(); });
+      if (s->stop && s->queue.empty() && !have) break;
+      admit_locked(s);
+      if (s->sets_dirty && !have) {
+        lk.unlock();
+        (void)hipStreamSynchronize(s->stream);
+        (void)rebuild_sets(s);
+        lk.lock();
+      }
+      if (!s->sets_dirty) rd = form_round_locked(s);
+    }
+    int rc = QF_OK;
+    if (!rd.parts.empty()) rc = launch_round(s, rd, s->stage[cur]);
+    if (have) complete_round(s, inflight, s->stage[cur ^ 1], inflight_rc);
+    have = !rd.empty();
+    if (have) {
+      inflight = rd;
+      inflight_rc = rc;
+      cur ^= 1;
+    }
+  }
+  (void)hipStreamSynchronize(s->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+qfs_t *qfs_create(uint64_t budget_bytes, uint64_t max_round_keys) {
+  if (max_round_keys == 0 || max_round_keys > (1ull << 31)) return nullptr;
+  qf_server *s = new (std::nothrow) qf_server();
+  if (!s) return nullptr;
+  s->budget = budget_bytes;
+  s->max_round = max_round_keys;
+  (void)hipGetDevice(&s->device);
+  bool ok = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess &&
+            s->stage[0].alloc(max_round_keys) && s->stage[1].alloc(max_round_keys);
+  if (!ok) {
+    s->stage[0].release();
+    s->stage[1].release();
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+    return nullptr;
+  }
+  // the two stages and the sets' scratch (64 B per key, up to two sets)
+  s->used = 2 * max_round_keys * 21 + 2 * 64 * max_round_keys;
+  s->loop = std::thread(serve, s);
+  return s;
+}
+
+void qfs_destroy(qfs_t *s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  s->loop.join();
+  for (auto &kv : s->sets) qf_set_destroy(kv.second.set);
+  for (Slot &sl : s->slots)
+    if (sl.f) qf_destroy(sl.f);
+  for (Req *q : s->queue) delete q;
+  for (Req *q : s->done) delete q;
+  s->stage[0].release();
+  s->stage[1].release();
+  (void)hipStreamDestroy(s->stream);
+  delete s;
+}
+
+int qfs_open(qfs_t *s, uint32_t q, uint32_t r) {
+  if (!s || q < 6 || q > 31 || (r != 8 && r != 16)) return QF_ERR_ARG;
+  const uint64_t b = filter_bytes(q, r);
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (b > s->budget) return QF_ERR_BUDGET;
+  Slot sl;
+  sl.q = q;
+  sl.r = r;
+  sl.bytes = b;
+  s->slots.push_back(sl);
+  s->cv_work.notify_all();
+  return static_cast<int>(s->slots.size() - 1);
+}
+
+int qfs_submit(qfs_t *s, int op, int id, const uint64_t *h_keys, uint64_t n, void *h_out, uint64_t tag) {
+  if (!s || op < QFS_INSERT || op > QFS_COUNT || (n && !h_keys)) return QF_ERR_ARG;
+  if ((op == QFS_QUERY || op == QFS_COUNT) && n && !h_out) return QF_ERR_ARG;
+  Req *q = new (std::nothrow) Req();
+  if (!q) return QF_ERR_OOM;
+  q->op = op;
+  q->id = id;
+  q->out = h_out;
+  q->tag = tag;
+  q->status = QF_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (id < 0 || static_cast<size_t>(id) >= s->slots.size() || s->slots[id].state == Slot::CLOSED ||
+        s->slots[id].closing || n > s->max_round) {
+      delete q;
+      return QF_ERR_ARG;
+    }
+    q->keys.assign(h_keys, h_keys + n);
+    q->seq = s->seq++;
+    s->queue.push_back(q);
+  }
+  s->cv_work.notify_all();
+  return QF_OK;
+}
+
+int qfs_close(qfs_t *s, int id, uint64_t tag) {
+  if (!s) return QF_ERR_ARG;
+  Req *q = new (std::nothrow) Req();
+  if (!q) return QF_ERR_OOM;
+  q->op = OP_CLOSE;
+  q->id = id;
+  q->out = nullptr;
+  q->tag = tag;
+  q->status = QF_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (id < 0 || static_cast<size_t>(id) >= s->slots.size() || s->slots[id].closing ||
+        s->slots[id].state == Slot::CLOSED) {
+      delete q;
+      return QF_ERR_ARG;
+    }
+    s->slots[id].closing = true;
+    q->seq = s->seq++;
+    s->queue.push_back(q);
+  }
+  s->cv_work.notify_all();
+  return QF_OK;
+}
+
+int qfs_poll(qfs_t *s, uint64_t *tags, int32_t *status, uint32_t max, int wait_us) {
+  if (!s || (max && (!tags || !status))) return QF_ERR_ARG;
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (s->done.empty() && wait_us > 0)
+    s->cv_done.wait_for(lk, std::chrono::microseconds(wait_us), [s] { return !s->done.empty(); });
+  uint32_t k = 0;
+  while (k < max && !s->done.empty()) {
+    Req *q = s->done.front();
+    s->done.erase(s->done.begin());
+    tags[k] = q->tag;
+    status[k] = q->status;
+    delete q;
+    ++k;
+  }
+  return static_cast<int>(k);
+}
+
+int qfs_stats(qfs_t *s, uint64_t *st) {
+  if (!s || !st) return QF_ERR_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  uint64_t open = 0, pending = 0;
+  for (const Slot &sl : s->slots) {
+    open += sl.state == Slot::OPEN;
+    pending += sl.state == Slot::PENDING;
+  }
+  st[0] = s->rounds;
+  st[1] = s->requests;
+  st[2] = s->keys;
+  st[3] = open;
+  st[4] = pending;
+  st[5] = s->used;
+  st[6] = s->budget;
+  st[7] = s->queue.size();
+  return QF_OK;
+}
+
+}  // extern "C"

@@ -60,15 +60,27 @@ __global__ __launch_bounds__(NT) void k_hash_multi(const uint64_t *__restrict__ 
   }
 }
 
+__global__ __launch_bounds__(NT) void k_take_errors(const FDesc *__restrict__ desc, uint32_t nf,
+                                                    int64_t *__restrict__ err) {
+  const uint32_t f = blockIdx.x * NT + threadIdx.x;
+  if (f >= nf) return;
+  uint64_t *st = desc[f].state;
+  err[f] = static_cast<int64_t>(st[ST_ERR]);
+  st[ST_ERR] = 0;
+}
+
 __global__ __launch_bounds__(NT) void k_fill(uint64_t *p, uint64_t n, uint64_t v) {
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * NT;
   for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * NT + threadIdx.x; i < n; i += stride)
     p[i] = v;
 }
 
-// per-group digit histogram, stored digit-major: hist[d * G + g]
+// per-group digit histogram, stored digit-major: hist[d * G + g].  With HASH
+// the input is the raw keys and the sorted value is mix64(key) & pmask (the
+// hash is fused into the first pass).
+template <bool HASH>
 __global__ __launch_bounds__(NT) void k_rs_hist(const uint64_t *__restrict__ in, uint64_t n,
-                                                uint32_t G, uint32_t shift,
+                                                uint32_t G, uint32_t shift, uint64_t pmask,
                                                 uint32_t *__restrict__ hist) {
   __shared__ uint32_t h[NWAVE][256];
   const int tid = threadIdx.x, wv = tid >> 6;
@@ -77,7 +89,10 @@ __global__ __launch_bounds__(NT) void k_rs_hist(const uint64_t *__restrict__ in,
   __syncthreads();
   const uint32_t g = blockIdx.x;
   const uint64_t lo = chunk_lo(n, G, g), hi = chunk_lo(n, G, g + 1);
-  for (uint64_t i = lo + tid; i < hi; i += NT) atomicAdd(&h[wv][(in[i] >> shift) & 255u], 1u);
+  for (uint64_t i = lo + tid; i < hi; i += NT) {
+    const uint64_t v = HASH ? (mix64(in[i]) & pmask) : in[i];
+    atomicAdd(&h[wv][(v >> shift) & 255u], 1u);
+  }
   __syncthreads();
   for (int d = tid; d < 256; d += NT) {
     uint32_t t = 0;
@@ -146,14 +161,27 @@ __global__ __launch_bounds__(1024) void k_scan_u32(uint32_t *a, uint32_t n, uint
   if (tid == 1023 && total) *total = part[1023];
 }
 
-// stable scatter of one digit; each group walks its chunk 256 keys at a time
+// Stable scatter of one digit.  Each group takes its chunk in tiles of TILE
+// keys: the tile is ordered by digit in LDS (ranks from wave ballots, rounds
+// of 256 keys in index order, so the order is stable), then written out so
+// that each digit's keys of the tile land as one contiguous run -- coalesced
+// stores instead of one 8-byte store per key to a different line.
+constexpr int TILE = 4096;
+constexpr int KPL = TILE / NT;  // keys per lane and tile
+
+template <bool HASH>
 __global__ __launch_bounds__(NT) void k_rs_scatter(const uint64_t *__restrict__ in,
                                                    uint64_t *__restrict__ out, uint64_t n,
                                                    uint32_t G, uint32_t shift, uint32_t nbits,
+                                                   uint64_t pmask,
                                                    const uint32_t *__restrict__ hist,
                                                    const uint32_t *__restrict__ dtot) {
-  __shared__ uint32_t base[256];
+  __shared__ uint64_t tile[TILE];
+  __shared__ uint32_t gpos[256];  // global position of the group's next key of digit d
+  __shared__ uint32_t loff[256];  // start of digit d in the tile
+  __shared__ uint32_t placed[256];
   __shared__ uint32_t wc[NWAVE][256];
+  __shared__ uint32_t sh[NWAVE];
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const uint32_t g = blockIdx.x;
   {
@@ -164,46 +192,83 @@ __global__ __launch_bounds__(NT) void k_rs_scatter(const uint64_t *__restrict__ 
       const uint32_t t = __shfl_up(inc, o);
       if (lane >= o) inc += t;
     }
-    if (lane == 63) wc[0][wv] = inc;
+    if (lane == 63) sh[wv] = inc;
     __syncthreads();
     uint32_t ex = inc - v;
-    for (int w = 0; w < wv; ++w) ex += wc[0][w];
-    __syncthreads();
-    base[tid] = ex + hist[static_cast<uint64_t>(tid) * G + g];
+    for (int w = 0; w < wv; ++w) ex += sh[w];
+    gpos[tid] = ex + hist[static_cast<uint64_t>(tid) * G + g];
     for (int w = 0; w < NWAVE; ++w) wc[w][tid] = 0;
   }
-  __syncthreads();
   const uint64_t lo = chunk_lo(n, G, g), hi = chunk_lo(n, G, g + 1);
   const uint32_t dmask = (1u << nbits) - 1u;
-  for (uint64_t r0 = lo; r0 < hi; r0 += NT) {
-    const uint64_t i = r0 + tid;
-    const bool valid = i < hi;
-    const uint64_t key = valid ? in[i] : 0;
-    const uint32_t d = static_cast<uint32_t>(key >> shift) & dmask;
-    uint64_t peers = __ballot(valid);
-    for (uint32_t b = 0; b < nbits; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t bal = __ballot(bit);
-      peers &= bit ? bal : ~bal;
-    }
-    const uint32_t rank = static_cast<uint32_t>(popc64(peers & lanemask_lt()));
-    if (valid && rank == 0) wc[wv][d] = static_cast<uint32_t>(popc64(peers));
+  for (uint64_t t0 = lo; t0 < hi; t0 += TILE) {
+    const uint32_t cnt = static_cast<uint32_t>(min(static_cast<uint64_t>(TILE), hi - t0));
+    placed[tid] = 0;
     __syncthreads();
-    if (valid) {
-      uint32_t pos = base[d] + rank;
-      for (int w = 0; w < wv; ++w) pos += wc[w][d];
-      out[pos] = key;
-    }
-    __syncthreads();
-    for (int dd = tid; dd < 256; dd += NT) {
-      uint32_t t = 0;
-      for (int w = 0; w < NWAVE; ++w) {
-        t += wc[w][dd];
-        wc[w][dd] = 0;
+    uint64_t key[KPL];
+#pragma unroll
+    for (int k = 0; k < KPL; ++k) {
+      const uint32_t j = k * NT + tid;
+      key[k] = 0;
+      if (j < cnt) {
+        key[k] = HASH ? (mix64(in[t0 + j]) & pmask) : in[t0 + j];
+        atomicAdd(&placed[static_cast<uint32_t>(key[k] >> shift) & dmask], 1u);
       }
-      base[dd] += t;
     }
     __syncthreads();
+    {
+      // tile-local digit starts: exclusive scan of the tile's digit counts
+      const uint32_t v = placed[tid];
+      uint32_t inc = v;
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(inc, o);
+        if (lane >= o) inc += t;
+      }
+      if (lane == 63) sh[wv] = inc;
+      __syncthreads();
+      uint32_t ex = inc - v;
+      for (int w = 0; w < wv; ++w) ex += sh[w];
+      loff[tid] = ex;
+      placed[tid] = 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < KPL; ++k) {
+      const bool valid = static_cast<uint32_t>(k * NT + tid) < cnt;
+      const uint32_t d = static_cast<uint32_t>(key[k] >> shift) & dmask;
+      uint64_t peers = __ballot(valid);
+      for (uint32_t b = 0; b < nbits; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bal = __ballot(bit);
+        peers &= bit ? bal : ~bal;
+      }
+      const uint32_t rank = static_cast<uint32_t>(popc64(peers & lanemask_lt()));
+      if (valid && rank == 0) wc[wv][d] = static_cast<uint32_t>(popc64(peers));
+      __syncthreads();
+      if (valid) {
+        uint32_t pos = loff[d] + placed[d] + rank;
+        for (int w = 0; w < wv; ++w) pos += wc[w][d];
+        tile[pos] = key[k];
+      }
+      __syncthreads();
+      {
+        uint32_t t = 0;
+        for (int w = 0; w < NWAVE; ++w) {
+          t += wc[w][tid];
+          wc[w][tid] = 0;
+        }
+        placed[tid] += t;
+      }
+      __syncthreads();
+    }
+    // the tile in digit order -> each digit's run to its global place
+    for (uint32_t j = tid; j < cnt; j += NT) {
+      const uint64_t v = tile[j];
+      const uint32_t d = static_cast<uint32_t>(v >> shift) & dmask;
+      out[gpos[d] + (j - loff[d])] = v;
+    }
+    __syncthreads();
+    gpos[tid] += placed[tid];
   }
 }
 
@@ -322,6 +387,11 @@ hipError_t launch_hash_multi(const uint64_t *keys, const uint32_t *fid, uint64_t
   return hipGetLastError();
 }
 
+hipError_t launch_take_errors(const Pipe &p, int64_t *err, hipStream_t s) {
+  k_take_errors<<<(p.nf + NT - 1) / NT, NT, 0, s>>>(p.d_desc, p.nf, err);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s) {
   if (n == 0) return hipSuccess;
   k_fill<<<blocks_for(n), NT, 0, s>>>(p, n, v);
@@ -329,7 +399,7 @@ hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s) {
 }
 
 hipError_t launch_sort(uint64_t *a, uint64_t *b, uint64_t n, uint32_t bits, uint32_t *hist,
-                       uint64_t **result, hipStream_t s, Timer *t) {
+                       uint64_t **result, hipStream_t s, Timer *t, const uint64_t *raw, uint64_t pmask) {
   const uint32_t G = sort_groups(n);
   const uint32_t npass = (bits + 7) / 8;
   // digit totals live after the G * 256 histogram words
@@ -338,14 +408,22 @@ hipError_t launch_sort(uint64_t *a, uint64_t *b, uint64_t n, uint32_t bits, uint
   for (uint32_t p = 0; p < npass; ++p) {
     const uint32_t shift = 8 * p;
     const uint32_t nb = bits - shift < 8 ? bits - shift : 8;
+    // with raw keys the first pass hashes them itself (its output goes to b)
+    const bool hash = raw && p == 0;
     if (t) t->begin(QF_PROF_SORT_HIST, s);
-    k_rs_hist<<<G, NT, 0, s>>>(in, n, G, shift, hist);
+    if (hash)
+      k_rs_hist<true><<<G, NT, 0, s>>>(raw, n, G, shift, pmask, hist);
+    else
+      k_rs_hist<false><<<G, NT, 0, s>>>(in, n, G, shift, 0, hist);
     if (t) t->end(QF_PROF_SORT_HIST, s);
     if (t) t->begin(QF_PROF_SORT_SCAN, s);
     k_rs_offsets<<<256, NT, 0, s>>>(hist, G, dtot);
     if (t) t->end(QF_PROF_SORT_SCAN, s);
     if (t) t->begin(QF_PROF_SORT_SCATTER, s);
-    k_rs_scatter<<<G, NT, 0, s>>>(in, out, n, G, shift, nb, hist, dtot);
+    if (hash)
+      k_rs_scatter<true><<<G, NT, 0, s>>>(raw, out, n, G, shift, nb, pmask, hist, dtot);
+    else
+      k_rs_scatter<false><<<G, NT, 0, s>>>(in, out, n, G, shift, nb, 0, hist, dtot);
     if (t) t->end(QF_PROF_SORT_SCATTER, s);
     uint64_t *tmp = in;
     in = out;

@@ -25,6 +25,7 @@ QF_ERR_OOM = -3
 QF_ERR_DEVICE = -4
 QF_ERR_COUNT_OVERFLOW = -5
 QF_ERR_STALLED = -6
+QF_ERR_BUDGET = -7
 ERRORS = {
     QF_ERR_ARG: "QF_ERR_ARG",
     QF_ERR_FULL: "QF_ERR_FULL",
@@ -32,6 +33,7 @@ ERRORS = {
     QF_ERR_DEVICE: "QF_ERR_DEVICE",
     QF_ERR_COUNT_OVERFLOW: "QF_ERR_COUNT_OVERFLOW",
     QF_ERR_STALLED: "QF_ERR_STALLED",
+    QF_ERR_BUDGET: "QF_ERR_BUDGET",
 }
 
 
@@ -110,6 +112,14 @@ def lib() -> ctypes.CDLL:
         "qf_set_info": (i32, [vp, ctypes.POINTER(ctypes.c_uint64)]),
         "qf_set_profile_enable": (i32, [vp, i32]),
         "qf_set_profile_read": (i32, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64)]),
+        "qf_set_errors": (i32, [vp, ctypes.POINTER(ctypes.c_int32), vp]),
+        "qfs_create": (vp, [u64, u64]),
+        "qfs_destroy": (None, [vp]),
+        "qfs_open": (i32, [vp, u32, u32]),
+        "qfs_submit": (i32, [vp, i32, i32, vp, u64, vp, u64]),
+        "qfs_close": (i32, [vp, i32, u64]),
+        "qfs_poll": (i32, [vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int32), u32, i32]),
+        "qfs_stats": (i32, [vp, ctypes.POINTER(ctypes.c_uint64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -417,3 +427,71 @@ class CQFSet:
 
     def reserve(self, n: int, stream=None):
         _check(lib().qf_set_reserve(self.h, n, _stream(stream)), "qf_set_reserve")
+
+
+# ---- serving --------------------------------------------------------------
+QFS_INSERT, QFS_DELETE, QFS_QUERY, QFS_COUNT = 0, 1, 2, 3
+
+
+class Server:
+    """Device-resident filters answering host requests with continuous batching (qfs_* calls).
+    Keys are host numpy uint64 arrays; outputs are host numpy arrays kept alive until completion."""
+
+    def __init__(self, budget_bytes: int, max_round_keys: int = 1 << 22):
+        self.h = lib().qfs_create(budget_bytes, max_round_keys)
+        if not self.h:
+            raise QFError(QF_ERR_OOM, "qfs_create")
+        self._live = {}  # tag -> (keys, out) kept alive until polled
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().qfs_destroy(self.h)
+            self.h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def open(self, q: int, r: int) -> int:
+        rc = lib().qfs_open(self.h, q, r)
+        if rc < 0:
+            raise QFError(rc, f"qfs_open({q}, {r})")
+        return rc
+
+    def submit(self, op: int, fid: int, keys: np.ndarray, tag: int) -> np.ndarray | None:
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        n = len(keys)
+        out = None
+        if op == QFS_QUERY:
+            out = np.zeros(n, np.uint8)
+        elif op == QFS_COUNT:
+            out = np.zeros(n, np.uint64)
+        rc = lib().qfs_submit(self.h, op, fid, keys.ctypes.data if n else None, n,
+                              out.ctypes.data if out is not None and n else None, tag)
+        _check(rc, "qfs_submit")
+        self._live[tag] = (keys, out)
+        return out
+
+    def close_filter(self, fid: int, tag: int):
+        _check(lib().qfs_close(self.h, fid, tag), "qfs_close")
+        self._live[tag] = (None, None)
+
+    def poll(self, max_n: int = 4096, wait_us: int = 1000) -> list[tuple[int, int]]:
+        tags = (ctypes.c_uint64 * max_n)()
+        st = (ctypes.c_int32 * max_n)()
+        k = lib().qfs_poll(self.h, tags, st, max_n, wait_us)
+        if k < 0:
+            raise QFError(k, "qfs_poll")
+        res = [(int(tags[i]), int(st[i])) for i in range(k)]
+        for t, _ in res:
+            self._live.pop(t, None)
+        return res
+
+    def stats(self) -> dict:
+        buf = (ctypes.c_uint64 * 8)()
+        _check(lib().qfs_stats(self.h, buf), "qfs_stats")
+        keys = ("rounds", "requests", "keys", "open", "pending", "bytes_used", "budget", "waiting")
+        return dict(zip(keys, (int(v) for v in buf)))
