@@ -164,6 +164,7 @@ int pipe_init(qf::Pipe &p, qf_filter *const *fs, uint32_t nf) {
     pipe_free(p);
     return fail(QF_ERR_OOM);
   }
+  p.one = desc[0];
   p.rstat = p.tags + 3ull * G;
   p.cb = reinterpret_cast<int64_t *>(p.tags + 7ull * G);
   p.device_bytes = nf * sizeof(qf::FDesc) + G * 4 + (G + 1) * 8 + tag_words * 8 + qf::ST_WORDS * 8 +

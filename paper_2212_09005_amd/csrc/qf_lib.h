@@ -34,6 +34,7 @@ struct Pipe {
   uint32_t nf = 0, G = 0, RL = 0, r = 0;
   uint32_t gbits = 0;         // bits of a global region index
   FDesc *d_desc = nullptr;    // nf
+  FDesc one;                  // host copy of the descriptor when nf == 1
   uint32_t *d_rmap = nullptr; // G: global region -> filter
   uint64_t *rb = nullptr;     // G + 1 region bounds into the reduced batch
   uint64_t *tags = nullptr;   // 3 G look-back words, then

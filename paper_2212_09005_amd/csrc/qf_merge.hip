@@ -43,6 +43,16 @@ namespace {
 constexpr int NT = 256;
 constexpr int64_t INF = INT64_MAX / 4;
 
+// pointer to global memory (address space 1): loads and stores through it
+// compile to global_* instructions instead of generic flat ones
+template <typename U>
+using GPtr = __attribute__((address_space(1))) U *;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));  // 16 bytes, no class methods
+template <typename U>
+__device__ __forceinline__ GPtr<U> to_global(U *p) {
+  return (GPtr<U>)p;  // (a cast between address spaces; no reinterpret_cast for it)
+}
+
 template <typename T>
 struct Cfg {
   // largest region: 8192 slots (r = 8), 4096 (r = 16); the LDS buffers hold
@@ -68,6 +78,7 @@ __device__ __forceinline__ Fn32 f32_then(Fn32 g, Fn32 h) { return Fn32{max(h.A, 
 // One merge launch over the G regions of a pipeline (all filters of a set, or
 // one filter); a work-group finds its filter through rmap and desc.
 struct MergeArgs {
+  FDesc one;  // the filter of a one-filter pipeline (read from the kernel arguments)
   const FDesc *desc;
   const uint32_t *rmap;
   const uint64_t *ufp, *ucnt, *rb;  // composite keys, counts, region bounds
@@ -757,41 +768,63 @@ __device__ int64_t look_back_wave(const uint64_t *tags, uint32_t nreg, uint32_t 
   }
 }
 
+// The kernel's LDS arrays, handed to the region body.
 template <typename T>
-__global__ __launch_bounds__(NT) void k_merge(MergeArgs a) {
-  using C = Cfg<T>;
-  __shared__ __align__(16) T old_s[C::CAP];
-  __shared__ __align__(16) T new_s[C::CAP];
-  __shared__ uint64_t old_b[C::CAPW];
-  __shared__ uint64_t new_b[C::CAPW];
-  __shared__ uint32_t old_wp[C::CAPW + 1];
-  __shared__ uint64_t occ_l[C::OW];
-  // quotients that receive new entries; reused for the new occupied bits of
-  // the one-lane path
-  __shared__ uint64_t chg_l[C::OW];
-  // the region's new entries, and its changed runs (one per distinct
-  // quotient), in LDS when there are at most NCAP entries, else in the
-  // launch's per-entry scratch
-  __shared__ uint32_t nfp_l[C::NCAP];
-  __shared__ uint32_t ncnt_l[C::NCAP];
-  __shared__ uint16_t cxr_l[C::NCAP];   // quotient - RS
-  __shared__ uint32_t chead_l[C::NCAP]; // first entry
-  __shared__ uint16_t cop_l[C::NCAP];   // old run, staged indexes (coe 0xFFFF: none)
-  __shared__ uint16_t coe_l[C::NCAP];
-  __shared__ uint32_t cL_l[C::NCAP];    // new length
-  __shared__ uint16_t cst_l[C::NCAP];   // new first slot, output index
-  __shared__ Fn32 gaf_l[C::NCAP];       // maps of the unchanged runs after it
-  __shared__ int64_t sh_i[8];
-  __shared__ Fn sh_fn[NT / 64];
-  __shared__ uint32_t sh_u[2 * NT / 64];
-  __shared__ uint64_t sh_r[NT / 64];
+struct Smem {
+  T *old_s;
+  T *new_s;
+  uint64_t *old_b;
+  uint64_t *new_b;
+  uint32_t *old_wp;
+  uint64_t *occ_l;
+  uint64_t *chg_l;
+  uint32_t *nfp_l;
+  uint32_t *ncnt_l;
+  uint16_t *cxr_l;
+  uint32_t *chead_l;
+  uint16_t *cop_l;
+  uint16_t *coe_l;
+  uint32_t *cL_l;
+  uint16_t *cst_l;
+  Fn32 *gaf_l;
+  int64_t *sh_i;
+  Fn *sh_fn;
+  uint32_t *sh_u;
+  uint64_t *sh_r;
+};
 
+// One region (see k_merge).  SMALL: the region's entries fit the LDS arrays.
+template <typename T, bool SINGLE, bool SMALL>
+__device__ __forceinline__ void merge_body(const MergeArgs &a, const Smem<T> &m) {
+  using C = Cfg<T>;
+  T *const old_s = m.old_s;
+  T *const new_s = m.new_s;
+  uint64_t *const old_b = m.old_b;
+  uint64_t *const new_b = m.new_b;
+  uint32_t *const old_wp = m.old_wp;
+  uint64_t *const occ_l = m.occ_l;
+  uint64_t *const chg_l = m.chg_l;
+  uint32_t *const nfp_l = m.nfp_l;
+  uint32_t *const ncnt_l = m.ncnt_l;
+  uint16_t *const cxr_l = m.cxr_l;
+  uint32_t *const chead_l = m.chead_l;
+  uint16_t *const cop_l = m.cop_l;
+  uint16_t *const coe_l = m.coe_l;
+  uint32_t *const cL_l = m.cL_l;
+  uint16_t *const cst_l = m.cst_l;
+  Fn32 *const gaf_l = m.gaf_l;
+  int64_t *const sh_i = m.sh_i;
+  Fn *const sh_fn = m.sh_fn;
+  uint32_t *const sh_u = m.sh_u;
+  uint64_t *const sh_r = m.sh_r;
   const int tid = threadIdx.x;
   // global region = work-group index (no shared ticket counter: one atomic
   // per work-group on one address serialises the whole launch); the filter
   // and its local region R follow from the pipeline's region map
   const uint32_t gR = blockIdx.x;
-  const FDesc &fd = a.desc[a.rmap[gR]];
+  // (a one-filter pipeline takes its descriptor from the kernel arguments,
+  // saving two dependent loads before the region's first load)
+  const FDesc &fd = SINGLE ? a.one : a.desc[a.rmap[gR]];
   const int64_t R = gR - fd.rbase;
   const uint32_t rlog = fd.rlog;
   const int64_t FN = fd.N, FP = fd.P, FNB = fd.nblocks;
@@ -804,6 +837,13 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs a) {
   const Block<T> *ob = static_cast<const Block<T> *>(cur ? fd.blk[1] : fd.blk[0]);
   Block<T> *nbk = static_cast<Block<T> *>(cur ? fd.blk[0] : fd.blk[1]);
   uint32_t *noff = cur ? fd.off[0] : fd.off[1];
+  // the same pointers typed as global memory for the hot loads and stores
+  // (they come from a descriptor in memory, so the compiler cannot tell)
+  const GPtr<const Block<T>> gob = to_global(ob);
+  const GPtr<Block<T>> gnbk = to_global(nbk);
+  const GPtr<uint32_t> gnoff = to_global(noff);
+  const GPtr<const uint64_t> gufp = to_global(a.ufp);
+  const GPtr<const uint64_t> gucnt = to_global(a.ucnt);
   const bool qreg = RS < FN;
   const int64_t send = min(RS + S, FP);
   const int nw_reg = static_cast<int>((send - RS + 63) >> 6);
@@ -813,26 +853,27 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs a) {
   const uint64_t lmask = (1ull << (rlog + r)) - 1ull;  // fingerprint bits inside the region
 
   for (int w = tid; w < nw_reg; w += NT) {
-    occ_l[w] = qreg ? ob[(RS >> 6) + w].occ : 0ull;
+    occ_l[w] = qreg ? gob[(RS >> 6) + w].occ : 0ull;
     chg_l[w] = 0ull;
   }
   for (int w = tid; w < C::CAPW; w += NT) new_b[w] = 0ull;
   for (int i = tid; i < C::CAP * static_cast<int>(sizeof(T)) / 16; i += NT)
     reinterpret_cast<uint4 *>(new_s)[i] = make_uint4(0u, 0u, 0u, 0u);
-  const bool small = ne <= static_cast<uint64_t>(C::NCAP);
-  uint32_t *const nfp = small ? nfp_l : a.g_fp + rb0;
-  uint32_t *const ncnt = small ? ncnt_l : a.g_cnt + rb0;
-  uint16_t *const cxr = small ? cxr_l : a.g_xr + rb0;
-  uint32_t *const chead = small ? chead_l : a.g_head + rb0;
-  uint16_t *const cop = small ? cop_l : a.g_op + rb0;
-  uint16_t *const coe = small ? coe_l : a.g_oe + rb0;
-  uint32_t *const cL = small ? cL_l : a.g_L + rb0;
-  uint16_t *const cst = small ? cst_l : a.g_st + rb0;
-  Fn32 *const gaf = small ? gaf_l : a.g_gaf + rb0;
+  // (SMALL is a template argument, so the LDS case compiles to LDS
+  // instructions rather than generic ones)
+  uint32_t *const nfp = SMALL ? nfp_l : a.g_fp + rb0;
+  uint32_t *const ncnt = SMALL ? ncnt_l : a.g_cnt + rb0;
+  uint16_t *const cxr = SMALL ? cxr_l : a.g_xr + rb0;
+  uint32_t *const chead = SMALL ? chead_l : a.g_head + rb0;
+  uint16_t *const cop = SMALL ? cop_l : a.g_op + rb0;
+  uint16_t *const coe = SMALL ? coe_l : a.g_oe + rb0;
+  uint32_t *const cL = SMALL ? cL_l : a.g_L + rb0;
+  uint16_t *const cst = SMALL ? cst_l : a.g_st + rb0;
+  Fn32 *const gaf = SMALL ? gaf_l : a.g_gaf + rb0;
   if (ne < (1ull << 31)) {
     for (uint32_t i = tid; i < ne; i += NT) {
-      nfp[i] = static_cast<uint32_t>(a.ufp[rb0 + i] & lmask);
-      ncnt[i] = static_cast<uint32_t>(a.ucnt[rb0 + i]);
+      nfp[i] = static_cast<uint32_t>(gufp[rb0 + i] & lmask);
+      ncnt[i] = static_cast<uint32_t>(gucnt[rb0 + i]);
     }
   }
   __syncthreads();
@@ -850,11 +891,11 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs a) {
     // 16-byte chunks of the staged blocks' slots, then their run-end words
     for (int idx = tid; idx < nblk * C::CH; idx += NT) {
       const int b = idx / C::CH, c = idx % C::CH;
-      const uint4 v = reinterpret_cast<const uint4 *>(ob[bb + b].s)[c];
-      reinterpret_cast<uint4 *>(old_s + b * 64)[c] = v;
+      const u32x4 v = reinterpret_cast<GPtr<const u32x4>>(gob[bb + b].s)[c];
+      reinterpret_cast<u32x4 *>(old_s + b * 64)[c] = v;
     }
     for (int w = tid; w < nblk; w += NT) {
-      uint64_t v = ob[bb + w].rend;
+      uint64_t v = gob[bb + w].rend;
       if (w == 0) v &= ~0ull << (lo_old & 63);
       if (w == nblk - 1) v &= ~0ull >> (63 - (hi_old & 63));
       old_b[w] = v;
@@ -1039,18 +1080,18 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs a) {
         ct0 = lane_walk<true, T>(t0, occ_c, chg_c, obr, ope0, ce, c0, cop, coe, gaf, df, du, cL, cst, old_s,
                                  new_s, new_b, xb, carry, nocc);
       }
-      if ((t0 & 63) == 0) noff[(RS + t0) >> 6] = static_cast<uint32_t>(max(ct0 - t0, 0));
+      if ((t0 & 63) == 0) gnoff[(RS + t0) >> 6] = static_cast<uint32_t>(max(ct0 - t0, 0));
     }
     if (qreg) {
       // the new occupied words: OR the chunks of each 64-quotient word into
       // its first lane (all lanes take part in the shuffles)
       uint64_t wv = chunk ? static_cast<uint64_t>(nocc) << (t0 & 63) : 0ull;
       for (int d = 1; d < 64 / QT; d <<= 1) wv |= __shfl_down(wv, d);
-      if (chunk && (t0 & 63) == 0) nbk[(RS + t0) >> 6].occ = wv;
+      if (chunk && (t0 & 63) == 0) gnbk[(RS + t0) >> 6].occ = wv;
     } else {
       for (int w = tid; w < nw_reg; w += NT) {
-        nbk[(RS >> 6) + w].occ = 0ull;
-        noff[(RS >> 6) + w] = static_cast<uint32_t>(max(c_in - (RS + 64ll * w), static_cast<int64_t>(0)));
+        gnbk[(RS >> 6) + w].occ = 0ull;
+        gnoff[(RS >> 6) + w] = static_cast<uint32_t>(max(c_in - (RS + 64ll * w), static_cast<int64_t>(0)));
       }
     }
     __syncthreads();
@@ -1072,10 +1113,10 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs a) {
       const int b = idx / C::CH, c = idx % C::CH;
       const int64_t p0 = xbase + b * 64 + c * C::PER;
       const int64_t p1 = p0 + C::PER - 1;
-      T *dst = nbk[(xbase >> 6) + b].s + c * C::PER;
+      GPtr<T> dst = gnbk[(xbase >> 6) + b].s + c * C::PER;
       const T *src = new_s + b * 64 + c * C::PER;
       if (p0 >= ext_lo && p1 <= ext_hi) {
-        *reinterpret_cast<uint4 *>(dst) = *reinterpret_cast<const uint4 *>(src);
+        *reinterpret_cast<GPtr<u32x4>>(dst) = *reinterpret_cast<const u32x4 *>(src);
       } else {
         for (int k = 0; k < C::PER; ++k)
           if (p0 + k >= ext_lo && p0 + k <= ext_hi) dst[k] = src[k];
@@ -1087,7 +1128,7 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs a) {
       const uint64_t mask = (~0ull >> (63 - (phi & 63))) & (~0ull << (plo & 63));
       const uint64_t v = new_b[b] & mask;
       if (mask == ~0ull) {
-        nbk[w].rend = v;
+        gnbk[w].rend = v;
       } else {
         atomic_and_u64(&nbk[w].rend, ~mask);
         atomic_or_u64(&nbk[w].rend, v);
@@ -1106,6 +1147,42 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs a) {
     __syncthreads();
     for (int w = tid; w < nw_reg; w += NT) nbk[(RS >> 6) + w].occ = chg_l[w];
   }
+}
+
+template <typename T, bool SINGLE>
+__global__ __launch_bounds__(NT) void k_merge(MergeArgs a) {
+  using C = Cfg<T>;
+  __shared__ __align__(16) T old_s[C::CAP];
+  __shared__ __align__(16) T new_s[C::CAP];
+  __shared__ uint64_t old_b[C::CAPW];
+  __shared__ uint64_t new_b[C::CAPW];
+  __shared__ uint32_t old_wp[C::CAPW + 1];
+  __shared__ uint64_t occ_l[C::OW];
+  // quotients that receive new entries; reused for the new occupied bits of
+  // the one-lane path
+  __shared__ uint64_t chg_l[C::OW];
+  // the region's new entries, and its changed runs (one per distinct
+  // quotient), in LDS when there are at most NCAP entries, else in the
+  // launch's per-entry scratch
+  __shared__ uint32_t nfp_l[C::NCAP];
+  __shared__ uint32_t ncnt_l[C::NCAP];
+  __shared__ uint16_t cxr_l[C::NCAP];   // quotient - RS
+  __shared__ uint32_t chead_l[C::NCAP]; // first entry
+  __shared__ uint16_t cop_l[C::NCAP];   // old run, staged indexes (coe 0xFFFF: none)
+  __shared__ uint16_t coe_l[C::NCAP];
+  __shared__ uint32_t cL_l[C::NCAP];    // new length
+  __shared__ uint16_t cst_l[C::NCAP];   // new first slot, output index
+  __shared__ Fn32 gaf_l[C::NCAP];       // maps of the unchanged runs after it
+  __shared__ int64_t sh_i[8];
+  __shared__ Fn sh_fn[NT / 64];
+  __shared__ uint32_t sh_u[2 * NT / 64];
+  __shared__ uint64_t sh_r[NT / 64];
+
+  const Smem<T> m{old_s, new_s, old_b, new_b, old_wp, occ_l, chg_l, nfp_l, ncnt_l, cxr_l, chead_l, cop_l, coe_l, cL_l, cst_l, gaf_l, sh_i, sh_fn, sh_u, sh_r};
+  if (a.rb[blockIdx.x + 1] - a.rb[blockIdx.x] <= static_cast<uint64_t>(C::NCAP))
+    merge_body<T, SINGLE, true>(a, m);
+  else
+    merge_body<T, SINGLE, false>(a, m);
 }
 
 // After the merge, one work-group per filter: sum its regions' statistics;
@@ -1173,7 +1250,12 @@ hipError_t launch_merge_t(Pipe &p, const uint64_t *ufp, const uint64_t *ucnt, in
   a.g_st = reinterpret_cast<uint16_t *>(e + 30 * cap);
   if (p.timer) p.timer->begin(QF_PROF_MERGE, s);
   k_carries<T><<<(p.G + NT - 1) / NT, NT, 0, s>>>(p.d_desc, p.d_rmap, p.G, wrap, p.tags, p.cb);
-  k_merge<T><<<p.G, NT, 0, s>>>(a);
+  if (p.nf == 1) {
+    a.one = p.one;
+    k_merge<T, true><<<p.G, NT, 0, s>>>(a);
+  } else {
+    k_merge<T, false><<<p.G, NT, 0, s>>>(a);
+  }
   k_finish<<<p.nf, 1024, 0, s>>>(p.d_desc, p.rstat, del, not_found);
   if (p.timer) p.timer->end(QF_PROF_MERGE, s);
   return hipGetLastError();
