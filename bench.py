@@ -352,6 +352,48 @@ def bench_zipf(args) -> dict:
             "delete_Bps": round(len(dk) / t_del / 1e9, 4), "device_bytes": info["device_bytes"]}
 
 
+def bench_fill(args) -> dict:
+    """One big batch (the paper's bulk set-up): insert 0.9 * 2^q distinct uniform keys into an empty
+    filter (2^28 quotients, r = 8) as one batch, then query 2^22 keys (half present, half absent)."""
+    import torch
+
+    from paper_2212_09005_amd import inputs, qf
+
+    q, r = args.q, 8
+    n = int(0.9 * (1 << q))
+    keys = inputs.uniform_keys(1, n)
+    f = qf.CQF(q, r)
+    f.reserve(n)
+    d = torch.from_numpy(keys.view(np.int64)).to("cuda")
+    times = []
+    for rep in range(2):  # the second run on a fresh filter is the one reported
+        if rep:
+            f.close()
+            f = qf.CQF(q, r)
+            f.reserve(n)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f.insert(d)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        assert f.sync() == 0
+    m = 1 << 22
+    qk = inputs.mixed_queries(2000, keys, m // 2, m - m // 2)
+    dq = torch.from_numpy(qk.view(np.int64)).to("cuda")
+    out = torch.empty(m, dtype=torch.uint8, device="cuda")
+    f.query(dq, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f.query(dq, out)
+    torch.cuda.synchronize()
+    tq = time.perf_counter() - t0
+    f.close()
+    return {"metric": "one-batch bulk insert (empty to load 0.9), then query", "value": round(n / times[-1] / 1e9, 4),
+            "unit": "B inserts/s", "n_gpus": 1, "higher_is_better": True, "dtype": "u64", "data": "synthetic",
+            "config": {"workload": f"cqf_q{q}_r8_one_batch_fill_0.9", "q": q, "r": r, "keys": n},
+            "insert_s": round(times[-1], 4), "query_Bps": round(m / tq / 1e9, 4)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -361,9 +403,10 @@ def main() -> int:
     ap.add_argument("--load", type=float, default=0.9)
     ap.add_argument("--batch-log2", type=int, default=22)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["c2", "sweep", "zipf", "c4"], default="c2",
-                    help="c2: the single-filter step (default); sweep: load sweep to 0.95; zipf: one-batch "
-                         "counting with skew (2^30, r=16); c4: many filters, set vs per-filter loop")
+    ap.add_argument("--workload", choices=["c2", "sweep", "fill", "zipf", "c4"], default="c2",
+                    help="c2: the single-filter step (default); sweep: load sweep to 0.95; fill: one-batch fill "
+                         "to 0.9; zipf: one-batch counting with skew (2^30, r=16); c4: many filters, set vs "
+                         "per-filter loop")
     ap.add_argument("--zipf-scale", type=int, default=0)
     ap.add_argument("--sets-filters", type=int, default=4096)
     ap.add_argument("--sets-query-log2", type=int, default=24)
@@ -384,7 +427,7 @@ def main() -> int:
     if args.workload != "c2":
         assert torch.cuda.is_available(), "bench.py needs a GPU"
         torch.cuda.set_device(0)
-        fn = {"c4": bench_sets, "sweep": bench_sweep, "zipf": bench_zipf}[args.workload]
+        fn = {"c4": bench_sets, "sweep": bench_sweep, "fill": bench_fill, "zipf": bench_zipf}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return 0
 
