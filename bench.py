@@ -394,6 +394,127 @@ def bench_fill(args) -> dict:
             "insert_s": round(times[-1], 4), "query_Bps": round(m / tq / 1e9, 4)}
 
 
+def bench_serve(args) -> dict:
+    """Serving: 256 device-resident filters (2^18..2^26 quotients, r = 8 or 16), filled to load 0.5,
+    answer Poisson arrivals of mixed requests (70 % query, 25 % insert, 5 % delete) with sizes
+    log-uniform in 1..65,536 keys, HBM budget 64 GB.  A saturation run measures capacity; then
+    arrivals at 25 / 50 / 90 % of it give ops/s and p50 / p99 latency (submission to completion)."""
+    import threading
+
+    from paper_2212_09005_amd import inputs, qf
+
+    rng = np.random.Generator(np.random.PCG64(55))
+    nf = args.serve_filters
+    qs = rng.integers(18, 27, size=nf)
+    rs = np.where(rng.random(nf) < 0.5, 8, 16)
+    srv = qf.Server(64 << 30, max_round_keys=1 << 22)
+    ids = [srv.open(int(q), int(r)) for q, r in zip(qs, rs)]
+    cap_keys = np.array([int(0.95 * (1 << int(q))) for q in qs])
+    fill = [inputs.uniform_keys(7000 + i, int(0.5 * (1 << int(q)))) for i, q in enumerate(qs)]
+    count = np.array([len(k) for k in fill])
+    tag = 0
+    for i, k in enumerate(fill):
+        for a in range(0, len(k), 1 << 22):
+            srv.submit(qf.QFS_INSERT, ids[i], k[a:a + (1 << 22)], tag)
+            tag += 1
+    got = 0
+    while got < tag:
+        got += len(srv.poll(4096, 100000))
+    log(f"serve: {nf} filters filled to 0.5 ({int(count.sum())} keys)")
+    pool = np.concatenate(fill)
+    pool_off = np.concatenate([[0], np.cumsum(count)])
+
+    def make_requests(nreq, seed):
+        g = np.random.Generator(np.random.PCG64(seed))
+        ops = g.choice(3, size=nreq, p=[0.70, 0.25, 0.05])
+        sizes = np.floor(2.0 ** g.uniform(0, 16, size=nreq)).astype(np.int64)
+        fids = g.integers(0, nf, size=nreq)
+        reqs = []
+        for k in range(nreq):
+            f, n = int(fids[k]), int(sizes[k])
+            if ops[k] == 1:  # insert, rerouted when the filter would pass load 0.95
+                if count[f] + n > cap_keys[f]:
+                    room = np.nonzero(count + n <= cap_keys)[0]
+                    if len(room) == 0:
+                        ops[k] = 0
+                    else:
+                        f = int(room[g.integers(0, len(room))])
+                if ops[k] == 1:
+                    keys = inputs.uniform_keys(seed * 1_000_003 + k, n)
+                    count[f] += n
+                    reqs.append((qf.QFS_INSERT, f, keys))
+                    continue
+            if ops[k] == 2:  # delete present keys
+                keys = pool[pool_off[f] + g.integers(0, pool_off[f + 1] - pool_off[f], size=n)]
+                reqs.append((qf.QFS_DELETE, f, keys))
+                continue
+            half = n // 2
+            keys = np.concatenate([pool[pool_off[f] + g.integers(0, pool_off[f + 1] - pool_off[f], size=n - half)],
+                                   inputs.absent_keys(seed * 7 + k, half)])
+            reqs.append((qf.QFS_QUERY, f, keys))
+        return reqs
+
+    def run(reqs, rate):
+        """Submit reqs with Poisson arrivals at `rate` requests/s (None = as fast as possible)."""
+        nonlocal tag
+        sub = {}
+        lat = []
+        done = threading.Event()
+        base_tag = tag
+
+        def poller():
+            left = len(reqs)
+            while left:
+                for t, st in srv.poll(4096, 2000):
+                    lat.append(time.perf_counter() - sub[t])
+                    left -= 1
+            done.set()
+
+        th = threading.Thread(target=poller)
+        g = np.random.Generator(np.random.PCG64(99))
+        gaps = g.exponential(1.0 / rate, size=len(reqs)) if rate else np.zeros(len(reqs))
+        t_start = time.perf_counter()
+        t_next = t_start
+        th.start()
+        for k, (op, f, keys) in enumerate(reqs):
+            t_next += gaps[k]
+            while rate and time.perf_counter() < t_next:
+                pass
+            t = base_tag + k
+            sub[t] = time.perf_counter()
+            srv.submit(op, ids[f], keys, t)
+        done.wait()
+        th.join()
+        t_end = time.perf_counter()
+        tag = base_tag + len(reqs)
+        nkeys = sum(len(k) for _, _, k in reqs)
+        lat_ms = np.array(lat) * 1e3
+        return {"requests": len(reqs), "keys": nkeys, "seconds": round(t_end - t_start, 4),
+                "Bps": round(nkeys / (t_end - t_start) / 1e9, 4),
+                "req_per_s": round(len(reqs) / (t_end - t_start), 1),
+                "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+                "p99_ms": round(float(np.percentile(lat_ms, 99)), 3)}
+
+    nreq = args.serve_requests
+    sat = run(make_requests(nreq, 1), None)
+    log(f"serve saturation: {sat}")
+    cap_rps = sat["req_per_s"]
+    points = []
+    for frac in (0.25, 0.5, 0.9):
+        r_ = run(make_requests(nreq, 2 + int(frac * 100)), frac * cap_rps)
+        r_["offered_frac"] = frac
+        points.append(r_)
+        log(f"serve at {frac:.0%} of capacity: {r_}")
+    st = srv.stats()
+    srv.close()
+    return {"metric": "serving: mixed request throughput and latency (256 filters, 2^18..2^26, r=8/16)",
+            "value": sat["Bps"], "unit": "B keys/s at saturation", "n_gpus": 1, "higher_is_better": True,
+            "dtype": "u64", "data": "synthetic",
+            "config": {"workload": f"serve_{nf}filters_q18to26_r8or16_mix70q25i5d", "filters": nf,
+                       "requests_per_run": nreq, "budget_bytes": 64 << 30},
+            "saturation": sat, "points": points, "server": st}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -403,10 +524,12 @@ def main() -> int:
     ap.add_argument("--load", type=float, default=0.9)
     ap.add_argument("--batch-log2", type=int, default=22)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["c2", "sweep", "fill", "zipf", "c4"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "sweep", "fill", "zipf", "c4", "serve"], default="c2",
                     help="c2: the single-filter step (default); sweep: load sweep to 0.95; fill: one-batch fill "
                          "to 0.9; zipf: one-batch counting with skew (2^30, r=16); c4: many filters, set vs "
-                         "per-filter loop")
+                         "per-filter loop; serve: the serving loop")
+    ap.add_argument("--serve-filters", type=int, default=256)
+    ap.add_argument("--serve-requests", type=int, default=4000)
     ap.add_argument("--zipf-scale", type=int, default=0)
     ap.add_argument("--sets-filters", type=int, default=4096)
     ap.add_argument("--sets-query-log2", type=int, default=24)
@@ -427,7 +550,8 @@ def main() -> int:
     if args.workload != "c2":
         assert torch.cuda.is_available(), "bench.py needs a GPU"
         torch.cuda.set_device(0)
-        fn = {"c4": bench_sets, "sweep": bench_sweep, "fill": bench_fill, "zipf": bench_zipf}[args.workload]
+        fn = {"c4": bench_sets, "sweep": bench_sweep, "fill": bench_fill, "zipf": bench_zipf,
+              "serve": bench_serve}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return 0
 

@@ -179,6 +179,15 @@ int qf_set_insert_batch(qf_set_t *s, const uint32_t *d_fid, const uint64_t *d_ke
  * d_not_found[i]), or NULL. */
 int qf_set_delete_batch(qf_set_t *s, const uint32_t *d_fid, const uint64_t *d_keys, uint64_t n,
                         uint64_t *d_not_found, void *stream);
+/* The same, restricted to the filters listed in h_filters (host, n_filters
+ * distinct indexes in ascending order): only their regions are merged, so a
+ * batch that touches few filters of a large set costs in proportion to
+ * those filters.  Every key's filter must be listed; keys of unlisted
+ * filters are dropped. */
+int qf_set_insert_some(qf_set_t *s, const uint32_t *h_filters, uint32_t n_filters, const uint32_t *d_fid,
+                       const uint64_t *d_keys, uint64_t n, void *stream);
+int qf_set_delete_some(qf_set_t *s, const uint32_t *h_filters, uint32_t n_filters, const uint32_t *d_fid,
+                       const uint64_t *d_keys, uint64_t n, uint64_t *d_not_found, void *stream);
 int qf_set_query_batch(qf_set_t *s, const uint32_t *d_fid, const uint64_t *d_keys, uint64_t n,
                        uint8_t *d_out, void *stream);
 int qf_set_count_batch(qf_set_t *s, const uint32_t *d_fid, const uint64_t *d_keys, uint64_t n,

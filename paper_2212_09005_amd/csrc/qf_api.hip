@@ -92,6 +92,8 @@ void pipe_free(qf::Pipe &p) {
   (void)hipFree(p.pst);
   (void)hipFree(p.hist);
   (void)hipFree(p.d_err);
+  (void)hipFree(p.d_afil);
+  (void)hipFree(p.d_areg);
   free_scratch(p);
   delete p.timer;
   p = qf::Pipe();
@@ -145,8 +147,11 @@ int pipe_init(qf::Pipe &p, qf_filter *const *fs, uint32_t nf) {
   p.gbits = bits_for(G);
   if (nf > 1 && p.gbits + p.RL + p.r > 62) return fail(QF_ERR_ARG);
   std::vector<uint32_t> rmap(G);
-  for (uint32_t i = 0; i < nf; ++i)
+  p.h_rbase.resize(nf);
+  for (uint32_t i = 0; i < nf; ++i) {
+    p.h_rbase[i] = desc[i].rbase;
     for (uint32_t k = 0; k < fs[i]->nregions; ++k) rmap[desc[i].rbase + k] = i;
+  }
   p.hist_words = 256ull * 1024ull + 256ull * 8;  // histograms + per-pass digit totals
   const uint64_t tag_words = 8ull * G + 8;        // 3 G tags, 4 G statistics, G carries
   bool ok = hipMalloc(reinterpret_cast<void **>(&p.d_desc), nf * sizeof(qf::FDesc)) == hipSuccess &&
@@ -155,7 +160,9 @@ int pipe_init(qf::Pipe &p, qf_filter *const *fs, uint32_t nf) {
             hipMalloc(reinterpret_cast<void **>(&p.tags), tag_words * sizeof(uint64_t)) == hipSuccess &&
             hipMalloc(reinterpret_cast<void **>(&p.pst), qf::ST_WORDS * sizeof(uint64_t)) == hipSuccess &&
             hipMalloc(reinterpret_cast<void **>(&p.hist), p.hist_words * sizeof(uint32_t)) == hipSuccess &&
-            hipMalloc(reinterpret_cast<void **>(&p.d_err), nf * sizeof(int64_t)) == hipSuccess;
+            hipMalloc(reinterpret_cast<void **>(&p.d_err), nf * sizeof(int64_t)) == hipSuccess &&
+            hipMalloc(reinterpret_cast<void **>(&p.d_afil), nf * sizeof(uint32_t)) == hipSuccess &&
+            hipMalloc(reinterpret_cast<void **>(&p.d_areg), G * sizeof(uint32_t)) == hipSuccess;
   ok = ok && hipMemcpy(p.d_desc, desc.data(), nf * sizeof(qf::FDesc), hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(p.d_rmap, rmap.data(), G * sizeof(uint32_t), hipMemcpyHostToDevice) == hipSuccess &&
        hipMemset(p.tags, 0, tag_words * sizeof(uint64_t)) == hipSuccess &&
@@ -175,9 +182,29 @@ int pipe_init(qf::Pipe &p, qf_filter *const *fs, uint32_t nf) {
 // hash -> radix sort -> reduction -> region bounds -> merge, on stream s.
 // fid == nullptr: the pipeline has one filter and keys are its own.
 int pipe_update(qf::Pipe &p, const uint64_t *keys, const uint32_t *fid, uint64_t n, int del,
-                uint64_t *not_found, hipStream_t s, uint32_t single_q) {
+                uint64_t *not_found, hipStream_t s, uint32_t single_q, const qf_set *set = nullptr,
+                const uint32_t *h_active = nullptr, uint32_t nactive = 0) {
   int rc = ensure_scratch(p, n, s);
   if (rc) return rc;
+  // restrict the merge to the listed filters (their regions, in order); the
+  // lists are copied from pageable host memory, which the runtime stages
+  // before the call returns
+  p.nafil = p.nareg = 0;
+  if (set && h_active) {
+    if (nactive == 0) return QF_OK;
+    p.h_afil.assign(h_active, h_active + nactive);
+    p.h_areg.clear();
+    for (uint32_t k = 0; k < nactive; ++k) {
+      const uint32_t f = h_active[k];
+      if (f >= set->nf || (k && f <= h_active[k - 1])) return fail(QF_ERR_ARG);
+      for (uint32_t R = 0; R < set->fs[f]->nregions; ++R) p.h_areg.push_back(p.h_rbase[f] + R);
+    }
+    QF_HIP(hipMemcpyAsync(p.d_afil, p.h_afil.data(), nactive * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    QF_HIP(hipMemcpyAsync(p.d_areg, p.h_areg.data(), p.h_areg.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                          s));
+    p.nafil = nactive;
+    p.nareg = static_cast<uint32_t>(p.h_areg.size());
+  }
   uint64_t *sorted = nullptr;
   if (fid) {
     QF_HIP(qf::launch_hash_multi(keys, fid, n, p, p.bufA, s, p.timer));
@@ -550,6 +577,24 @@ int qf_set_delete_batch(qf_set_t *st, const uint32_t *d_fid, const uint64_t *d_k
   if (n == 0) return QF_OK;
   if (n > 0xFFFFFFFFull) return fail(QF_ERR_ARG);
   return pipe_update(st->pipe, d_keys, d_fid, n, 1, d_not_found, static_cast<hipStream_t>(stream), 0);
+}
+
+int qf_set_insert_some(qf_set_t *st, const uint32_t *h_filters, uint32_t n_filters, const uint32_t *d_fid,
+                       const uint64_t *d_keys, uint64_t n, void *stream) {
+  if (!st || !h_filters || (n && (!d_keys || !d_fid))) return fail(QF_ERR_ARG);
+  if (n == 0) return QF_OK;
+  if (n > 0xFFFFFFFFull) return fail(QF_ERR_ARG);
+  return pipe_update(st->pipe, d_keys, d_fid, n, 0, nullptr, static_cast<hipStream_t>(stream), 0, st, h_filters,
+                     n_filters);
+}
+
+int qf_set_delete_some(qf_set_t *st, const uint32_t *h_filters, uint32_t n_filters, const uint32_t *d_fid,
+                       const uint64_t *d_keys, uint64_t n, uint64_t *d_not_found, void *stream) {
+  if (!st || !h_filters || (n && (!d_keys || !d_fid))) return fail(QF_ERR_ARG);
+  if (n == 0) return QF_OK;
+  if (n > 0xFFFFFFFFull) return fail(QF_ERR_ARG);
+  return pipe_update(st->pipe, d_keys, d_fid, n, 1, d_not_found, static_cast<hipStream_t>(stream), 0, st,
+                     h_filters, n_filters);
 }
 
 int qf_set_query_batch(qf_set_t *st, const uint32_t *d_fid, const uint64_t *d_keys, uint64_t n,

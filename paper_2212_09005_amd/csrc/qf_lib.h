@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace qf {
 // Optional launch timer: begin/end record events on the launch stream.
 struct Timer {
@@ -42,6 +44,10 @@ struct Pipe {
   int64_t *cb = nullptr;      // G old carries (region boundaries)
   uint64_t *pst = nullptr;    // ST_WORDS pipeline words (unique count)
   int64_t *d_err = nullptr;   // nf: per-filter deferred errors gathered by qf_set_errors
+  // a launch restricted to some filters: their indexes and regions
+  uint32_t *d_afil = nullptr, *d_areg = nullptr;  // capacity nf, G
+  uint32_t nafil = 0, nareg = 0;                  // 0: all filters
+  std::vector<uint32_t> h_rbase, h_afil, h_areg;  // host copies
   uint32_t epoch = 0;
   int device = 0;
   // grow-only scratch, capacity in keys

@@ -87,6 +87,7 @@ struct MergeArgs {
   const int64_t *cb;                // old carries at region boundaries
   uint32_t G, epoch;
   int del;
+  const uint32_t *areg;  // the launch's regions (nullptr: all G, in order)
   // per-entry scratch (indexed like the reduced batch) for regions with more
   // entries than the LDS holds: region-relative fingerprints and counts, and
   // the changed-run arrays (a region has at most as many changed runs as
@@ -223,23 +224,19 @@ __device__ int64_t carry_old(const Block<T> *b, const uint32_t *off, int64_t i, 
   }
 }
 
-// Before the merge, one thread per region g of the pipeline: the old carry at
-// the region's first slot (cb[g] = carry_old(R S) for local regions R up to
-// the first extra-slot region), the filter's batch flags (by its region 0),
-// and, when the launch epoch wraps, the region's look-back words.
+// Before the merge, one thread per region g of the launch (all regions of
+// the pipeline, or those listed in areg): the old carry at the region's
+// first slot (cb[g] = carry_old(R S) for local regions R up to the first
+// extra-slot region) and the filter's batch flags (by its region 0).
 template <typename T>
 __global__ __launch_bounds__(NT) void k_carries(const FDesc *__restrict__ desc, const uint32_t *__restrict__ rmap,
-                                                uint32_t G, bool wrap, uint64_t *tags, int64_t *cb) {
-  const uint32_t g = blockIdx.x * NT + threadIdx.x;
-  if (g >= G) return;
+                                                const uint32_t *__restrict__ areg, uint32_t nreg, int64_t *cb) {
+  const uint32_t i = blockIdx.x * NT + threadIdx.x;
+  if (i >= nreg) return;
+  const uint32_t g = areg ? areg[i] : i;
   const FDesc &d = desc[rmap[g]];
   const uint32_t R = g - d.rbase;
   if (R == 0) d.state[ST_BATCH] = 0;
-  if (wrap) {
-    tags[g] = 0;
-    tags[static_cast<uint64_t>(G) + g] = 0;
-    tags[2ull * G + g] = 0;
-  }
   if (R <= d.nqregions) {
     const bool cur = d.state[ST_CUR] & 1ull;
     cb[g] = carry_old(static_cast<const Block<T> *>(cur ? d.blk[1] : d.blk[0]), cur ? d.off[1] : d.off[0],
@@ -821,7 +818,7 @@ __device__ __forceinline__ void merge_body(const MergeArgs &a, const Smem<T> &m)
   // global region = work-group index (no shared ticket counter: one atomic
   // per work-group on one address serialises the whole launch); the filter
   // and its local region R follow from the pipeline's region map
-  const uint32_t gR = blockIdx.x;
+  const uint32_t gR = a.areg ? a.areg[blockIdx.x] : blockIdx.x;
   // (a one-filter pipeline takes its descriptor from the kernel arguments,
   // saving two dependent loads before the region's first load)
   const FDesc &fd = SINGLE ? a.one : a.desc[a.rmap[gR]];
@@ -1179,7 +1176,8 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs a) {
   __shared__ uint64_t sh_r[NT / 64];
 
   const Smem<T> m{old_s, new_s, old_b, new_b, old_wp, occ_l, chg_l, nfp_l, ncnt_l, cxr_l, chead_l, cop_l, coe_l, cL_l, cst_l, gaf_l, sh_i, sh_fn, sh_u, sh_r};
-  if (a.rb[blockIdx.x + 1] - a.rb[blockIdx.x] <= static_cast<uint64_t>(C::NCAP))
+  const uint32_t g = a.areg ? a.areg[blockIdx.x] : blockIdx.x;
+  if (a.rb[g + 1] - a.rb[g] <= static_cast<uint64_t>(C::NCAP))
     merge_body<T, SINGLE, true>(a, m);
   else
     merge_body<T, SINGLE, false>(a, m);
@@ -1188,10 +1186,11 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs a) {
 // After the merge, one work-group per filter: sum its regions' statistics;
 // flip its current copy if none of its regions failed, else record the error
 // (all-or-nothing per filter); add its delete shortfall to not_found[f].
-__global__ __launch_bounds__(1024) void k_finish(const FDesc *__restrict__ desc, const uint64_t *rstat, int del,
-                                                 uint64_t *not_found) {
+__global__ __launch_bounds__(1024) void k_finish(const FDesc *__restrict__ desc, const uint32_t *__restrict__ afil,
+                                                 const uint64_t *rstat, int del, uint64_t *not_found) {
   __shared__ uint64_t sh[4][16];
-  const FDesc &d = desc[blockIdx.x];
+  const uint32_t f = afil ? afil[blockIdx.x] : blockIdx.x;
+  const FDesc &d = desc[f];
   uint64_t v[4] = {0, 0, 0, 0};
   for (uint32_t R = threadIdx.x; R < d.nregions; R += 1024)
     for (int k = 0; k < 4; ++k) v[k] += rstat[4ull * (d.rbase + R) + k];
@@ -1216,7 +1215,7 @@ __global__ __launch_bounds__(1024) void k_finish(const FDesc *__restrict__ desc,
                                             : (st & BATCH_FULL) ? QF_ERR_FULL
                                                                 : QF_ERR_COUNT_OVERFLOW);
     }
-    if (del && not_found) not_found[blockIdx.x] += t[3];
+    if (del && not_found) not_found[f] += t[3];
     state[ST_BATCHES] += 1;
   }
 }
@@ -1249,14 +1248,26 @@ hipError_t launch_merge_t(Pipe &p, const uint64_t *ufp, const uint64_t *ucnt, in
   a.g_oe = reinterpret_cast<uint16_t *>(e + 28 * cap);
   a.g_st = reinterpret_cast<uint16_t *>(e + 30 * cap);
   if (p.timer) p.timer->begin(QF_PROF_MERGE, s);
-  k_carries<T><<<(p.G + NT - 1) / NT, NT, 0, s>>>(p.d_desc, p.d_rmap, p.G, wrap, p.tags, p.cb);
+  // the launch's regions: all, or those of the listed filters
+  const uint32_t *areg = p.nareg ? p.d_areg : nullptr;
+  const uint32_t nreg = p.nareg ? p.nareg : p.G;
+  a.areg = areg;
+  // when the 16-bit launch epoch wraps, every look-back word is cleared (also
+  // those of regions outside this launch, which could otherwise carry an
+  // old word with a current epoch into a later launch)
+  if (wrap) {
+    const hipError_t e = launch_fill_u64(p.tags, 3ull * p.G, 0, s);
+    if (e != hipSuccess) return e;
+  }
+  k_carries<T><<<(nreg + NT - 1) / NT, NT, 0, s>>>(p.d_desc, p.d_rmap, areg, nreg, p.cb);
   if (p.nf == 1) {
     a.one = p.one;
-    k_merge<T, true><<<p.G, NT, 0, s>>>(a);
+    k_merge<T, true><<<nreg, NT, 0, s>>>(a);
   } else {
-    k_merge<T, false><<<p.G, NT, 0, s>>>(a);
+    k_merge<T, false><<<nreg, NT, 0, s>>>(a);
   }
-  k_finish<<<p.nf, 1024, 0, s>>>(p.d_desc, p.rstat, del, not_found);
+  k_finish<<<p.nareg ? p.nafil : p.nf, 1024, 0, s>>>(p.d_desc, p.nareg ? p.d_afil : nullptr, p.rstat, del,
+                                                     not_found);
   if (p.timer) p.timer->end(QF_PROF_MERGE, s);
   return hipGetLastError();
 }

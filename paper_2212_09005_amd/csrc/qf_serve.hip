@@ -295,8 +295,18 @@ int launch_round(qf_server *s, Round &rd, Stage &st) {
     const uint64_t *k = st.d_keys + base;
     const uint32_t *f = st.d_fid + base;
     int rc = QF_OK;
-    if (p.op == OP_INSERT) rc = qf_set_insert_batch(set, f, k, p.n, s->stream);
-    if (p.op == OP_DELETE) rc = qf_set_delete_batch(set, f, k, p.n, nullptr, s->stream);
+    if (p.op == OP_INSERT || p.op == OP_DELETE) {
+      // merge only the filters this part touches
+      std::vector<uint32_t> act;
+      for (Req *q : p.reqs) act.push_back(s->sets[p.r].idx[q->id]);
+      std::sort(act.begin(), act.end());
+      act.erase(std::unique(act.begin(), act.end()), act.end());
+      if (p.op == OP_INSERT)
+        rc = qf_set_insert_some(set, act.data(), static_cast<uint32_t>(act.size()), f, k, p.n, s->stream);
+      else
+        rc = qf_set_delete_some(set, act.data(), static_cast<uint32_t>(act.size()), f, k, p.n, nullptr,
+                                s->stream);
+    }
     if (p.op == OP_QUERY) {
       rc = qf_set_query_batch(set, f, k, p.n, st.d_out8 + base, s->stream);
       if (!rc && hipMemcpyAsync(st.out8 + base, st.d_out8 + base, p.n, hipMemcpyDeviceToHost, s->stream))

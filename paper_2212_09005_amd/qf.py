@@ -113,6 +113,8 @@ def lib() -> ctypes.CDLL:
         "qf_set_profile_enable": (i32, [vp, i32]),
         "qf_set_profile_read": (i32, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64)]),
         "qf_set_errors": (i32, [vp, ctypes.POINTER(ctypes.c_int32), vp]),
+        "qf_set_insert_some": (i32, [vp, ctypes.POINTER(ctypes.c_uint32), u32, vp, vp, u64, vp]),
+        "qf_set_delete_some": (i32, [vp, ctypes.POINTER(ctypes.c_uint32), u32, vp, vp, u64, vp, vp]),
         "qfs_create": (vp, [u64, u64]),
         "qfs_destroy": (None, [vp]),
         "qfs_open": (i32, [vp, u32, u32]),
@@ -397,11 +399,27 @@ class CQFSet:
         except Exception:
             pass
 
-    def insert(self, fid, keys, stream=None):
-        _check(qf_set_insert_batch(self.h, fid, keys, stream), "qf_set_insert_batch")
+    def insert(self, fid, keys, stream=None, active=None):
+        """active: optional ascending list of the filter indexes the batch touches (only they are merged)."""
+        if active is None:
+            _check(qf_set_insert_batch(self.h, fid, keys, stream), "qf_set_insert_batch")
+            return
+        n = keys.numel()
+        act = (ctypes.c_uint32 * max(len(active), 1))(*active)
+        _check(lib().qf_set_insert_some(self.h, act, len(active), _dev_ptr(fid, n, 4) if n else None,
+                                        _dev_ptr(keys, n, 8) if n else None, n, _stream(stream)),
+               "qf_set_insert_some")
 
-    def delete(self, fid, keys, not_found=None, stream=None):
-        _check(qf_set_delete_batch(self.h, fid, keys, not_found, stream), "qf_set_delete_batch")
+    def delete(self, fid, keys, not_found=None, stream=None, active=None):
+        if active is None:
+            _check(qf_set_delete_batch(self.h, fid, keys, not_found, stream), "qf_set_delete_batch")
+            return
+        n = keys.numel()
+        act = (ctypes.c_uint32 * max(len(active), 1))(*active)
+        nf = _dev_ptr(not_found, None, 8) if not_found is not None else None
+        _check(lib().qf_set_delete_some(self.h, act, len(active), _dev_ptr(fid, n, 4) if n else None,
+                                        _dev_ptr(keys, n, 8) if n else None, n, nf, _stream(stream)),
+               "qf_set_delete_some")
 
     def query(self, fid, keys, out=None, stream=None):
         import torch

@@ -211,3 +211,45 @@ def test_set_many_small_filters():
     probe_fid = np.concatenate([fid[:20000], rng.integers(0, len(qs), 20000).astype(np.int32)])
     probe = np.concatenate([keys[:20000], inputs.absent_keys(44, 20000)])
     c.check_lookups(probe_fid, probe, "many small filters")
+
+
+def test_set_updates_restricted_to_listed_filters():
+    # batches that list the filters they touch merge only those; the others
+    # must stay exactly as they were, across many launches (look-back epochs)
+    qs = [12, 13, 14, 15, 16]
+    note("restricted set updates")
+    c = SetCase(qs, 8, seed=61)
+    fid, keys = c.tagged(3000, seed=62)
+    c.insert(fid, keys)  # a full launch first
+    for step in range(40):
+        active = sorted(set(int(x) for x in c.rng.choice(len(qs), size=2, replace=False)))
+        n = int(c.rng.integers(1, 150))
+        f2 = c.rng.choice(active, size=n).astype(np.int32)
+        k2 = inputs.uniform_keys(7000 + step, n)
+        if step % 5 == 4:
+            # delete some of the present keys of the listed filters
+            pres = np.concatenate([keys[fid == a] for a in active])
+            pf = np.concatenate([np.full(int((fid == a).sum()), a, np.int32) for a in active])
+            sel = c.rng.integers(0, len(pres), size=min(n, len(pres)))
+            nf = torch.zeros(len(qs), dtype=torch.int64, device="cuda")
+            c.set.delete(dev_fid(pf[sel]), dev(pres[sel]), nf, active=active)
+            want = np.zeros(len(qs), dtype=U64)
+            for a in active:
+                part = pres[sel][pf[sel] == a]
+                if len(part):
+                    rc, short = c.os[a].delete(part)
+                    assert rc == 0
+                    want[a] = short
+            assert np.array_equal(host(nf), want)
+        else:
+            c.set.insert(dev_fid(f2), dev(k2), active=active)
+            for a in active:
+                part = k2[f2 == a]
+                if len(part):
+                    assert c.os[a].insert(part) == 0
+            fid = np.concatenate([fid, f2])
+            keys = np.concatenate([keys, k2])
+        if step % 10 == 9:
+            c.check_all(f"after restricted step {step}")
+    c.check_all("after restricted updates")
+    c.check_lookups(fid[:5000], keys[:5000], "restricted updates")
