@@ -104,8 +104,6 @@ qf::FDesc desc_of(const qf_filter *f, uint32_t rbase) {
   std::memset(&d, 0, sizeof(d));
   d.blk[0] = f->blk[0];
   d.blk[1] = f->blk[1];
-  d.off[0] = f->off[0];
-  d.off[1] = f->off[1];
   d.state = f->state;
   d.N = static_cast<int64_t>(f->N);
   d.P = static_cast<int64_t>(f->P);
@@ -353,16 +351,12 @@ qf_t *qf_create(uint32_t q, uint32_t r) {
   const uint64_t S = 1ull << f->rlog;
   f->nqregions = static_cast<uint32_t>(f->N / S);
   f->nregions = static_cast<uint32_t>((f->P + S - 1) / S);
-  f->block_bytes = r == 8 ? 80 : 144;
+  f->block_bytes = static_cast<uint32_t>(qf::table_bytes(1, r));
   (void)hipGetDevice(&f->device);
   bool ok = true;
   for (int c = 0; c < 2 && ok; ++c) {
     ok = hipMalloc(&f->blk[c], f->nblocks * f->block_bytes) == hipSuccess &&
-         hipMalloc(reinterpret_cast<void **>(&f->off[c]), f->nblocks * sizeof(uint32_t)) == hipSuccess;
-    if (ok) {
-      ok = hipMemset(f->blk[c], 0, f->nblocks * f->block_bytes) == hipSuccess &&
-           hipMemset(f->off[c], 0, f->nblocks * sizeof(uint32_t)) == hipSuccess;
-    }
+         hipMemset(f->blk[c], 0, f->nblocks * f->block_bytes) == hipSuccess;
   }
   ok = ok && hipMalloc(reinterpret_cast<void **>(&f->state), qf::ST_WORDS * sizeof(uint64_t)) == hipSuccess &&
        hipMemset(f->state, 0, qf::ST_WORDS * sizeof(uint64_t)) == hipSuccess;
@@ -386,7 +380,6 @@ void qf_destroy(qf_t *f) {
   (void)hipDeviceSynchronize();
   for (int c = 0; c < 2; ++c) {
     (void)hipFree(f->blk[c]);
-    (void)hipFree(f->off[c]);
   }
   (void)hipFree(f->state);
   pipe_free(f->pipe);

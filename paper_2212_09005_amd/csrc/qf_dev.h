@@ -1,12 +1,12 @@
 // qf_dev.h -- device-side building blocks of the MI355X counting quotient filter.
 //
 // Physical table (one of the two copies the library alternates between):
-//   blocks[b]  : 64 slots = { uint64 occupieds; uint64 runends; T slot[64] }
-//                (80 B for r = 8, 144 B for r = 16), array of structs so that a
-//                lookup finds the metadata and most of its run in one or two
-//                128-byte lines;
-//   offsets[b] : uint32, distance from slot 64b to the end of the run of the
-//                last occupied quotient <= 64b (0 if that end lies before 64b).
+//   blocks[b] : 64 slots = { uint64 occupieds; uint64 runends; uint32 offset;
+//               padding; T slot[64] } (128 B for r = 8: one 128-byte line, so
+//               a lookup usually reads one line; 160 B for r = 16), where the
+//               offset is the distance from slot 64b to the end of the run of
+//               the last occupied quotient <= 64b (0 if that end lies before
+//               64b).
 // Quotient x's occupied bit is bit x%64 of blocks[x/64].occupieds, slot j's
 // run-end bit is bit j%64 of blocks[j/64].runends (Sec. 5.1: runs, clusters;
 // the rank/select metadata is this library's reading of the paper's CQF).
@@ -21,7 +21,20 @@ template <typename T>
 struct Block {
   uint64_t occ;
   uint64_t rend;
+  uint32_t off;
+  uint32_t pad[sizeof(T) == 1 ? 11 : 3];
   T s[64];
+};
+// r = 8: one 128-byte line per block (metadata and offset in the first 64
+// bytes, slots in the second); r = 16: 32 bytes of metadata + 128 of slots.
+static_assert(sizeof(Block<uint8_t>) == 128, "r = 8 block is one 128-byte line");
+static_assert(sizeof(Block<uint16_t>) == 160, "r = 16 block is 160 bytes");
+
+// the block offsets seen as an array (offset of block i = blocks[i].off)
+template <typename T>
+struct OffRef {
+  Block<T> *b;
+  __device__ uint32_t &operator[](int64_t i) const { return b[i].off; }
 };
 
 // Device state words of one filter.

@@ -18,8 +18,7 @@ struct Timer {
 // One filter as the kernels see it (an array of these lives in device memory
 // for every pipeline; a single filter's pipeline has one).
 struct FDesc {
-  void *blk[2];       // the two table copies (blocks)
-  uint32_t *off[2];   // and their offsets
+  void *blk[2];       // the two table copies (blocks, offsets inside)
   uint64_t *state;    // ST_WORDS device words of the filter
   int64_t N, P, nblocks;
   uint32_t q, r, rlog, nregions, nqregions;
@@ -66,10 +65,9 @@ struct qf_filter {
   uint32_t q, r, rlog;      // region = 2^rlog slots
   uint64_t N, E, P, nblocks;
   uint32_t nregions, nqregions;
-  uint32_t block_bytes;     // 80 (r = 8) or 144 (r = 16)
+  uint32_t block_bytes;     // 128 (r = 8) or 160 (r = 16)
   int device;
-  void *blk[2];             // two table copies (blocks)
-  uint32_t *off[2];         // and their offsets
+  void *blk[2];             // two table copies (blocks, offsets inside)
   uint64_t *state;          // qf::ST_WORDS device words
   uint64_t table_device_bytes;
   qf::Pipe pipe;            // the single-filter update pipeline

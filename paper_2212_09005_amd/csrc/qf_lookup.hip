@@ -17,15 +17,14 @@ namespace {
 constexpr int NT = 256;
 
 template <typename T>
-__device__ __forceinline__ uint64_t lookup_one(const Block<T> *__restrict__ b,
-                                               const uint32_t *__restrict__ off, int64_t nblocks,
+__device__ __forceinline__ uint64_t lookup_one(const Block<T> *__restrict__ b, int64_t nblocks,
                                                int64_t x, uint64_t rem, uint32_t r) {
   const int64_t bi = x >> 6;
   const int bit = static_cast<int>(x & 63);
   const uint64_t occ = b[bi].occ;
   if (!((occ >> bit) & 1ull)) return 0;
   int d = popc64(occ & ((2ull << bit) - 2ull));  // occupied quotients in (64*bi, x]
-  const int64_t p = (bi << 6) + off[bi];
+  const int64_t p = (bi << 6) + b[bi].off;
   int64_t e;
   if (d == 0) {
     e = p;
@@ -77,7 +76,6 @@ __device__ __forceinline__ uint64_t lookup_one(const Block<T> *__restrict__ b,
 
 template <typename T, bool COUNT>
 __global__ __launch_bounds__(NT) void k_lookup(const Block<T> *b0, const Block<T> *b1,
-                                               const uint32_t *o0, const uint32_t *o1,
                                                const uint64_t *state,
                                                const uint64_t *__restrict__ keys, uint64_t n,
                                                uint32_t q, uint32_t r, int64_t nblocks,
@@ -85,14 +83,13 @@ __global__ __launch_bounds__(NT) void k_lookup(const Block<T> *b0, const Block<T
                                                uint64_t *__restrict__ out64) {
   const int cur = static_cast<int>(state[ST_CUR] & 1ull);
   const Block<T> *b = cur ? b1 : b0;
-  const uint32_t *off = cur ? o1 : o0;
   const uint32_t p = q + r;
   const uint64_t pmask = p >= 64 ? ~0ull : ((1ull << p) - 1ull);
   const uint64_t rmask = (1ull << r) - 1ull;
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * NT;
   for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * NT + threadIdx.x; i < n; i += stride) {
     const uint64_t fp = mix64(keys[i]) & pmask;
-    const uint64_t c = lookup_one(b, off, nblocks, static_cast<int64_t>(fp >> r), fp & rmask, r);
+    const uint64_t c = lookup_one(b, nblocks, static_cast<int64_t>(fp >> r), fp & rmask, r);
     if (COUNT)
       out64[i] = c;
     else
@@ -117,8 +114,7 @@ __global__ __launch_bounds__(NT) void k_lookup_multi(const FDesc *__restrict__ d
       const bool cur = d.state[ST_CUR] & 1ull;
       const uint32_t p = d.q + d.r;
       const uint64_t fp = mix64(keys[i]) & ((1ull << p) - 1ull);
-      c = lookup_one(static_cast<const Block<T> *>(cur ? d.blk[1] : d.blk[0]), cur ? d.off[1] : d.off[0],
-                     d.nblocks, static_cast<int64_t>(fp >> d.r), fp & ((1ull << d.r) - 1ull), d.r);
+      c = lookup_one(static_cast<const Block<T> *>(cur ? d.blk[1] : d.blk[0]), d.nblocks, static_cast<int64_t>(fp >> d.r), fp & ((1ull << d.r) - 1ull), d.r);
     } else {
       pst[ST_ERR] = static_cast<uint64_t>(static_cast<int64_t>(QF_ERR_ARG));
     }
@@ -131,13 +127,11 @@ __global__ __launch_bounds__(NT) void k_lookup_multi(const FDesc *__restrict__ d
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_export(const Block<T> *b0, const Block<T> *b1,
-                                               const uint32_t *o0, const uint32_t *o1,
                                                const uint64_t *state, int64_t nblocks,
                                                int64_t nqblocks, uint64_t *occ, uint64_t *rend,
                                                uint16_t *slots, uint32_t *offs) {
   const int cur = static_cast<int>(state[ST_CUR] & 1ull);
   const Block<T> *b = cur ? b1 : b0;
-  const uint32_t *off = cur ? o1 : o0;
   const uint64_t total = static_cast<uint64_t>(nblocks) * 64;
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * NT;
   for (uint64_t j = static_cast<uint64_t>(blockIdx.x) * NT + threadIdx.x; j < total; j += stride) {
@@ -145,14 +139,14 @@ __global__ __launch_bounds__(NT) void k_export(const Block<T> *b0, const Block<T
     slots[j] = static_cast<uint16_t>(b[bi].s[j & 63]);
     if ((j & 63) == 0) {
       rend[bi] = b[bi].rend;
-      offs[bi] = off[bi];
+      offs[bi] = b[bi].off;
       if (bi < nqblocks) occ[bi] = b[bi].occ;
     }
   }
 }
 
 template <typename T>
-__global__ __launch_bounds__(NT) void k_import(Block<T> *b, uint32_t *off, int64_t nblocks,
+__global__ __launch_bounds__(NT) void k_import(Block<T> *b, int64_t nblocks,
                                                int64_t nqblocks, const uint64_t *occ,
                                                const uint64_t *rend, const uint16_t *slots,
                                                const uint32_t *offs) {
@@ -163,7 +157,7 @@ __global__ __launch_bounds__(NT) void k_import(Block<T> *b, uint32_t *off, int64
     b[bi].s[j & 63] = static_cast<T>(slots[j]);
     if ((j & 63) == 0) {
       b[bi].rend = rend[bi];
-      off[bi] = offs[bi];
+      b[bi].off = offs[bi];
       b[bi].occ = bi < nqblocks ? occ[bi] : 0ull;
     }
   }
@@ -184,11 +178,11 @@ hipError_t lookup_t(qf_filter *f, const uint64_t *keys, uint64_t n, uint8_t *out
   Timer *t = f->pipe.timer;
   if (t) t->begin(QF_PROF_LOOKUP, s);
   if (out64)
-    k_lookup<T, true><<<grid_for(n), NT, 0, s>>>(b0, b1, f->off[0], f->off[1], f->state, keys, n,
+    k_lookup<T, true><<<grid_for(n), NT, 0, s>>>(b0, b1, f->state, keys, n,
                                                  f->q, f->r, static_cast<int64_t>(f->nblocks),
                                                  nullptr, out64);
   else
-    k_lookup<T, false><<<grid_for(n), NT, 0, s>>>(b0, b1, f->off[0], f->off[1], f->state, keys, n,
+    k_lookup<T, false><<<grid_for(n), NT, 0, s>>>(b0, b1, f->state, keys, n,
                                                   f->q, f->r, static_cast<int64_t>(f->nblocks),
                                                   out8, nullptr);
   if (t) t->end(QF_PROF_LOOKUP, s);
@@ -217,7 +211,7 @@ hipError_t launch_lookup_multi(const Pipe &p, const uint64_t *keys, const uint32
 
 uint64_t table_bytes(uint64_t nblocks, uint32_t r) {
   const uint64_t bb = r == 8 ? sizeof(Block<uint8_t>) : sizeof(Block<uint16_t>);
-  return nblocks * bb + nblocks * sizeof(uint32_t);
+  return nblocks * bb;
 }
 
 hipError_t launch_lookup(qf_filter *f, const uint64_t *keys, uint64_t n, uint8_t *out8,
@@ -233,11 +227,11 @@ hipError_t launch_export(qf_filter *f, uint64_t *occ, uint64_t *rend, uint16_t *
   if (f->r == 8)
     k_export<uint8_t><<<grid_for(total), NT, 0, s>>>(
         static_cast<const Block<uint8_t> *>(f->blk[0]), static_cast<const Block<uint8_t> *>(f->blk[1]),
-        f->off[0], f->off[1], f->state, nb, nq, occ, rend, slots, offs);
+        f->state, nb, nq, occ, rend, slots, offs);
   else
     k_export<uint16_t><<<grid_for(total), NT, 0, s>>>(
         static_cast<const Block<uint16_t> *>(f->blk[0]), static_cast<const Block<uint16_t> *>(f->blk[1]),
-        f->off[0], f->off[1], f->state, nb, nq, occ, rend, slots, offs);
+        f->state, nb, nq, occ, rend, slots, offs);
   return hipGetLastError();
 }
 
@@ -246,10 +240,10 @@ hipError_t launch_import(qf_filter *f, const uint64_t *occ, const uint64_t *rend
   const uint64_t total = f->nblocks * 64;
   const int64_t nb = static_cast<int64_t>(f->nblocks), nq = static_cast<int64_t>(f->N / 64);
   if (f->r == 8)
-    k_import<uint8_t><<<grid_for(total), NT, 0, s>>>(static_cast<Block<uint8_t> *>(f->blk[0]), f->off[0],
+    k_import<uint8_t><<<grid_for(total), NT, 0, s>>>(static_cast<Block<uint8_t> *>(f->blk[0]),
                                                      nb, nq, occ, rend, slots, offs);
   else
-    k_import<uint16_t><<<grid_for(total), NT, 0, s>>>(static_cast<Block<uint16_t> *>(f->blk[0]), f->off[0],
+    k_import<uint16_t><<<grid_for(total), NT, 0, s>>>(static_cast<Block<uint16_t> *>(f->blk[0]),
                                                       nb, nq, occ, rend, slots, offs);
   return hipGetLastError();
 }

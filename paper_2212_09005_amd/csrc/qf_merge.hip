@@ -204,9 +204,9 @@ __device__ __forceinline__ int64_t next_occ(const uint64_t *occ_l, int64_t RS, i
 // End of the last (old) run whose quotient is < i, or i - 1 when it ends
 // before i / there is none.  i is a multiple of 64 and i <= N.
 template <typename T>
-__device__ int64_t carry_old(const Block<T> *b, const uint32_t *off, int64_t i, int64_t N) {
+__device__ int64_t carry_old(const Block<T> *b, int64_t i, int64_t N) {
   const int64_t bi = i >> 6;
-  const int64_t O = off[bi];
+  const int64_t O = b[bi].off;
   const bool occ_i = i < N && (b[bi].occ & 1ull);
   if (!occ_i) {
     if (O > 0) return i + O;
@@ -239,8 +239,8 @@ __global__ __launch_bounds__(NT) void k_carries(const FDesc *__restrict__ desc, 
   if (R == 0) d.state[ST_BATCH] = 0;
   if (R <= d.nqregions) {
     const bool cur = d.state[ST_CUR] & 1ull;
-    cb[g] = carry_old(static_cast<const Block<T> *>(cur ? d.blk[1] : d.blk[0]), cur ? d.off[1] : d.off[0],
-                      static_cast<int64_t>(R) << d.rlog, d.N);
+    cb[g] = carry_old(static_cast<const Block<T> *>(cur ? d.blk[1] : d.blk[0]), static_cast<int64_t>(R) << d.rlog,
+                      d.N);
   }
 }
 
@@ -318,7 +318,7 @@ __device__ __forceinline__ void walk(uint32_t r, int del, int64_t RS, const uint
                                      int64_t x0, int64_t x1, int64_t s0, int64_t s1, int64_t ope,
                                      uint64_t ni, uint64_t nb, const Old &old, const New &nw,
                                      Out &out, int64_t carry, Acc &acc, uint64_t *nocc_l,
-                                     uint32_t *noff) {
+                                     OffRef<T> noff) {
   int64_t wpos = max(carry + 1, s0);
   int64_t next_bs = (s0 + 63) & ~static_cast<int64_t>(63);
   int64_t xo = x0 < x1 ? next_occ(occ_l, RS, x0, x1) : INF;
@@ -577,7 +577,7 @@ __device__ __forceinline__ void walk_global(const Block<T> *ob, Block<T> *nbk, i
                                          int del, int64_t RS, const uint64_t *occ_l, int64_t x0,
                                          int64_t x1, int64_t s0, int64_t s1, int64_t ope,
                                          uint64_t ni, uint64_t nb, int64_t hi, int64_t carry,
-                                         Acc *acc, uint64_t *nocc_l, uint32_t *noff) {
+                                         Acc *acc, uint64_t *nocc_l, OffRef<T> noff) {
   OldGlb<T> old{ob, nblocks};
   NewGlb nw{ufp, ucnt, fbase, fmask};
   Acc a = *acc;
@@ -833,12 +833,11 @@ __device__ __forceinline__ void merge_body(const MergeArgs &a, const Smem<T> &m)
   const int cur = static_cast<int>(fstate[ST_CUR] & 1ull);
   const Block<T> *ob = static_cast<const Block<T> *>(cur ? fd.blk[1] : fd.blk[0]);
   Block<T> *nbk = static_cast<Block<T> *>(cur ? fd.blk[0] : fd.blk[1]);
-  uint32_t *noff = cur ? fd.off[0] : fd.off[1];
+  const OffRef<T> noff{nbk};
   // the same pointers typed as global memory for the hot loads and stores
   // (they come from a descriptor in memory, so the compiler cannot tell)
   const GPtr<const Block<T>> gob = to_global(ob);
   const GPtr<Block<T>> gnbk = to_global(nbk);
-  const GPtr<uint32_t> gnoff = to_global(noff);
   const GPtr<const uint64_t> gufp = to_global(a.ufp);
   const GPtr<const uint64_t> gucnt = to_global(a.ucnt);
   const bool qreg = RS < FN;
@@ -1077,7 +1076,7 @@ __device__ __forceinline__ void merge_body(const MergeArgs &a, const Smem<T> &m)
         ct0 = lane_walk<true, T>(t0, occ_c, chg_c, obr, ope0, ce, c0, cop, coe, gaf, df, du, cL, cst, old_s,
                                  new_s, new_b, xb, carry, nocc);
       }
-      if ((t0 & 63) == 0) gnoff[(RS + t0) >> 6] = static_cast<uint32_t>(max(ct0 - t0, 0));
+      if ((t0 & 63) == 0) gnbk[(RS + t0) >> 6].off = static_cast<uint32_t>(max(ct0 - t0, 0));
     }
     if (qreg) {
       // the new occupied words: OR the chunks of each 64-quotient word into
@@ -1088,7 +1087,7 @@ __device__ __forceinline__ void merge_body(const MergeArgs &a, const Smem<T> &m)
     } else {
       for (int w = tid; w < nw_reg; w += NT) {
         gnbk[(RS >> 6) + w].occ = 0ull;
-        gnoff[(RS >> 6) + w] = static_cast<uint32_t>(max(c_in - (RS + 64ll * w), static_cast<int64_t>(0)));
+        gnbk[(RS >> 6) + w].off = static_cast<uint32_t>(max(c_in - (RS + 64ll * w), static_cast<int64_t>(0)));
       }
     }
     __syncthreads();

@@ -54,8 +54,8 @@ def test_argument_errors_return_before_the_device():
 
 
 def test_table_bytes():
-    # 80-byte blocks (r = 8) or 144-byte blocks (r = 16) plus a 4-byte offset
-    assert qf.qf_table_bytes(16, 8) == (65536 + 2560) // 64 * 84
-    assert qf.qf_table_bytes(28, 8) == ((1 << 28) + 163840) // 64 * 84
-    assert qf.qf_table_bytes(30, 16) == ((1 << 30) + 327680) // 64 * 148
+    # 128-byte blocks (r = 8) or 160-byte blocks (r = 16), offset inside
+    assert qf.qf_table_bytes(16, 8) == (65536 + 2560) // 64 * 128
+    assert qf.qf_table_bytes(28, 8) == ((1 << 28) + 163840) // 64 * 128
+    assert qf.qf_table_bytes(30, 16) == ((1 << 30) + 327680) // 64 * 160
     assert qf.qf_table_bytes(5, 8) == 0
