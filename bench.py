@@ -133,8 +133,10 @@ def cpu_baseline(w, budget_s: float = 20.0) -> dict:
 def bench_sets(args) -> dict:
     """Many filters (4096, 2^10..2^20 quotients, r = 8): fill each to load 0.85, then query 2^24 keys
     spread over the filters in proportion to their size (half present, half absent).  The same work
-    runs through one filter set (one pipeline of launches for all filters) and through a plain loop
-    of per-filter calls on the same GPU; the tables must come out identical."""
+    runs three ways on the same GPU: a filter set with autotuned launch parameters whose fill and
+    query are each one captured graph (the reported value), a filter set with default parameters
+    called directly, and a plain loop of per-filter calls; answers and tables must come out
+    identical."""
     import torch
 
     from paper_2212_09005_amd import inputs, qf
@@ -174,6 +176,37 @@ def bench_sets(args) -> dict:
         return time.perf_counter() - t0
 
     sample = sorted(set(rng.integers(0, nf, size=8).tolist()) | {int(np.argmax(qs)), int(np.argmin(qs))})
+    # the set with autotuned launch parameters, fill and query each captured
+    # as one graph (the graph's launch is what is timed)
+    t0 = time.perf_counter()
+    tuning, tune_ms = qf.autotune_set([int(q) for q in qs], 8, 0.85, m)
+    t_tune = time.perf_counter() - t0
+    log(f"c4 autotune: {tuning} in {t_tune:.1f}s (sample insert {tune_ms[0]:.2f} ms, query {tune_ms[1]:.3f} ms)")
+    fs_g = [qf.CQF(int(q), 8) for q in qs]
+    st_g = qf.CQFSet(fs_g)
+    st_g.tune(**tuning)
+    st_g.reserve(total)
+    gs = torch.cuda.Stream()
+    out_g = torch.empty(m, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    g_fill, g_query = qf.Graph(gs), qf.Graph(gs)
+    with g_fill:
+        st_g.insert(d_fid, d_keys, stream=gs.cuda_stream)
+    with g_query:
+        st_g.query(d_qfid, d_qkeys, out_g, stream=gs.cuda_stream)
+    t_g_fill = timed(lambda: g_fill.launch())
+    assert st_g.sync() == 0
+    g_query.launch()  # warm-up
+    t_g_query = timed(lambda: g_query.launch())
+    got_g = out_g.cpu().numpy()
+    lay_g = {i: fs_g[i].export() for i in sample}
+    g_fill.close()
+    g_query.close()
+    st_g.close()
+    for f in fs_g:
+        f.close()
+    del fs_g, st_g
+    log(f"c4 tuned set, graphs: fill {t_g_fill:.3f}s, query {t_g_query * 1e3:.2f} ms")
     # the set (scratch reserved beforehand, so no allocation is timed)
     fs_set = [qf.CQF(int(q), 8) for q in qs]
     st = qf.CQFSet(fs_set)
@@ -217,19 +250,22 @@ def bench_sets(args) -> dict:
     got_loop = np.empty(m, np.uint8)
     got_loop[order] = out_loop.cpu().numpy()
     assert np.array_equal(got_set, got_loop), "set and loop answers differ"
+    assert np.array_equal(got_g, got_loop), "tuned graph and loop answers differ"
     assert got_set[present].all(), "a present key was not found"
     for i in sample:
         rc1, l1 = lay_set[i]
         rc2, l2 = fs_loop[i].export()
-        assert rc1 == 0 and rc2 == 0
+        rc3, l3 = lay_g[i]
+        assert rc1 == 0 and rc2 == 0 and rc3 == 0
         for name in ("occ_words", "runend_words", "slots", "offsets", "header"):
             assert np.array_equal(getattr(l1, name), getattr(l2, name)), f"filter {i}: {name} differs"
+            assert np.array_equal(getattr(l3, name), getattr(l2, name)), f"filter {i}: {name} differs (graph)"
     fp_rate = float(got_set[~present].mean())
     for f in fs_loop:
         f.close()
     res = {
         "metric": "filter-set fill and query throughput (4096 filters of 2^10..2^20 quotients, r=8, load 0.85)",
-        "value": round(total / t_set_fill / 1e9, 4),
+        "value": round(total / t_g_fill / 1e9, 4),
         "unit": "B inserts/s",
         "n_gpus": 1,
         "higher_is_better": True,
@@ -237,11 +273,16 @@ def bench_sets(args) -> dict:
         "data": "synthetic",
         "config": {"workload": f"c4_sets_{nf}filters_q10to20_r8_load0.85", "filters": nf, "fill_keys": total,
                    "queries": m},
+        "tuned_graph": {"fill_s": round(t_g_fill, 4), "fill_Bps": round(total / t_g_fill / 1e9, 4),
+                        "query_ms": round(t_g_query * 1e3, 3), "query_Bps": round(m / t_g_query / 1e9, 4),
+                        "tuning": tuning, "autotune_s": round(t_tune, 2)},
         "set": {"fill_s": round(t_set_fill, 4), "fill_Bps": round(total / t_set_fill / 1e9, 4),
                 "query_ms": round(t_set_query * 1e3, 3), "query_Bps": round(m / t_set_query / 1e9, 4)},
         "loop": {"fill_s": round(t_loop_fill, 4), "fill_Bps": round(total / t_loop_fill / 1e9, 4),
                  "query_ms": round(t_loop_query * 1e3, 3), "query_Bps": round(m / t_loop_query / 1e9, 4)},
-        "speedup": {"fill": round(t_loop_fill / t_set_fill, 2), "query": round(t_loop_query / t_set_query, 2)},
+        "speedup": {"fill": round(t_loop_fill / t_set_fill, 2), "query": round(t_loop_query / t_set_query, 2),
+                    "tuned_graph_fill": round(t_loop_fill / t_g_fill, 2),
+                    "tuned_graph_query": round(t_loop_query / t_g_query, 2)},
         "absent_positive_rate": round(fp_rate, 6),
     }
     return res

@@ -125,7 +125,9 @@ int qf_last_error(void);
  * nothing.  May wait for `stream` when the area grows. */
 int qf_reserve(qf_t *f, uint64_t n, void *stream);
 
-/* Device bytes of one table copy of a (q, r) filter (blocks + offsets). */
+/* Device bytes of one table copy of a (q, r) filter: 64-slot blocks of 128
+ * bytes (r = 8) or 160 bytes (r = 16), each holding its occupied bits, run-end
+ * bits, offset and slots. */
 uint64_t qf_table_bytes(uint32_t q, uint32_t r);
 
 /* info[0..7] = q, r, N, E, P, region slots, device bytes held, batches run. */
@@ -205,6 +207,75 @@ int qf_set_reserve(qf_set_t *s, uint64_t n, void *stream);
 int qf_set_info(const qf_set_t *s, uint64_t *info);
 int qf_set_profile_enable(qf_set_t *s, int enable);
 int qf_set_profile_read(qf_set_t *s, double *ms, uint64_t *n);
+
+/* ---- launch parameters ---------------------------------------------------
+ * How a pipeline (a filter's own, or a set's) cuts its work into
+ * work-groups.  They change speed, never results: the table is canonical.
+ * 0 in a field selects the default.
+ *   region_log2          slots per merge region (one work-group's share of
+ *                        the table), log2 in [6, 13]; capped at the largest
+ *                        region the merge's LDS holds (2^13 slots for r = 8,
+ *                        2^12 for r = 16) and at q.  Default: that cap.
+ *   sort_tile            keys a sort work-group orders in LDS per step:
+ *                        2048 or 4096 (default).
+ *   sort_chunk           fewest keys per sort work-group, a power of two in
+ *                        [4096 (default), 65536]; sets the sort's grid.
+ *   lookup_keys_per_lane keys one lane of a query / count launch looks up:
+ *                        1 (default), 2 or 4; sets the lookup grid.
+ * qf_tune / qf_set_tune check the fields (QF_ERR_ARG, nothing changed),
+ * wait for the device, rebuild the pipeline (its scratch capacity is kept)
+ * and switch its profiling off.  The get calls report the parameters in
+ * effect, region_log2 as the largest region log2 of the pipeline. */
+typedef struct qf_tuning {
+  uint32_t region_log2;
+  uint32_t sort_tile;
+  uint32_t sort_chunk;
+  uint32_t lookup_keys_per_lane;
+} qf_tuning_t;
+int qf_tune(qf_t *f, const qf_tuning_t *t);
+int qf_get_tuning(const qf_t *f, qf_tuning_t *t);
+int qf_set_tune(qf_set_t *s, const qf_tuning_t *t);
+int qf_set_get_tuning(const qf_set_t *s, qf_tuning_t *t);
+
+/* Autotuner for filter sets: picks launch parameters for a set of nf
+ * filters with quotient bits qs[0..nf) (host) and remainder bits r that is
+ * filled to `load` (fraction of 2^q per filter) by one set insert batch and
+ * then answers set query batches of n_query keys (spread over the filters in
+ * proportion to 2^q, half of them present).  It builds private filters of a
+ * sample of those sizes (at most 2^26 quotients in total, every k-th
+ * filter), times candidate parameters on them on the device with synthetic
+ * keys (region size first, then the sort's tile and chunk, then keys per
+ * lane for the lookups; each candidate's best of two runs) and writes the
+ * fastest to *best.  ms (host, 2 doubles, may be NULL) receives the insert and
+ * query milliseconds of the chosen parameters on the sample.  Synchronous;
+ * it uses the null stream and frees what it allocated.  Results are cached
+ * per process by (qs, r, load, n_query). */
+int qf_autotune_set(const uint32_t *qs, uint32_t nf, uint32_t r, double load, uint64_t n_query,
+                    qf_tuning_t *best, double *ms);
+
+/* ---- stream capture ------------------------------------------------------
+ * The batch calls (qf_insert_batch, qf_delete_batch, qf_query_batch,
+ * qf_count_batch and the qf_set_ forms without _some) can be recorded into
+ * a graph and replayed: qf_graph_begin starts capturing `stream` (not NULL;
+ * thread-local capture mode), the calls enqueue as usual, qf_graph_end ends
+ * the capture and instantiates it (NULL on error, see qf_last_error), and
+ * each qf_graph_launch replays every recorded launch on `stream` against
+ * the filters' current contents, reading the key buffers and writing the
+ * outputs given at capture time.  Everything a batch keeps between launches
+ * lives on the device, so replays behave like the same calls made again.
+ * Before capturing, reserve scratch for the largest batch (qf_reserve /
+ * qf_set_reserve) and leave profiling off: under capture a call that would
+ * have to allocate, copy from host memory or time itself fails with
+ * QF_ERR_ARG.  qf_sync, qf_export, qf_import, the _some calls, the tune
+ * calls and the serving calls must not be used on a stream being captured.
+ * Deferred device errors of replayed batches surface at qf_sync /
+ * qf_set_sync as for direct calls; a delete's not-found counts are added
+ * to the captured d_not_found on every replay. */
+typedef struct qf_graph qf_graph_t;
+int qf_graph_begin(void *stream);
+qf_graph_t *qf_graph_end(void *stream);
+int qf_graph_launch(qf_graph_t *g, void *stream);
+void qf_graph_destroy(qf_graph_t *g); /* NULL-safe */
 
 /* ---- serving: device-resident filters, requests batched as they arrive ----
  * A server keeps filters in HBM and answers requests submitted from any host

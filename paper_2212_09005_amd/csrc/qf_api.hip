@@ -99,7 +99,14 @@ void pipe_free(qf::Pipe &p) {
   p = qf::Pipe();
 }
 
-qf::FDesc desc_of(const qf_filter *f, uint32_t rbase) {
+// region log2 of filter f in a pipeline that asks for `req` (0: the largest
+// region the merge's LDS holds, and never more than the filter's quotients)
+uint32_t rlog_for(const qf_filter *f, uint32_t req) {
+  const uint32_t mx = std::min<uint32_t>(f->q, static_cast<uint32_t>(qf::max_region_log2(f->r)));
+  return req == 0 ? mx : std::min(mx, std::max<uint32_t>(req, 6));
+}
+
+qf::FDesc desc_of(const qf_filter *f, uint32_t rbase, uint32_t rlog) {
   qf::FDesc d;
   std::memset(&d, 0, sizeof(d));
   d.blk[0] = f->blk[0];
@@ -110,9 +117,10 @@ qf::FDesc desc_of(const qf_filter *f, uint32_t rbase) {
   d.nblocks = static_cast<int64_t>(f->nblocks);
   d.q = f->q;
   d.r = f->r;
-  d.rlog = f->rlog;
-  d.nregions = f->nregions;
-  d.nqregions = f->nqregions;
+  d.rlog = rlog;
+  const uint64_t S = 1ull << rlog;
+  d.nqregions = static_cast<uint32_t>(f->N / S);
+  d.nregions = static_cast<uint32_t>((f->P + S - 1) / S);
   d.rbase = rbase;
   return d;
 }
@@ -125,18 +133,22 @@ uint32_t bits_for(uint64_t v) {  // bits of the values 0..v
 
 // The update pipeline of nf filters (same r): descriptors, region map, bounds,
 // look-back words, statistics, old carries, histograms.  Synchronous.
-int pipe_init(qf::Pipe &p, qf_filter *const *fs, uint32_t nf) {
+int pipe_init(qf::Pipe &p, qf_filter *const *fs, uint32_t nf, const qf::Tune &tn) {
   p = qf::Pipe();
+  p.tune = tn;
   p.nf = nf;
   p.r = fs[0]->r;
   (void)hipGetDevice(&p.device);
   std::vector<qf::FDesc> desc(nf);
   uint64_t G = 0;
+  p.h_nreg.resize(nf);
   for (uint32_t i = 0; i < nf; ++i) {
     if (fs[i]->r != p.r) return fail(QF_ERR_ARG);
-    p.RL = std::max(p.RL, fs[i]->rlog);
-    desc[i] = desc_of(fs[i], static_cast<uint32_t>(G));
-    G += fs[i]->nregions;
+    const uint32_t rl = rlog_for(fs[i], tn.region_log2);
+    p.RL = std::max(p.RL, rl);
+    desc[i] = desc_of(fs[i], static_cast<uint32_t>(G), rl);
+    p.h_nreg[i] = desc[i].nregions;
+    G += desc[i].nregions;
   }
   if (G >= (1ull << 31)) return fail(QF_ERR_ARG);
   p.G = static_cast<uint32_t>(G);
@@ -148,7 +160,7 @@ int pipe_init(qf::Pipe &p, qf_filter *const *fs, uint32_t nf) {
   p.h_rbase.resize(nf);
   for (uint32_t i = 0; i < nf; ++i) {
     p.h_rbase[i] = desc[i].rbase;
-    for (uint32_t k = 0; k < fs[i]->nregions; ++k) rmap[desc[i].rbase + k] = i;
+    for (uint32_t k = 0; k < desc[i].nregions; ++k) rmap[desc[i].rbase + k] = i;
   }
   p.hist_words = 256ull * 1024ull + 256ull * 8;  // histograms + per-pass digit totals
   const uint64_t tag_words = 8ull * G + 8;        // 3 G tags, 4 G statistics, G carries
@@ -177,11 +189,20 @@ int pipe_init(qf::Pipe &p, qf_filter *const *fs, uint32_t nf) {
   return QF_OK;
 }
 
+// true while `s` is being captured into a graph: nothing may allocate,
+// synchronise or copy from pageable host memory then
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
+}
+
 // hash -> radix sort -> reduction -> region bounds -> merge, on stream s.
 // fid == nullptr: the pipeline has one filter and keys are its own.
 int pipe_update(qf::Pipe &p, const uint64_t *keys, const uint32_t *fid, uint64_t n, int del,
                 uint64_t *not_found, hipStream_t s, uint32_t single_q, const qf_set *set = nullptr,
                 const uint32_t *h_active = nullptr, uint32_t nactive = 0) {
+  // under capture: scratch must be reserved, lists and timers are refused
+  if (capturing(s) && (n > p.cap || h_active || p.timer)) return fail(QF_ERR_ARG);
   int rc = ensure_scratch(p, n, s);
   if (rc) return rc;
   // restrict the merge to the listed filters (their regions, in order); the
@@ -195,7 +216,7 @@ int pipe_update(qf::Pipe &p, const uint64_t *keys, const uint32_t *fid, uint64_t
     for (uint32_t k = 0; k < nactive; ++k) {
       const uint32_t f = h_active[k];
       if (f >= set->nf || (k && f <= h_active[k - 1])) return fail(QF_ERR_ARG);
-      for (uint32_t R = 0; R < set->fs[f]->nregions; ++R) p.h_areg.push_back(p.h_rbase[f] + R);
+      for (uint32_t R = 0; R < p.h_nreg[f]; ++R) p.h_areg.push_back(p.h_rbase[f] + R);
     }
     QF_HIP(hipMemcpyAsync(p.d_afil, p.h_afil.data(), nactive * sizeof(uint32_t), hipMemcpyHostToDevice, s));
     QF_HIP(hipMemcpyAsync(p.d_areg, p.h_areg.data(), p.h_areg.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
@@ -206,21 +227,18 @@ int pipe_update(qf::Pipe &p, const uint64_t *keys, const uint32_t *fid, uint64_t
   uint64_t *sorted = nullptr;
   if (fid) {
     QF_HIP(qf::launch_hash_multi(keys, fid, n, p, p.bufA, s, p.timer));
-    QF_HIP(qf::launch_sort(p.bufA, p.bufB, n, p.gbits + p.RL + p.r, p.hist, &sorted, s, p.timer));
+    QF_HIP(qf::launch_sort(p.bufA, p.bufB, n, p.gbits + p.RL + p.r, p.hist, &sorted, s, p));
   } else {
     // one filter: its composite key is the fingerprint itself, and the first
     // sort pass hashes the keys
     const uint32_t bits = single_q + p.r;
     const uint64_t pmask = bits >= 64 ? ~0ull : ((1ull << bits) - 1ull);
-    QF_HIP(qf::launch_sort(p.bufA, p.bufB, n, bits, p.hist, &sorted, s, p.timer, keys, pmask));
+    QF_HIP(qf::launch_sort(p.bufA, p.bufB, n, bits, p.hist, &sorted, s, p, keys, pmask));
   }
   uint64_t *other = sorted == p.bufA ? p.bufB : p.bufA;
-  QF_HIP(qf::launch_rle(sorted, n, other, p.bufC, p.bufD, p.hist, p.pst, s, p.timer));
+  QF_HIP(qf::launch_rle(sorted, n, other, p.bufC, p.bufD, p.hist, p.pst, s, p));
   QF_HIP(qf::launch_bounds(p.bufC, p, s));
-  const bool wrap = p.epoch == 65535;
-  if (wrap) p.epoch = 0;
-  p.epoch += 1;
-  QF_HIP(qf::launch_merge(p, p.bufC, p.bufD, del, not_found, wrap, s));
+  QF_HIP(qf::launch_merge(p, p.bufC, p.bufD, del, not_found, s));
   p.batches += 1;
   return QF_OK;
 }
@@ -297,6 +315,39 @@ struct EventTimer : qf::Timer {
   }
 };
 
+bool tuning_from(const qf_tuning_t &t, qf::Tune *out) {
+  qf::Tune d;
+  if (t.region_log2 != 0 && (t.region_log2 < 6 || t.region_log2 > 13)) return false;
+  if (t.sort_tile != 0 && t.sort_tile != 2048 && t.sort_tile != 4096) return false;
+  if (t.sort_chunk != 0 && (t.sort_chunk < 4096 || t.sort_chunk > 65536 || (t.sort_chunk & (t.sort_chunk - 1))))
+    return false;
+  const uint32_t k = t.lookup_keys_per_lane;
+  if (k != 0 && k != 1 && k != 2 && k != 4) return false;
+  out->region_log2 = t.region_log2;
+  out->sort_tile = t.sort_tile ? t.sort_tile : d.sort_tile;
+  out->sort_chunk = t.sort_chunk ? t.sort_chunk : d.sort_chunk;
+  out->lookup_kpl = k ? k : d.lookup_kpl;
+  return true;
+}
+
+void tuning_to(const qf::Pipe &p, qf_tuning_t *t) {
+  t->region_log2 = p.RL;
+  t->sort_tile = p.tune.sort_tile;
+  t->sort_chunk = p.tune.sort_chunk;
+  t->lookup_keys_per_lane = p.tune.lookup_kpl;
+}
+
+// rebuild a pipeline with new launch parameters (waits for the device; keeps
+// the scratch capacity, drops the launch timer)
+int retune(qf::Pipe &p, qf_filter *const *fs, uint32_t nf, const qf::Tune &tn) {
+  QF_HIP(hipDeviceSynchronize());
+  const uint64_t cap = p.cap;
+  pipe_free(p);
+  int rc = pipe_init(p, fs, nf, tn);
+  if (rc == QF_OK && cap) rc = ensure_scratch(p, cap, nullptr);
+  return rc;
+}
+
 int profile_enable(qf::Pipe &p, int enable) {
   if (enable && !p.timer) p.timer = new (std::nothrow) EventTimer();
   if (enable && !p.timer) return fail(QF_ERR_OOM);
@@ -347,10 +398,6 @@ qf_t *qf_create(uint32_t q, uint32_t r) {
   f->E = extra_slots(q);
   f->P = f->N + f->E;
   f->nblocks = f->P / 64;
-  f->rlog = std::min<uint32_t>(q, static_cast<uint32_t>(qf::max_region_log2(r)));
-  const uint64_t S = 1ull << f->rlog;
-  f->nqregions = static_cast<uint32_t>(f->N / S);
-  f->nregions = static_cast<uint32_t>((f->P + S - 1) / S);
   f->block_bytes = static_cast<uint32_t>(qf::table_bytes(1, r));
   (void)hipGetDevice(&f->device);
   bool ok = true;
@@ -366,7 +413,7 @@ qf_t *qf_create(uint32_t q, uint32_t r) {
     return nullptr;
   }
   qf_filter *self[1] = {f};
-  if (pipe_init(f->pipe, self, 1) != QF_OK) {
+  if (pipe_init(f->pipe, self, 1, qf::Tune()) != QF_OK) {
     qf_destroy(f);
     fail(QF_ERR_OOM);
     return nullptr;
@@ -538,7 +585,7 @@ qf_set_t *qf_set_create(qf_t *const *filters, uint32_t nf) {
     return nullptr;
   }
   for (uint32_t i = 0; i < nf; ++i) st->fs[i] = filters[i];
-  const int rc = pipe_init(st->pipe, st->fs, nf);
+  const int rc = pipe_init(st->pipe, st->fs, nf, qf::Tune());
   if (rc != QF_OK) {
     delete[] st->fs;
     delete st;
@@ -677,7 +724,7 @@ int qf_info(const qf_t *f, uint64_t *info) {
   info[2] = f->N;
   info[3] = f->E;
   info[4] = f->P;
-  info[5] = 1ull << f->rlog;
+  info[5] = 1ull << f->pipe.one.rlog;
   info[6] = f->table_device_bytes + f->pipe.device_bytes;
   info[7] = f->pipe.batches;
   return QF_OK;
@@ -691,6 +738,88 @@ int qf_profile_enable(qf_t *f, int enable) {
 int qf_profile_read(qf_t *f, double *ms, uint64_t *n) {
   if (!f || !ms || !n) return fail(QF_ERR_ARG);
   return profile_read(f->pipe, ms, n);
+}
+
+// ---- launch parameters -----------------------------------------------------
+
+int qf_tune(qf_t *f, const qf_tuning_t *t) {
+  if (!f || !t) return fail(QF_ERR_ARG);
+  qf::Tune tn;
+  if (!tuning_from(*t, &tn)) return fail(QF_ERR_ARG);
+  qf_filter *self[1] = {f};
+  return retune(f->pipe, self, 1, tn);
+}
+
+int qf_get_tuning(const qf_t *f, qf_tuning_t *t) {
+  if (!f || !t) return fail(QF_ERR_ARG);
+  tuning_to(f->pipe, t);
+  return QF_OK;
+}
+
+int qf_set_tune(qf_set_t *st, const qf_tuning_t *t) {
+  if (!st || !t) return fail(QF_ERR_ARG);
+  qf::Tune tn;
+  if (!tuning_from(*t, &tn)) return fail(QF_ERR_ARG);
+  return retune(st->pipe, st->fs, st->nf, tn);
+}
+
+int qf_set_get_tuning(const qf_set_t *st, qf_tuning_t *t) {
+  if (!st || !t) return fail(QF_ERR_ARG);
+  tuning_to(st->pipe, t);
+  return QF_OK;
+}
+
+// ---- stream capture ----------------------------------------------------------
+
+struct qf_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+int qf_graph_begin(void *stream) {
+  if (!stream) return fail(QF_ERR_ARG);
+  QF_HIP(hipStreamBeginCapture(static_cast<hipStream_t>(stream), hipStreamCaptureModeThreadLocal));
+  return QF_OK;
+}
+
+qf_graph_t *qf_graph_end(void *stream) {
+  if (!stream) {
+    fail(QF_ERR_ARG);
+    return nullptr;
+  }
+  hipGraph_t g = nullptr;
+  if (hipStreamEndCapture(static_cast<hipStream_t>(stream), &g) != hipSuccess || !g) {
+    (void)hipGetLastError();
+    fail(QF_ERR_DEVICE);
+    return nullptr;
+  }
+  qf_graph *q = new (std::nothrow) qf_graph();
+  if (!q) {
+    (void)hipGraphDestroy(g);
+    fail(QF_ERR_OOM);
+    return nullptr;
+  }
+  q->graph = g;
+  if (hipGraphInstantiate(&q->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    qf_graph_destroy(q);
+    fail(QF_ERR_DEVICE);
+    return nullptr;
+  }
+  return q;
+}
+
+int qf_graph_launch(qf_graph_t *g, void *stream) {
+  if (!g || !g->exec) return fail(QF_ERR_ARG);
+  QF_HIP(hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
+  return QF_OK;
+}
+
+void qf_graph_destroy(qf_graph_t *g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
 }
 
 }  // extern "C"

@@ -53,6 +53,7 @@ enum : int {
   ST_NUNIQ = 11,  // distinct fingerprints in the running batch
   ST_BATCHES = 12,
   ST_SCRATCH = 13,  // sink for a NULL not-found pointer
+  ST_EPOCH = 14,    // (pipeline words) epoch of the last merge launch, 1..65535
   ST_WORDS = 16
 };
 enum : uint64_t { BATCH_FULL = 1, BATCH_OVF = 2, BATCH_STALL = 4 };
@@ -111,6 +112,10 @@ __device__ __forceinline__ int64_t fn_apply(Fn f, int64_t c) { return max(f.A, c
 __device__ __forceinline__ void tag_store(uint64_t* p, uint32_t epoch, int64_t v) {
   const uint64_t w = (static_cast<uint64_t>(epoch) << 48) | static_cast<uint64_t>(v + 1);
   __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// the epoch of the next merge launch after one that used e (0 = none yet)
+__device__ __forceinline__ uint32_t next_epoch(uint64_t e) {
+  return e >= 65535 ? 1u : static_cast<uint32_t>(e) + 1u;
 }
 __device__ __forceinline__ bool tag_load(const uint64_t* p, uint32_t epoch, int64_t* v) {
   const uint64_t w = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -15,6 +15,15 @@ struct Timer {
   virtual ~Timer() {}
 };
 
+// Launch parameters of a pipeline.  They change how the work is cut into
+// work-groups, never the results (the table is canonical).
+struct Tune {
+  uint32_t region_log2 = 0;   // slots per merge region, log2 (0: the largest the LDS holds)
+  uint32_t sort_tile = 4096;  // keys a sort work-group orders in LDS per step (2048 or 4096)
+  uint32_t sort_chunk = 4096; // fewest keys per sort work-group (power of two, 2^12..2^16)
+  uint32_t lookup_kpl = 1;    // keys per lane of a lookup launch (1, 2 or 4)
+};
+
 // One filter as the kernels see it (an array of these lives in device memory
 // for every pipeline; a single filter's pipeline has one).
 struct FDesc {
@@ -41,13 +50,13 @@ struct Pipe {
   uint64_t *tags = nullptr;   // 3 G look-back words, then
   uint64_t *rstat = nullptr;  // 4 G per-region merge statistics, then
   int64_t *cb = nullptr;      // G old carries (region boundaries)
-  uint64_t *pst = nullptr;    // ST_WORDS pipeline words (unique count)
+  uint64_t *pst = nullptr;    // ST_WORDS pipeline words (unique count, launch epoch)
   int64_t *d_err = nullptr;   // nf: per-filter deferred errors gathered by qf_set_errors
   // a launch restricted to some filters: their indexes and regions
   uint32_t *d_afil = nullptr, *d_areg = nullptr;  // capacity nf, G
   uint32_t nafil = 0, nareg = 0;                  // 0: all filters
-  std::vector<uint32_t> h_rbase, h_afil, h_areg;  // host copies
-  uint32_t epoch = 0;
+  std::vector<uint32_t> h_rbase, h_nreg, h_afil, h_areg;  // host copies
+  Tune tune;
   int device = 0;
   // grow-only scratch, capacity in keys
   uint64_t cap = 0;
@@ -62,9 +71,8 @@ struct Pipe {
 }  // namespace qf
 
 struct qf_filter {
-  uint32_t q, r, rlog;      // region = 2^rlog slots
+  uint32_t q, r;
   uint64_t N, E, P, nblocks;
-  uint32_t nregions, nqregions;
   uint32_t block_bytes;     // 128 (r = 8) or 160 (r = 16)
   int device;
   void *blk[2];             // two table copies (blocks, offsets inside)
@@ -93,19 +101,19 @@ hipError_t launch_hash_multi(const uint64_t *keys, const uint32_t *fid, uint64_t
 // holds the result (a or b).  With raw != nullptr the input is raw keys
 // (a is not read): the first pass sorts mix64(raw[i]) & pmask.
 hipError_t launch_sort(uint64_t *a, uint64_t *b, uint64_t n, uint32_t bits, uint32_t *hist,
-                       uint64_t **result, hipStream_t s, Timer *t, const uint64_t *raw = nullptr,
+                       uint64_t **result, hipStream_t s, const Pipe &p, const uint64_t *raw = nullptr,
                        uint64_t pmask = 0);
 // run-length reduction of the sorted keys: ufp/ucnt, count in state[ST_NUNIQ]
 hipError_t launch_rle(const uint64_t *sorted, uint64_t n, uint64_t *scratch_start,
                       uint64_t *ufp, uint64_t *ucnt, uint32_t *tile_counts, uint64_t *state,
-                      hipStream_t s, Timer *t);
+                      hipStream_t s, const Pipe &p);
 // region bounds of the pipeline's G regions
 hipError_t launch_bounds(const uint64_t *ufp, Pipe &p, hipStream_t s);
 // old carries, per-filter batch flags, tag reset on epoch wrap, region merge
 // into the other table copies, finish (statistics, flip or deferred error).
 // not_found: nullptr or one word per filter of the pipeline.
 hipError_t launch_merge(Pipe &p, const uint64_t *ufp, const uint64_t *ucnt, int del,
-                        uint64_t *not_found, bool wrap, hipStream_t s);
+                        uint64_t *not_found, hipStream_t s);
 hipError_t launch_lookup(qf_filter *f, const uint64_t *keys, uint64_t n, uint8_t *out8,
                          uint64_t *out64, hipStream_t s);
 hipError_t launch_lookup_multi(const Pipe &p, const uint64_t *keys, const uint32_t *fid, uint64_t n,
@@ -118,8 +126,9 @@ hipError_t launch_export(qf_filter *f, uint64_t *occ, uint64_t *rend, uint16_t *
 hipError_t launch_import(qf_filter *f, const uint64_t *occ, const uint64_t *rend,
                          const uint16_t *slots, const uint32_t *offs, hipStream_t s);
 
-// sort tiling: G work-groups each own a contiguous chunk of the keys
-uint32_t sort_groups(uint64_t n);
+// sort tiling: G work-groups each own a contiguous chunk of at least
+// `chunk` keys (at most SORT_MAX_GROUPS groups)
+uint32_t sort_groups(uint64_t n, uint32_t chunk);
 int max_region_log2(uint32_t r);
 
 }  // namespace qf

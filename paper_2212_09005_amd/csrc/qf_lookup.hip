@@ -74,7 +74,9 @@ __device__ __forceinline__ uint64_t lookup_one(const Block<T> *__restrict__ b, i
   return 0;
 }
 
-template <typename T, bool COUNT>
+// KPL keys per lane, NT apart (coalesced key loads and result stores; the
+// lookups of one lane are independent, so their loads can overlap)
+template <typename T, bool COUNT, int KPL>
 __global__ __launch_bounds__(NT) void k_lookup(const Block<T> *b0, const Block<T> *b1,
                                                const uint64_t *state,
                                                const uint64_t *__restrict__ keys, uint64_t n,
@@ -86,42 +88,54 @@ __global__ __launch_bounds__(NT) void k_lookup(const Block<T> *b0, const Block<T
   const uint32_t p = q + r;
   const uint64_t pmask = p >= 64 ? ~0ull : ((1ull << p) - 1ull);
   const uint64_t rmask = (1ull << r) - 1ull;
-  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * NT;
-  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * NT + threadIdx.x; i < n; i += stride) {
-    const uint64_t fp = mix64(keys[i]) & pmask;
-    const uint64_t c = lookup_one(b, nblocks, static_cast<int64_t>(fp >> r), fp & rmask, r);
-    if (COUNT)
-      out64[i] = c;
-    else
-      out8[i] = c != 0;
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * NT * KPL;
+  for (uint64_t i0 = static_cast<uint64_t>(blockIdx.x) * NT * KPL + threadIdx.x; i0 < n; i0 += stride) {
+#pragma unroll
+    for (int k = 0; k < KPL; ++k) {
+      const uint64_t i = i0 + static_cast<uint64_t>(k) * NT;
+      if (i < n) {
+        const uint64_t fp = mix64(keys[i]) & pmask;
+        const uint64_t c = lookup_one(b, nblocks, static_cast<int64_t>(fp >> r), fp & rmask, r);
+        if (COUNT)
+          out64[i] = c;
+        else
+          out8[i] = c != 0;
+      }
+    }
   }
 }
 
 // Lookups over a filter set: key i is looked up in filter fid[i] (0 for a
 // filter index out of range, which also flags the call in pst[ST_ERR]).
-template <typename T, bool COUNT>
+template <typename T, bool COUNT, int KPL>
 __global__ __launch_bounds__(NT) void k_lookup_multi(const FDesc *__restrict__ desc, uint32_t nf,
                                                      const uint64_t *__restrict__ keys,
                                                      const uint32_t *__restrict__ fid, uint64_t n,
                                                      uint8_t *__restrict__ out8, uint64_t *__restrict__ out64,
                                                      uint64_t *pst) {
-  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * NT;
-  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * NT + threadIdx.x; i < n; i += stride) {
-    const uint32_t f = fid[i];
-    uint64_t c = 0;
-    if (f < nf) {
-      const FDesc &d = desc[f];
-      const bool cur = d.state[ST_CUR] & 1ull;
-      const uint32_t p = d.q + d.r;
-      const uint64_t fp = mix64(keys[i]) & ((1ull << p) - 1ull);
-      c = lookup_one(static_cast<const Block<T> *>(cur ? d.blk[1] : d.blk[0]), d.nblocks, static_cast<int64_t>(fp >> d.r), fp & ((1ull << d.r) - 1ull), d.r);
-    } else {
-      pst[ST_ERR] = static_cast<uint64_t>(static_cast<int64_t>(QF_ERR_ARG));
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * NT * KPL;
+  for (uint64_t i0 = static_cast<uint64_t>(blockIdx.x) * NT * KPL + threadIdx.x; i0 < n; i0 += stride) {
+#pragma unroll
+    for (int k = 0; k < KPL; ++k) {
+      const uint64_t i = i0 + static_cast<uint64_t>(k) * NT;
+      if (i >= n) break;
+      const uint32_t f = fid[i];
+      uint64_t c = 0;
+      if (f < nf) {
+        const FDesc &d = desc[f];
+        const bool cur = d.state[ST_CUR] & 1ull;
+        const uint32_t p = d.q + d.r;
+        const uint64_t fp = mix64(keys[i]) & ((1ull << p) - 1ull);
+        c = lookup_one(static_cast<const Block<T> *>(cur ? d.blk[1] : d.blk[0]), d.nblocks,
+                       static_cast<int64_t>(fp >> d.r), fp & ((1ull << d.r) - 1ull), d.r);
+      } else {
+        pst[ST_ERR] = static_cast<uint64_t>(static_cast<int64_t>(QF_ERR_ARG));
+      }
+      if (COUNT)
+        out64[i] = c;
+      else
+        out8[i] = c != 0;
     }
-    if (COUNT)
-      out64[i] = c;
-    else
-      out8[i] = c != 0;
   }
 }
 
@@ -163,40 +177,63 @@ __global__ __launch_bounds__(NT) void k_import(Block<T> *b, int64_t nblocks,
   }
 }
 
-inline uint32_t grid_for(uint64_t n) {
-  uint64_t g = (n + NT - 1) / NT;
+inline uint32_t grid_for(uint64_t n, uint32_t kpl = 1) {
+  uint64_t g = (n + NT * kpl - 1) / (NT * kpl);
   if (g < 1) g = 1;
   if (g > 262140) g = 262140;
   return static_cast<uint32_t>(g);
 }
 
+template <typename T, int KPL>
+void lookup_kpl(qf_filter *f, const uint64_t *keys, uint64_t n, uint8_t *out8, uint64_t *out64, hipStream_t s) {
+  const Block<T> *b0 = static_cast<const Block<T> *>(f->blk[0]);
+  const Block<T> *b1 = static_cast<const Block<T> *>(f->blk[1]);
+  const int64_t nb = static_cast<int64_t>(f->nblocks);
+  if (out64)
+    k_lookup<T, true, KPL><<<grid_for(n, KPL), NT, 0, s>>>(b0, b1, f->state, keys, n, f->q, f->r, nb, nullptr,
+                                                           out64);
+  else
+    k_lookup<T, false, KPL><<<grid_for(n, KPL), NT, 0, s>>>(b0, b1, f->state, keys, n, f->q, f->r, nb, out8,
+                                                            nullptr);
+}
+
 template <typename T>
 hipError_t lookup_t(qf_filter *f, const uint64_t *keys, uint64_t n, uint8_t *out8,
                     uint64_t *out64, hipStream_t s) {
-  const Block<T> *b0 = static_cast<const Block<T> *>(f->blk[0]);
-  const Block<T> *b1 = static_cast<const Block<T> *>(f->blk[1]);
   Timer *t = f->pipe.timer;
   if (t) t->begin(QF_PROF_LOOKUP, s);
-  if (out64)
-    k_lookup<T, true><<<grid_for(n), NT, 0, s>>>(b0, b1, f->state, keys, n,
-                                                 f->q, f->r, static_cast<int64_t>(f->nblocks),
-                                                 nullptr, out64);
+  const uint32_t kpl = f->pipe.tune.lookup_kpl;
+  if (kpl >= 4)
+    lookup_kpl<T, 4>(f, keys, n, out8, out64, s);
+  else if (kpl == 2)
+    lookup_kpl<T, 2>(f, keys, n, out8, out64, s);
   else
-    k_lookup<T, false><<<grid_for(n), NT, 0, s>>>(b0, b1, f->state, keys, n,
-                                                  f->q, f->r, static_cast<int64_t>(f->nblocks),
-                                                  out8, nullptr);
+    lookup_kpl<T, 1>(f, keys, n, out8, out64, s);
   if (t) t->end(QF_PROF_LOOKUP, s);
   return hipGetLastError();
+}
+
+template <typename T, int KPL>
+void lookup_multi_kpl(const Pipe &p, const uint64_t *keys, const uint32_t *fid, uint64_t n, uint8_t *out8,
+                      uint64_t *out64, hipStream_t s) {
+  if (out64)
+    k_lookup_multi<T, true, KPL><<<grid_for(n, KPL), NT, 0, s>>>(p.d_desc, p.nf, keys, fid, n, nullptr, out64,
+                                                                 p.pst);
+  else
+    k_lookup_multi<T, false, KPL><<<grid_for(n, KPL), NT, 0, s>>>(p.d_desc, p.nf, keys, fid, n, out8, nullptr,
+                                                                  p.pst);
 }
 
 template <typename T>
 hipError_t lookup_multi_t(const Pipe &p, const uint64_t *keys, const uint32_t *fid, uint64_t n, uint8_t *out8,
                           uint64_t *out64, hipStream_t s) {
   if (p.timer) p.timer->begin(QF_PROF_LOOKUP, s);
-  if (out64)
-    k_lookup_multi<T, true><<<grid_for(n), NT, 0, s>>>(p.d_desc, p.nf, keys, fid, n, nullptr, out64, p.pst);
+  if (p.tune.lookup_kpl >= 4)
+    lookup_multi_kpl<T, 4>(p, keys, fid, n, out8, out64, s);
+  else if (p.tune.lookup_kpl == 2)
+    lookup_multi_kpl<T, 2>(p, keys, fid, n, out8, out64, s);
   else
-    k_lookup_multi<T, false><<<grid_for(n), NT, 0, s>>>(p.d_desc, p.nf, keys, fid, n, out8, nullptr, p.pst);
+    lookup_multi_kpl<T, 1>(p, keys, fid, n, out8, out64, s);
   if (p.timer) p.timer->end(QF_PROF_LOOKUP, s);
   return hipGetLastError();
 }

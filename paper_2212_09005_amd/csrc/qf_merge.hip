@@ -85,7 +85,8 @@ struct MergeArgs {
   uint64_t *tags;                   // 3 G look-back words
   uint64_t *rstat;                  // 4 words per region: used, distinct, total, shortfall
   const int64_t *cb;                // old carries at region boundaries
-  uint32_t G, epoch;
+  const uint64_t *pst;               // pipeline words: the epoch of the last launch
+  uint32_t G;
   int del;
   const uint32_t *areg;  // the launch's regions (nullptr: all G, in order)
   // per-entry scratch (indexed like the reduced batch) for regions with more
@@ -228,10 +229,21 @@ __device__ int64_t carry_old(const Block<T> *b, int64_t i, int64_t N) {
 // the pipeline, or those listed in areg): the old carry at the region's
 // first slot (cb[g] = carry_old(R S) for local regions R up to the first
 // extra-slot region) and the filter's batch flags (by its region 0).
+// The launch epoch lives in device memory (so that a captured graph replays
+// with a fresh one); when it wraps, the grid (which covers all G regions of
+// the pipeline) clears every look-back word, also those of regions outside
+// the launch, which could otherwise carry an old word with a current epoch
+// into a later launch.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_carries(const FDesc *__restrict__ desc, const uint32_t *__restrict__ rmap,
-                                                const uint32_t *__restrict__ areg, uint32_t nreg, int64_t *cb) {
+                                                const uint32_t *__restrict__ areg, uint32_t nreg, int64_t *cb,
+                                                uint64_t *tags, uint32_t G, const uint64_t *pst) {
   const uint32_t i = blockIdx.x * NT + threadIdx.x;
+  if (i < G && next_epoch(pst[ST_EPOCH]) == 1u) {
+    tags[i] = 0;
+    tags[static_cast<uint64_t>(G) + i] = 0;
+    tags[2ull * G + i] = 0;
+  }
   if (i >= nreg) return;
   const uint32_t g = areg ? areg[i] : i;
   const FDesc &d = desc[rmap[g]];
@@ -847,6 +859,7 @@ __device__ __forceinline__ void merge_body(const MergeArgs &a, const Smem<T> &m)
   const uint64_t ne = rb1 - rb0;
   const uint32_t r = fd.r;
   const uint64_t lmask = (1ull << (rlog + r)) - 1ull;  // fingerprint bits inside the region
+  const uint32_t epoch = next_epoch(a.pst[ST_EPOCH]);
 
   for (int w = tid; w < nw_reg; w += NT) {
     occ_l[w] = qreg ? gob[(RS >> 6) + w].occ : 0ull;
@@ -1020,16 +1033,16 @@ __device__ __forceinline__ void merge_body(const MergeArgs &a, const Smem<T> &m)
   const uint64_t ovf = block_sum_u64(acc.ovf, sh_r);
 
   if (tid == 0) {
-    tag_store(&a.tags[gR], a.epoch, Ftot.A);
-    tag_store(&a.tags[static_cast<uint64_t>(a.G) + gR], a.epoch, Ftot.B);
+    tag_store(&a.tags[gR], epoch, Ftot.A);
+    tag_store(&a.tags[static_cast<uint64_t>(a.G) + gR], epoch, Ftot.B);
   }
   if (tid < 64) {
     bool stalled = false;
-    const int64_t c_in = look_back_wave(a.tags, a.G, a.epoch, gR, fd.rbase, &stalled);
+    const int64_t c_in = look_back_wave(a.tags, a.G, epoch, gR, fd.rbase, &stalled);
     if (tid == 0) {
       if (stalled) atomic_or_u64(&fstate[ST_BATCH], BATCH_STALL);
       const int64_t c_out = fn_apply(Ftot, c_in);
-      tag_store(&a.tags[2ull * a.G + gR], a.epoch, c_out);
+      tag_store(&a.tags[2ull * a.G + gR], epoch, c_out);
       sh_i[3] = c_in;
       sh_i[4] = c_out;
       // errors are rare and set one shared word; the statistics go to the
@@ -1185,8 +1198,10 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs a) {
 // After the merge, one work-group per filter: sum its regions' statistics;
 // flip its current copy if none of its regions failed, else record the error
 // (all-or-nothing per filter); add its delete shortfall to not_found[f].
+// The first work-group records the launch's epoch as the pipeline's last.
 __global__ __launch_bounds__(1024) void k_finish(const FDesc *__restrict__ desc, const uint32_t *__restrict__ afil,
-                                                 const uint64_t *rstat, int del, uint64_t *not_found) {
+                                                 const uint64_t *rstat, int del, uint64_t *not_found,
+                                                 uint64_t *pst) {
   __shared__ uint64_t sh[4][16];
   const uint32_t f = afil ? afil[blockIdx.x] : blockIdx.x;
   const FDesc &d = desc[f];
@@ -1216,12 +1231,13 @@ __global__ __launch_bounds__(1024) void k_finish(const FDesc *__restrict__ desc,
     }
     if (del && not_found) not_found[f] += t[3];
     state[ST_BATCHES] += 1;
+    if (blockIdx.x == 0) pst[ST_EPOCH] = next_epoch(pst[ST_EPOCH]);
   }
 }
 
 template <typename T>
 hipError_t launch_merge_t(Pipe &p, const uint64_t *ufp, const uint64_t *ucnt, int del, uint64_t *not_found,
-                          bool wrap, hipStream_t s) {
+                          hipStream_t s) {
   MergeArgs a;
   a.desc = p.d_desc;
   a.rmap = p.d_rmap;
@@ -1232,7 +1248,7 @@ hipError_t launch_merge_t(Pipe &p, const uint64_t *ufp, const uint64_t *ucnt, in
   a.rstat = p.rstat;
   a.cb = p.cb;
   a.G = p.G;
-  a.epoch = p.epoch;
+  a.pst = p.pst;
   a.del = del;
   // per-entry scratch: bufE holds cap entries of 32 bytes
   uint8_t *e = reinterpret_cast<uint8_t *>(p.bufE);
@@ -1251,14 +1267,8 @@ hipError_t launch_merge_t(Pipe &p, const uint64_t *ufp, const uint64_t *ucnt, in
   const uint32_t *areg = p.nareg ? p.d_areg : nullptr;
   const uint32_t nreg = p.nareg ? p.nareg : p.G;
   a.areg = areg;
-  // when the 16-bit launch epoch wraps, every look-back word is cleared (also
-  // those of regions outside this launch, which could otherwise carry an
-  // old word with a current epoch into a later launch)
-  if (wrap) {
-    const hipError_t e = launch_fill_u64(p.tags, 3ull * p.G, 0, s);
-    if (e != hipSuccess) return e;
-  }
-  k_carries<T><<<(nreg + NT - 1) / NT, NT, 0, s>>>(p.d_desc, p.d_rmap, areg, nreg, p.cb);
+  const uint32_t ncar = nreg > p.G ? nreg : p.G;
+  k_carries<T><<<(ncar + NT - 1) / NT, NT, 0, s>>>(p.d_desc, p.d_rmap, areg, nreg, p.cb, p.tags, p.G, p.pst);
   if (p.nf == 1) {
     a.one = p.one;
     k_merge<T, true><<<nreg, NT, 0, s>>>(a);
@@ -1266,7 +1276,7 @@ hipError_t launch_merge_t(Pipe &p, const uint64_t *ufp, const uint64_t *ucnt, in
     k_merge<T, false><<<nreg, NT, 0, s>>>(a);
   }
   k_finish<<<p.nareg ? p.nafil : p.nf, 1024, 0, s>>>(p.d_desc, p.nareg ? p.d_afil : nullptr, p.rstat, del,
-                                                     not_found);
+                                                     not_found, p.pst);
   if (p.timer) p.timer->end(QF_PROF_MERGE, s);
   return hipGetLastError();
 }
@@ -1274,9 +1284,9 @@ hipError_t launch_merge_t(Pipe &p, const uint64_t *ufp, const uint64_t *ucnt, in
 }  // namespace
 
 hipError_t launch_merge(Pipe &p, const uint64_t *ufp, const uint64_t *ucnt, int del, uint64_t *not_found,
-                        bool wrap, hipStream_t s) {
-  if (p.r == 8) return launch_merge_t<uint8_t>(p, ufp, ucnt, del, not_found, wrap, s);
-  return launch_merge_t<uint16_t>(p, ufp, ucnt, del, not_found, wrap, s);
+                        hipStream_t s) {
+  if (p.r == 8) return launch_merge_t<uint8_t>(p, ufp, ucnt, del, not_found, s);
+  return launch_merge_t<uint16_t>(p, ufp, ucnt, del, not_found, s);
 }
 
 int max_region_log2(uint32_t r) { return r == 8 ? Cfg<uint8_t>::SMAXLOG : Cfg<uint16_t>::SMAXLOG; }

@@ -16,7 +16,6 @@ namespace {
 
 constexpr int NT = 256;
 constexpr int NWAVE = NT / 64;
-constexpr uint64_t SORT_MIN_CHUNK = 4096;
 constexpr uint32_t SORT_MAX_GROUPS = 1024;
 
 __device__ __forceinline__ uint64_t chunk_lo(uint64_t n, uint32_t G, uint32_t g) {
@@ -162,20 +161,19 @@ __global__ __launch_bounds__(1024) void k_scan_u32(uint32_t *a, uint32_t n, uint
 }
 
 // Stable scatter of one digit.  Each group takes its chunk in tiles of TILE
-// keys: the tile is ordered by digit in LDS (ranks from wave ballots, rounds
-// of 256 keys in index order, so the order is stable), then written out so
-// that each digit's keys of the tile land as one contiguous run -- coalesced
-// stores instead of one 8-byte store per key to a different line.
-constexpr int TILE = 4096;
-constexpr int KPL = TILE / NT;  // keys per lane and tile
-
-template <bool HASH>
+// keys (KPL = TILE / NT per lane): the tile is ordered by digit in LDS (ranks
+// from wave ballots, rounds of 256 keys in index order, so the order is
+// stable), then written out so that each digit's keys of the tile land as
+// one contiguous run -- coalesced stores instead of one 8-byte store per key
+// to a different line.
+template <bool HASH, int TILE>
 __global__ __launch_bounds__(NT) void k_rs_scatter(const uint64_t *__restrict__ in,
                                                    uint64_t *__restrict__ out, uint64_t n,
                                                    uint32_t G, uint32_t shift, uint32_t nbits,
                                                    uint64_t pmask,
                                                    const uint32_t *__restrict__ hist,
                                                    const uint32_t *__restrict__ dtot) {
+  constexpr int KPL = TILE / NT;
   __shared__ uint64_t tile[TILE];
   __shared__ uint32_t gpos[256];  // global position of the group's next key of digit d
   __shared__ uint32_t loff[256];  // start of digit d in the tile
@@ -364,8 +362,8 @@ inline uint32_t blocks_for(uint64_t n, uint32_t cap = 65535u * 4u) {
 
 }  // namespace
 
-uint32_t sort_groups(uint64_t n) {
-  uint64_t g = (n + SORT_MIN_CHUNK - 1) / SORT_MIN_CHUNK;
+uint32_t sort_groups(uint64_t n, uint32_t chunk) {
+  uint64_t g = (n + chunk - 1) / chunk;
   if (g < 1) g = 1;
   if (g > SORT_MAX_GROUPS) g = SORT_MAX_GROUPS;
   return static_cast<uint32_t>(g);
@@ -399,8 +397,10 @@ hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s) {
 }
 
 hipError_t launch_sort(uint64_t *a, uint64_t *b, uint64_t n, uint32_t bits, uint32_t *hist,
-                       uint64_t **result, hipStream_t s, Timer *t, const uint64_t *raw, uint64_t pmask) {
-  const uint32_t G = sort_groups(n);
+                       uint64_t **result, hipStream_t s, const Pipe &pp, const uint64_t *raw, uint64_t pmask) {
+  Timer *t = pp.timer;
+  const uint32_t G = sort_groups(n, pp.tune.sort_chunk);
+  const bool small = pp.tune.sort_tile == 2048;
   const uint32_t npass = (bits + 7) / 8;
   // digit totals live after the G * 256 histogram words
   uint32_t *dtot = hist + 256ull * SORT_MAX_GROUPS;
@@ -420,10 +420,14 @@ hipError_t launch_sort(uint64_t *a, uint64_t *b, uint64_t n, uint32_t bits, uint
     k_rs_offsets<<<256, NT, 0, s>>>(hist, G, dtot);
     if (t) t->end(QF_PROF_SORT_SCAN, s);
     if (t) t->begin(QF_PROF_SORT_SCATTER, s);
-    if (hash)
-      k_rs_scatter<true><<<G, NT, 0, s>>>(raw, out, n, G, shift, nb, pmask, hist, dtot);
+    if (hash && small)
+      k_rs_scatter<true, 2048><<<G, NT, 0, s>>>(raw, out, n, G, shift, nb, pmask, hist, dtot);
+    else if (hash)
+      k_rs_scatter<true, 4096><<<G, NT, 0, s>>>(raw, out, n, G, shift, nb, pmask, hist, dtot);
+    else if (small)
+      k_rs_scatter<false, 2048><<<G, NT, 0, s>>>(in, out, n, G, shift, nb, 0, hist, dtot);
     else
-      k_rs_scatter<false><<<G, NT, 0, s>>>(in, out, n, G, shift, nb, 0, hist, dtot);
+      k_rs_scatter<false, 4096><<<G, NT, 0, s>>>(in, out, n, G, shift, nb, 0, hist, dtot);
     if (t) t->end(QF_PROF_SORT_SCATTER, s);
     uint64_t *tmp = in;
     in = out;
@@ -435,8 +439,9 @@ hipError_t launch_sort(uint64_t *a, uint64_t *b, uint64_t n, uint32_t bits, uint
 
 hipError_t launch_rle(const uint64_t *sorted, uint64_t n, uint64_t *scratch_start,
                       uint64_t *ufp, uint64_t *ucnt, uint32_t *tile_counts, uint64_t *state,
-                      hipStream_t s, Timer *t) {
-  const uint32_t G = sort_groups(n);
+                      hipStream_t s, const Pipe &pp) {
+  Timer *t = pp.timer;
+  const uint32_t G = sort_groups(n, pp.tune.sort_chunk);
   if (t) t->begin(QF_PROF_REDUCE, s);
   k_rle_count<<<G, NT, 0, s>>>(sorted, n, G, tile_counts);
   k_scan_u32<<<1, 1024, 0, s>>>(tile_counts, G, state + ST_NUNIQ);

@@ -43,6 +43,29 @@ class QFError(RuntimeError):
         self.code = code
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [
+        ("region_log2", ctypes.c_uint32),
+        ("sort_tile", ctypes.c_uint32),
+        ("sort_chunk", ctypes.c_uint32),
+        ("lookup_keys_per_lane", ctypes.c_uint32),
+    ]
+
+
+TUNING_FIELDS = ("region_log2", "sort_tile", "sort_chunk", "lookup_keys_per_lane")
+
+
+def _tuning(d: dict) -> _Tuning:
+    bad = set(d) - set(TUNING_FIELDS)
+    if bad:
+        raise ValueError(f"unknown tuning fields {sorted(bad)}")
+    return _Tuning(*[int(d.get(k, 0)) for k in TUNING_FIELDS])
+
+
+def _tuning_dict(t: _Tuning) -> dict:
+    return {k: int(getattr(t, k)) for k in TUNING_FIELDS}
+
+
 class _Layout(ctypes.Structure):
     _fields_ = [
         ("header", ctypes.c_uint64 * 8),
@@ -115,6 +138,16 @@ def lib() -> ctypes.CDLL:
         "qf_set_errors": (i32, [vp, ctypes.POINTER(ctypes.c_int32), vp]),
         "qf_set_insert_some": (i32, [vp, ctypes.POINTER(ctypes.c_uint32), u32, vp, vp, u64, vp]),
         "qf_set_delete_some": (i32, [vp, ctypes.POINTER(ctypes.c_uint32), u32, vp, vp, u64, vp, vp]),
+        "qf_tune": (i32, [vp, ctypes.POINTER(_Tuning)]),
+        "qf_get_tuning": (i32, [vp, ctypes.POINTER(_Tuning)]),
+        "qf_set_tune": (i32, [vp, ctypes.POINTER(_Tuning)]),
+        "qf_set_get_tuning": (i32, [vp, ctypes.POINTER(_Tuning)]),
+        "qf_autotune_set": (i32, [ctypes.POINTER(ctypes.c_uint32), u32, u32, ctypes.c_double, u64,
+                                  ctypes.POINTER(_Tuning), ctypes.POINTER(ctypes.c_double)]),
+        "qf_graph_begin": (i32, [vp]),
+        "qf_graph_end": (vp, [vp]),
+        "qf_graph_launch": (i32, [vp, vp]),
+        "qf_graph_destroy": (None, [vp]),
         "qfs_create": (vp, [u64, u64]),
         "qfs_destroy": (None, [vp]),
         "qfs_open": (i32, [vp, u32, u32]),
@@ -313,6 +346,16 @@ class CQF:
     def reserve(self, n: int, stream=None):
         _check(lib().qf_reserve(self.h, n, _stream(stream)), "qf_reserve")
 
+    def tune(self, **fields):
+        """Launch parameters (qf_tuning_t fields; omitted ones take their defaults)."""
+        t = _tuning(fields)
+        _check(lib().qf_tune(self.h, ctypes.byref(t)), "qf_tune")
+
+    def tuning(self) -> dict:
+        t = _Tuning()
+        _check(lib().qf_get_tuning(self.h, ctypes.byref(t)), "qf_get_tuning")
+        return _tuning_dict(t)
+
 
 # ---- filter sets ----------------------------------------------------------
 def qf_set_create(filters) -> int:
@@ -445,6 +488,70 @@ class CQFSet:
 
     def reserve(self, n: int, stream=None):
         _check(lib().qf_set_reserve(self.h, n, _stream(stream)), "qf_set_reserve")
+
+    def tune(self, **fields):
+        t = _tuning(fields)
+        _check(lib().qf_set_tune(self.h, ctypes.byref(t)), "qf_set_tune")
+
+    def tuning(self) -> dict:
+        t = _Tuning()
+        _check(lib().qf_set_get_tuning(self.h, ctypes.byref(t)), "qf_set_get_tuning")
+        return _tuning_dict(t)
+
+
+def autotune_set(qs, r: int, load: float, n_query: int) -> tuple[dict, tuple[float, float]]:
+    """qf_autotune_set: the launch parameters the library's autotuner picks for a set of filters with
+    quotient bits `qs`, filled to `load` by one insert batch and queried in batches of n_query keys;
+    also the sample's insert and query milliseconds under them."""
+    arr = (ctypes.c_uint32 * len(qs))(*[int(q) for q in qs])
+    t = _Tuning()
+    ms = (ctypes.c_double * 2)()
+    _check(lib().qf_autotune_set(arr, len(qs), r, float(load), int(n_query), ctypes.byref(t), ms),
+           "qf_autotune_set")
+    return _tuning_dict(t), (ms[0], ms[1])
+
+
+class Graph:
+    """Batch calls captured on a stream (qf_graph_begin / qf_graph_end) and replayed with launch().
+
+        g = Graph(stream)            # starts capturing `stream` (a torch.cuda.Stream)
+        with g: ...batch calls on stream...
+        g.launch()                   # replay on the same stream
+    """
+
+    def __init__(self, stream):
+        self.stream = stream
+        self.h = None
+
+    def __enter__(self):
+        _check(lib().qf_graph_begin(int(self.stream.cuda_stream)), "qf_graph_begin")
+        return self
+
+    def __exit__(self, exc_type, exc, tb):
+        h = lib().qf_graph_end(int(self.stream.cuda_stream))
+        if exc_type is not None:
+            if h:
+                lib().qf_graph_destroy(h)
+            return False
+        if not h:
+            raise QFError(lib().qf_last_error(), "qf_graph_end")
+        self.h = h
+        return False
+
+    def launch(self, stream=None):
+        s = self.stream if stream is None else stream
+        _check(lib().qf_graph_launch(self.h, int(s.cuda_stream)), "qf_graph_launch")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().qf_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---- serving --------------------------------------------------------------

@@ -50,6 +50,21 @@ def test_argument_errors_return_before_the_device():
     assert L.qf_count_batch(None, None, 5, None, None) == qf.QF_ERR_ARG
     assert L.qf_delete_batch(None, None, 5, None, None) == qf.QF_ERR_ARG
     assert L.qf_sync(None, None) == qf.QF_ERR_ARG
+    # tuning, autotuning and capture calls check their arguments first too
+    assert L.qf_tune(None, None) == qf.QF_ERR_ARG
+    assert L.qf_set_tune(None, None) == qf.QF_ERR_ARG
+    assert L.qf_get_tuning(None, None) == qf.QF_ERR_ARG
+    t = qf._Tuning()
+    qs = (ctypes.c_uint32 * 2)(10, 12)
+    assert L.qf_autotune_set(None, 2, 8, 0.85, 1000, ctypes.byref(t), None) == qf.QF_ERR_ARG
+    assert L.qf_autotune_set(qs, 2, 7, 0.85, 1000, ctypes.byref(t), None) == qf.QF_ERR_ARG
+    assert L.qf_autotune_set(qs, 2, 8, 1.5, 1000, ctypes.byref(t), None) == qf.QF_ERR_ARG
+    bad_q = (ctypes.c_uint32 * 1)(40)
+    assert L.qf_autotune_set(bad_q, 1, 8, 0.5, 1000, ctypes.byref(t), None) == qf.QF_ERR_ARG
+    assert L.qf_graph_begin(None) == qf.QF_ERR_ARG
+    assert L.qf_graph_end(None) is None and L.qf_last_error() == qf.QF_ERR_ARG
+    assert L.qf_graph_launch(None, None) == qf.QF_ERR_ARG
+    L.qf_graph_destroy(None)
     L.qf_destroy(None)
 
 
