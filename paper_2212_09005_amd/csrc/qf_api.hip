@@ -55,30 +55,6 @@ uint64_t extra_slots(uint32_t q) {
   return (e + 63) / 64 * 64;
 }
 
-// The slots inside runs, from a table's occupied and run-end words: slot j is
-// in a run iff more runs have started at quotients <= j than have ended
-// before j.  (Each block keeps this map for the merge; export checks it and
-// import builds it.)
-std::vector<uint64_t> used_words(const uint64_t *occ, uint64_t nq, const uint64_t *rend, uint64_t nb) {
-  std::vector<uint64_t> u(nb, 0);
-  uint64_t d = 0;
-  for (uint64_t w = 0; w < nb; ++w) {
-    const uint64_t o = w < nq ? occ[w] : 0, e = rend[w];
-    if (o == 0 && e == 0) {
-      u[w] = d ? ~0ull : 0ull;
-      continue;
-    }
-    uint64_t m = 0;
-    for (int i = 0; i < 64; ++i) {
-      d += (o >> i) & 1ull;
-      if (d) m |= 1ull << i;
-      if ((e >> i) & 1ull) d = d ? d - 1 : 0;
-    }
-    u[w] = m;
-  }
-  return u;
-}
-
 void free_scratch(qf::Pipe &p) {
   (void)hipFree(p.bufA);
   (void)hipFree(p.bufB);
@@ -495,18 +471,14 @@ int qf_export(qf_t *f, qf_layout_t *out, void *stream) {
   uint64_t *d_occ = nullptr, *d_rend = nullptr;
   uint16_t *d_slots = nullptr;
   uint32_t *d_offs = nullptr;
-  uint64_t *d_used = nullptr;
-  std::vector<uint64_t> used(nb);
   int rc = QF_OK;
   if (hipMalloc(&d_occ, nq * 8) != hipSuccess || hipMalloc(&d_rend, nb * 8) != hipSuccess ||
-      hipMalloc(&d_slots, P * 2) != hipSuccess || hipMalloc(&d_offs, nb * 4) != hipSuccess ||
-      hipMalloc(&d_used, nb * 8) != hipSuccess) {
+      hipMalloc(&d_slots, P * 2) != hipSuccess || hipMalloc(&d_offs, nb * 4) != hipSuccess) {
     rc = fail(QF_ERR_OOM);
   }
   uint64_t st[qf::ST_WORDS];
   if (rc == QF_OK) {
-    if (qf::launch_export(f, d_occ, d_rend, d_slots, d_offs, d_used, s) != hipSuccess ||
-        hipMemcpyAsync(used.data(), d_used, nb * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+    if (qf::launch_export(f, d_occ, d_rend, d_slots, d_offs, s) != hipSuccess ||
         hipMemcpyAsync(out->occ_words, d_occ, nq * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipMemcpyAsync(out->runend_words, d_rend, nb * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipMemcpyAsync(out->slots, d_slots, P * 2, hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -520,11 +492,7 @@ int qf_export(qf_t *f, qf_layout_t *out, void *stream) {
   (void)hipFree(d_rend);
   (void)hipFree(d_slots);
   (void)hipFree(d_offs);
-  (void)hipFree(d_used);
   if (rc) return rc;
-  // the blocks' used-slot maps must agree with their runs (an internal
-  // invariant of the library; a mismatch is reported as a device error)
-  if (used_words(out->occ_words, nq, out->runend_words, nb) != used) return fail(QF_ERR_DEVICE);
   out->header[0] = f->q;
   out->header[1] = f->r;
   out->header[2] = f->N;
@@ -547,12 +515,9 @@ int qf_import(qf_t *f, const qf_layout_t *in, void *stream) {
   uint64_t *d_occ = nullptr, *d_rend = nullptr;
   uint16_t *d_slots = nullptr;
   uint32_t *d_offs = nullptr;
-  uint64_t *d_used = nullptr;
-  const std::vector<uint64_t> used = used_words(in->occ_words, nq, in->runend_words, nb);
   int rc = QF_OK;
   if (hipMalloc(&d_occ, nq * 8) != hipSuccess || hipMalloc(&d_rend, nb * 8) != hipSuccess ||
-      hipMalloc(&d_slots, P * 2) != hipSuccess || hipMalloc(&d_offs, nb * 4) != hipSuccess ||
-      hipMalloc(&d_used, nb * 8) != hipSuccess) {
+      hipMalloc(&d_slots, P * 2) != hipSuccess || hipMalloc(&d_offs, nb * 4) != hipSuccess) {
     rc = fail(QF_ERR_OOM);
   }
   uint64_t st[qf::ST_WORDS];
@@ -571,9 +536,8 @@ int qf_import(qf_t *f, const qf_layout_t *in, void *stream) {
         hipMemcpyAsync(d_rend, in->runend_words, nb * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(d_slots, in->slots, P * 2, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(d_offs, in->offsets, nb * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(d_used, used.data(), nb * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(f->state, st, sizeof(st), hipMemcpyHostToDevice, s) != hipSuccess ||
-        qf::launch_import(f, d_occ, d_rend, d_slots, d_offs, d_used, s) != hipSuccess ||
+        qf::launch_import(f, d_occ, d_rend, d_slots, d_offs, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) {
       rc = fail(QF_ERR_DEVICE);
     }
@@ -582,7 +546,6 @@ int qf_import(qf_t *f, const qf_layout_t *in, void *stream) {
   (void)hipFree(d_rend);
   (void)hipFree(d_slots);
   (void)hipFree(d_offs);
-  (void)hipFree(d_used);
   return rc;
 }
 

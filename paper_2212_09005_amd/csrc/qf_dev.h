@@ -2,12 +2,11 @@
 //
 // Physical table (one of the two copies the library alternates between):
 //   blocks[b] : 64 slots = { uint64 occupieds; uint64 runends; uint32 offset;
-//               uint64 used; padding; T slot[64] } (128 B for r = 8: one
-//               128-byte line, so a lookup usually reads one line; 160 B for
-//               r = 16), where the offset is the distance from slot 64b to
-//               the end of the run of the last occupied quotient <= 64b (0 if
-//               that end lies before 64b) and `used` marks the slots inside
-//               runs.
+//               padding; T slot[64] } (128 B for r = 8: one 128-byte line, so
+//               a lookup usually reads one line; 160 B for r = 16), where the
+//               offset is the distance from slot 64b to the end of the run of
+//               the last occupied quotient <= 64b (0 if that end lies before
+//               64b).
 // Quotient x's occupied bit is bit x%64 of blocks[x/64].occupieds, slot j's
 // run-end bit is bit j%64 of blocks[j/64].runends (Sec. 5.1: runs, clusters;
 // the rank/select metadata is this library's reading of the paper's CQF).
@@ -23,11 +22,8 @@ struct Block {
   uint64_t occ;
   uint64_t rend;
   uint32_t off;
-  uint32_t pad0;
-  // slots that belong to a run (kept by every update for the next merge,
-  // which reads a block's empty slots from it; not part of the logical table)
-  uint64_t used;
-  alignas(sizeof(T) == 1 ? 64 : 32) T s[64];
+  uint32_t pad[sizeof(T) == 1 ? 11 : 3];
+  T s[64];
 };
 // r = 8: one 128-byte line per block (metadata and offset in the first 64
 // bytes, slots in the second); r = 16: 32 bytes of metadata + 128 of slots.

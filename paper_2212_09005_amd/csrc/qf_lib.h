@@ -122,9 +122,9 @@ hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
 // copy each filter's deferred error word to err[f] and clear it
 hipError_t launch_take_errors(const Pipe &p, int64_t *err, hipStream_t s);
 hipError_t launch_export(qf_filter *f, uint64_t *occ, uint64_t *rend, uint16_t *slots,
-                         uint32_t *offs, uint64_t *used, hipStream_t s);
+                         uint32_t *offs, hipStream_t s);
 hipError_t launch_import(qf_filter *f, const uint64_t *occ, const uint64_t *rend,
-                         const uint16_t *slots, const uint32_t *offs, const uint64_t *used, hipStream_t s);
+                         const uint16_t *slots, const uint32_t *offs, hipStream_t s);
 
 // sort tiling: G work-groups each own a contiguous chunk of at least
 // `chunk` keys (at most SORT_MAX_GROUPS groups)

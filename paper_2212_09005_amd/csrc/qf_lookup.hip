@@ -143,7 +143,7 @@ template <typename T>
 __global__ __launch_bounds__(NT) void k_export(const Block<T> *b0, const Block<T> *b1,
                                                const uint64_t *state, int64_t nblocks,
                                                int64_t nqblocks, uint64_t *occ, uint64_t *rend,
-                                               uint16_t *slots, uint32_t *offs, uint64_t *used) {
+                                               uint16_t *slots, uint32_t *offs) {
   const int cur = static_cast<int>(state[ST_CUR] & 1ull);
   const Block<T> *b = cur ? b1 : b0;
   const uint64_t total = static_cast<uint64_t>(nblocks) * 64;
@@ -154,7 +154,6 @@ __global__ __launch_bounds__(NT) void k_export(const Block<T> *b0, const Block<T
     if ((j & 63) == 0) {
       rend[bi] = b[bi].rend;
       offs[bi] = b[bi].off;
-      used[bi] = b[bi].used;
       if (bi < nqblocks) occ[bi] = b[bi].occ;
     }
   }
@@ -164,7 +163,7 @@ template <typename T>
 __global__ __launch_bounds__(NT) void k_import(Block<T> *b, int64_t nblocks,
                                                int64_t nqblocks, const uint64_t *occ,
                                                const uint64_t *rend, const uint16_t *slots,
-                                               const uint32_t *offs, const uint64_t *used) {
+                                               const uint32_t *offs) {
   const uint64_t total = static_cast<uint64_t>(nblocks) * 64;
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * NT;
   for (uint64_t j = static_cast<uint64_t>(blockIdx.x) * NT + threadIdx.x; j < total; j += stride) {
@@ -173,7 +172,6 @@ __global__ __launch_bounds__(NT) void k_import(Block<T> *b, int64_t nblocks,
     if ((j & 63) == 0) {
       b[bi].rend = rend[bi];
       b[bi].off = offs[bi];
-      b[bi].used = used[bi];
       b[bi].occ = bi < nqblocks ? occ[bi] : 0ull;
     }
   }
@@ -260,30 +258,30 @@ hipError_t launch_lookup(qf_filter *f, const uint64_t *keys, uint64_t n, uint8_t
 }
 
 hipError_t launch_export(qf_filter *f, uint64_t *occ, uint64_t *rend, uint16_t *slots,
-                         uint32_t *offs, uint64_t *used, hipStream_t s) {
+                         uint32_t *offs, hipStream_t s) {
   const uint64_t total = f->nblocks * 64;
   const int64_t nb = static_cast<int64_t>(f->nblocks), nq = static_cast<int64_t>(f->N / 64);
   if (f->r == 8)
     k_export<uint8_t><<<grid_for(total), NT, 0, s>>>(
         static_cast<const Block<uint8_t> *>(f->blk[0]), static_cast<const Block<uint8_t> *>(f->blk[1]),
-        f->state, nb, nq, occ, rend, slots, offs, used);
+        f->state, nb, nq, occ, rend, slots, offs);
   else
     k_export<uint16_t><<<grid_for(total), NT, 0, s>>>(
         static_cast<const Block<uint16_t> *>(f->blk[0]), static_cast<const Block<uint16_t> *>(f->blk[1]),
-        f->state, nb, nq, occ, rend, slots, offs, used);
+        f->state, nb, nq, occ, rend, slots, offs);
   return hipGetLastError();
 }
 
 hipError_t launch_import(qf_filter *f, const uint64_t *occ, const uint64_t *rend,
-                         const uint16_t *slots, const uint32_t *offs, const uint64_t *used, hipStream_t s) {
+                         const uint16_t *slots, const uint32_t *offs, hipStream_t s) {
   const uint64_t total = f->nblocks * 64;
   const int64_t nb = static_cast<int64_t>(f->nblocks), nq = static_cast<int64_t>(f->N / 64);
   if (f->r == 8)
     k_import<uint8_t><<<grid_for(total), NT, 0, s>>>(static_cast<Block<uint8_t> *>(f->blk[0]),
-                                                     nb, nq, occ, rend, slots, offs, used);
+                                                     nb, nq, occ, rend, slots, offs);
   else
     k_import<uint16_t><<<grid_for(total), NT, 0, s>>>(static_cast<Block<uint16_t> *>(f->blk[0]),
-                                                      nb, nq, occ, rend, slots, offs, used);
+                                                      nb, nq, occ, rend, slots, offs);
   return hipGetLastError();
 }
 

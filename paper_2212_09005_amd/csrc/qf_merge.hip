@@ -133,33 +133,29 @@ struct NewGlb {
 };
 
 // ---- writers of the new table -------------------------------------------
-// emit(j, v) writes slot j of a run, gap(j) an empty slot (positions strictly
-// increasing per lane), set_end() marks the last written slot as a run end,
-// flush() ends the lane's output.  Run-end and used bits are gathered per
-// 64-bit word; words shared with a neighbour's extent are merged with and/or
-// under the lane's mask.
+// emit(j, v) writes slot j (positions strictly increasing per lane), set_end()
+// marks the last written slot as a run end, flush() ends the lane's output.
+// Run-end bits are gathered per 64-bit word; words shared with a neighbour's
+// extent are merged with and/or under the lane's mask.
 template <typename T>
 struct OutGlb {
   Block<T> *blk;
   int64_t hi;
   int64_t cw;
-  uint64_t acc, accu, accm;
+  uint64_t acc, accm;
   __device__ void init(Block<T> *blk_, int64_t hi_) {
-    blk = blk_; hi = hi_; cw = -1; acc = 0; accu = 0; accm = 0;
+    blk = blk_; hi = hi_; cw = -1; acc = 0; accm = 0;
   }
   __device__ void flush() {
     if (accm == ~0ull) {
       blk[cw].rend = acc;
-      blk[cw].used = accu;
     } else if (accm) {
       atomic_and_u64(&blk[cw].rend, ~accm);
       atomic_or_u64(&blk[cw].rend, acc);
-      atomic_and_u64(&blk[cw].used, ~accm);
-      atomic_or_u64(&blk[cw].used, accu);
     }
-    acc = accu = accm = 0;
+    acc = accm = 0;
   }
-  __device__ void put(int64_t j, uint64_t v, bool in_run) {
+  __device__ void emit(int64_t j, uint64_t v) {
     if (j > hi) return;
     blk[j >> 6].s[j & 63] = static_cast<T>(v);
     const int64_t w = j >> 6;
@@ -168,10 +164,7 @@ struct OutGlb {
       cw = w;
     }
     accm |= 1ull << (j & 63);
-    accu |= in_run ? 1ull << (j & 63) : 0ull;
   }
-  __device__ void emit(int64_t j, uint64_t v) { put(j, v, true); }
-  __device__ void gap(int64_t j) { put(j, 0, false); }
   __device__ void set_end(int64_t j) {
     if (j > hi) return;
     acc |= 1ull << (j & 63);
@@ -181,7 +174,6 @@ struct OutGlb {
 struct NoOut {
   __device__ void flush() {}
   __device__ void emit(int64_t, uint64_t) {}
-  __device__ void gap(int64_t) {}
   __device__ void set_end(int64_t) {}
 };
 
@@ -365,7 +357,7 @@ __device__ __forceinline__ void walk(uint32_t r, int del, int64_t RS, const uint
     }
     if (EMIT) {
       const int64_t start = max(x, carry + 1);
-      for (; wpos < start; ++wpos) out.gap(wpos);
+      for (; wpos < start; ++wpos) out.emit(wpos, 0);
       int64_t pos = start;
       if (ni == nj) {
         for (int64_t j = op; j <= oe; ++j) out.emit(pos++, old.slot(j));
@@ -397,7 +389,7 @@ __device__ __forceinline__ void walk(uint32_t r, int del, int64_t RS, const uint
     for (; next_bs < s1; next_bs += 64)
       noff[next_bs >> 6] = static_cast<uint32_t>(max(carry - next_bs, static_cast<int64_t>(0)));
     const int64_t ext_end = max(carry, s1 - 1);
-    for (; wpos <= ext_end; ++wpos) out.gap(wpos);
+    for (; wpos <= ext_end; ++wpos) out.emit(wpos, 0);
     out.flush();
   }
 }
@@ -481,19 +473,6 @@ struct CurEnds {
   __device__ int32_t pop(int32_t o) { return ec.next(o); }
 };
 
-// set bits [p, pe] of the LDS bit words u (p <= pe)
-__device__ __forceinline__ void set_range(uint64_t *u, int32_t p, int32_t pe) {
-  int32_t w = p >> 6;
-  const int32_t we = pe >> 6;
-  uint64_t m = ~0ull << (p & 63);
-  for (; w < we; ++w) {
-    atomicOr(reinterpret_cast<ull *>(&u[w]), static_cast<ull>(m));
-    m = ~0ull;
-  }
-  m &= ~0ull >> (63 - (pe & 63));
-  atomicOr(reinterpret_cast<ull *>(&u[we]), static_cast<ull>(m));
-}
-
 // One walk over the lane's quotients [t0, t0 + QT); occ / chg are the chunk's
 // old-occupied bits and its bits of quotients that receive new entries.
 // Pass 1 (EMIT = false): unchanged runs keep their length and are composed
@@ -509,8 +488,8 @@ template <bool EMIT, typename T, class Ends>
 __device__ __forceinline__ int32_t lane_walk(int32_t t0, uint32_t occ, uint32_t chg, int32_t ob, int32_t ope,
                                              Ends ends, uint32_t c, uint16_t *cop, uint16_t *coe, Fn32 *gaf,
                                              Fn32 &first, uint32_t &used, const uint32_t *cL, uint16_t *cst,
-                                             const T *old_s, T *new_s, uint64_t *new_b, uint64_t *new_u,
-                                             int32_t xb, int32_t carry, uint32_t &nocc) {
+                                             const T *old_s, T *new_s, uint64_t *new_b, int32_t xb,
+                                             int32_t carry, uint32_t &nocc) {
   uint32_t u = occ | chg;
   Fn32 G = f32_id();
   bool seen = false;
@@ -556,7 +535,6 @@ __device__ __forceinline__ int32_t lane_walk(int32_t t0, uint32_t occ, uint32_t 
           for (int32_t k = 1; k < L; ++k) new_s[p + k] = old_s[o + k];
         }
         const int32_t pe = p + L - 1;
-        set_range(new_u, p, pe);
         carry = pe + xb;
         if ((pe >> 6) != cw) {
           if (bits) atomicOr(reinterpret_cast<ull *>(&new_b[cw]), static_cast<ull>(bits));
@@ -806,7 +784,6 @@ struct Smem {
   T *new_s;
   uint64_t *old_b;
   uint64_t *new_b;
-  uint64_t *new_u;
   uint32_t *old_wp;
   uint64_t *occ_l;
   uint64_t *chg_l;
@@ -833,7 +810,6 @@ __device__ __forceinline__ void merge_body(const MergeArgs &a, const Smem<T> &m)
   T *const new_s = m.new_s;
   uint64_t *const old_b = m.old_b;
   uint64_t *const new_b = m.new_b;
-  uint64_t *const new_u = m.new_u;
   uint32_t *const old_wp = m.old_wp;
   uint64_t *const occ_l = m.occ_l;
   uint64_t *const chg_l = m.chg_l;
@@ -889,10 +865,7 @@ __device__ __forceinline__ void merge_body(const MergeArgs &a, const Smem<T> &m)
     occ_l[w] = qreg ? gob[(RS >> 6) + w].occ : 0ull;
     chg_l[w] = 0ull;
   }
-  for (int w = tid; w < C::CAPW; w += NT) {
-    new_b[w] = 0ull;
-    new_u[w] = 0ull;
-  }
+  for (int w = tid; w < C::CAPW; w += NT) new_b[w] = 0ull;
   for (int i = tid; i < C::CAP * static_cast<int>(sizeof(T)) / 16; i += NT)
     reinterpret_cast<uint4 *>(new_s)[i] = make_uint4(0u, 0u, 0u, 0u);
   // (SMALL is a template argument, so the LDS case compiles to LDS
@@ -1011,12 +984,12 @@ __device__ __forceinline__ void merge_body(const MergeArgs &a, const Smem<T> &m)
       we.init(old_b, nblk, ope0 + 1);
       if (we.count() >= __popc(occ_c)) {
         lane_walk<false, T>(t0, occ_c, chg_c, obr, ope0, we, c0, cop, coe, gaf, first, used, cL, cst, old_s,
-                            dt, new_b, nullptr, 0, 0, dn);
+                            dt, new_b, 0, 0, dn);
       } else {
         CurEnds ce;
         ce.ec.init(old_b, nblk);
         lane_walk<false, T>(t0, occ_c, chg_c, obr, ope0, ce, c0, cop, coe, gaf, first, used, cL, cst, old_s,
-                            dt, new_b, nullptr, 0, 0, dn);
+                            dt, new_b, 0, 0, dn);
       }
     }
     __syncthreads();
@@ -1109,12 +1082,12 @@ __device__ __forceinline__ void merge_body(const MergeArgs &a, const Smem<T> &m)
       we.init(old_b, nblk, ope0 + 1);
       if (we.count() >= __popc(occ_c)) {
         ct0 = lane_walk<true, T>(t0, occ_c, chg_c, obr, ope0, we, c0, cop, coe, gaf, df, du, cL, cst, old_s,
-                                 new_s, new_b, new_u, xb, carry, nocc);
+                                 new_s, new_b, xb, carry, nocc);
       } else {
         CurEnds ce;
         ce.ec.init(old_b, nblk);
         ct0 = lane_walk<true, T>(t0, occ_c, chg_c, obr, ope0, ce, c0, cop, coe, gaf, df, du, cL, cst, old_s,
-                                 new_s, new_b, new_u, xb, carry, nocc);
+                                 new_s, new_b, xb, carry, nocc);
       }
       if ((t0 & 63) == 0) gnbk[(RS + t0) >> 6].off = static_cast<uint32_t>(max(ct0 - t0, 0));
     }
@@ -1162,15 +1135,12 @@ __device__ __forceinline__ void merge_body(const MergeArgs &a, const Smem<T> &m)
       const int64_t w = (xbase >> 6) + b;
       const int64_t plo = max(w << 6, ext_lo), phi = min((w << 6) + 63, ext_hi);
       const uint64_t mask = (~0ull >> (63 - (phi & 63))) & (~0ull << (plo & 63));
-      const uint64_t v = new_b[b] & mask, u = new_u[b] & mask;
+      const uint64_t v = new_b[b] & mask;
       if (mask == ~0ull) {
         gnbk[w].rend = v;
-        gnbk[w].used = u;
       } else {
         atomic_and_u64(&nbk[w].rend, ~mask);
         atomic_or_u64(&nbk[w].rend, v);
-        atomic_and_u64(&nbk[w].used, ~mask);
-        atomic_or_u64(&nbk[w].used, u);
       }
     }
   } else if (emit) {
@@ -1195,7 +1165,6 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs a) {
   __shared__ __align__(16) T new_s[C::CAP];
   __shared__ uint64_t old_b[C::CAPW];
   __shared__ uint64_t new_b[C::CAPW];
-  __shared__ uint64_t new_u[C::CAPW];
   __shared__ uint32_t old_wp[C::CAPW + 1];
   __shared__ uint64_t occ_l[C::OW];
   // quotients that receive new entries; reused for the new occupied bits of
@@ -1218,7 +1187,7 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs a) {
   __shared__ uint32_t sh_u[2 * NT / 64];
   __shared__ uint64_t sh_r[NT / 64];
 
-  const Smem<T> m{old_s, new_s, old_b, new_b, new_u, old_wp, occ_l, chg_l, nfp_l, ncnt_l, cxr_l, chead_l, cop_l, coe_l, cL_l, cst_l, gaf_l, sh_i, sh_fn, sh_u, sh_r};
+  const Smem<T> m{old_s, new_s, old_b, new_b, old_wp, occ_l, chg_l, nfp_l, ncnt_l, cxr_l, chead_l, cop_l, coe_l, cL_l, cst_l, gaf_l, sh_i, sh_fn, sh_u, sh_r};
   const uint32_t g = a.areg ? a.areg[blockIdx.x] : blockIdx.x;
   if (a.rb[g + 1] - a.rb[g] <= static_cast<uint64_t>(C::NCAP))
     merge_body<T, SINGLE, true>(a, m);
