@@ -182,8 +182,8 @@ int pipe_init(qf::Pipe &p, qf_filter *const *fs, uint32_t nf, const qf::Tune &tn
     return fail(QF_ERR_OOM);
   }
   p.one = desc[0];
-  p.rstat = p.tags + 3ull * G;
-  p.cb = reinterpret_cast<int64_t *>(p.tags + 7ull * G);
+  p.rstat = p.tags + ((3ull * G + 1) & ~1ull);  // 16-byte aligned (read as 16-byte vectors)
+  p.cb = reinterpret_cast<int64_t *>(p.tags + 7ull * G + 2);
   p.device_bytes = nf * sizeof(qf::FDesc) + G * 4 + (G + 1) * 8 + tag_words * 8 + qf::ST_WORDS * 8 +
                    p.hist_words * 4;
   return QF_OK;

@@ -679,15 +679,21 @@ __device__ __forceinline__ uint2 block_exscan2_u32(uint2 v, uint32_t *sh, uint2 
   return make_uint2(wpre.x + inc.x - v.x, wpre.y + inc.y - v.y);
 }
 
-__device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t *sh) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+// four sums at once (one set of barriers); sh holds 4 * NT / 64 words
+__device__ __forceinline__ void block_sum4_u64(uint64_t v[4], uint64_t *sh) {
+  for (int k = 0; k < 4; ++k) {
+    for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o);
+    if ((threadIdx.x & 63) == 0) sh[4 * (threadIdx.x >> 6) + k] = v[k];
+  }
   __syncthreads();
-  uint64_t t = 0;
-  for (int w = 0; w < NT / 64; ++w) t += sh[w];
+  for (int k = 0; k < 4; ++k) {
+    uint64_t t = 0;
+    for (int w = 0; w < NT / 64; ++w) t += sh[4 * w + k];
+    v[k] = t;
+  }
   __syncthreads();
-  return t;
 }
+
 
 // Carry-in of region R (called by the 64 lanes of one wave) of a filter whose
 // first region is R0: lane l looks at regions hi - LBK l - k, k < LBK; the
@@ -1026,11 +1032,10 @@ __device__ __forceinline__ void merge_body(const MergeArgs &a, const Smem<T> &m)
   }
   Fn Ftot;
   const Fn Fex = block_exscan_fn(Flane, sh_fn, &Ftot);
-  const uint64_t used = block_sum_u64(acc.used, sh_r);
-  const uint64_t dent = block_sum_u64(acc.dent, sh_r);
-  const uint64_t dtot = block_sum_u64(acc.dtot, sh_r);
-  const uint64_t shortfall = block_sum_u64(acc.shortfall, sh_r);
-  const uint64_t ovf = block_sum_u64(acc.ovf, sh_r);
+  uint64_t sums[4] = {acc.used, acc.dent, acc.dtot, acc.shortfall};
+  block_sum4_u64(sums, sh_r);
+  const uint64_t used = sums[0], dent = sums[1], dtot = sums[2], shortfall = sums[3];
+  const bool ovf = __syncthreads_or(acc.ovf != 0) != 0;
 
   if (tid == 0) {
     tag_store(&a.tags[gR], epoch, Ftot.A);
@@ -1185,7 +1190,7 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs a) {
   __shared__ int64_t sh_i[8];
   __shared__ Fn sh_fn[NT / 64];
   __shared__ uint32_t sh_u[2 * NT / 64];
-  __shared__ uint64_t sh_r[NT / 64];
+  __shared__ uint64_t sh_r[4 * NT / 64];
 
   const Smem<T> m{old_s, new_s, old_b, new_b, old_wp, occ_l, chg_l, nfp_l, ncnt_l, cxr_l, chead_l, cop_l, coe_l, cL_l, cst_l, gaf_l, sh_i, sh_fn, sh_u, sh_r};
   const uint32_t g = a.areg ? a.areg[blockIdx.x] : blockIdx.x;
@@ -1206,8 +1211,16 @@ __global__ __launch_bounds__(1024) void k_finish(const FDesc *__restrict__ desc,
   const uint32_t f = afil ? afil[blockIdx.x] : blockIdx.x;
   const FDesc &d = desc[f];
   uint64_t v[4] = {0, 0, 0, 0};
-  for (uint32_t R = threadIdx.x; R < d.nregions; R += 1024)
-    for (int k = 0; k < 4; ++k) v[k] += rstat[4ull * (d.rbase + R) + k];
+  // (16-byte loads, several regions in flight per lane)
+  const u32x4 *rs4 = reinterpret_cast<const u32x4 *>(rstat + 4ull * d.rbase);
+#pragma unroll 8
+  for (uint32_t R = threadIdx.x; R < d.nregions; R += 1024) {
+    const u32x4 a = rs4[2ull * R], b = rs4[2ull * R + 1];
+    v[0] += (static_cast<uint64_t>(a[1]) << 32) | a[0];
+    v[1] += (static_cast<uint64_t>(a[3]) << 32) | a[2];
+    v[2] += (static_cast<uint64_t>(b[1]) << 32) | b[0];
+    v[3] += (static_cast<uint64_t>(b[3]) << 32) | b[2];
+  }
   for (int k = 0; k < 4; ++k) {
     for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o);
     if ((threadIdx.x & 63) == 0) sh[k][threadIdx.x >> 6] = v[k];
