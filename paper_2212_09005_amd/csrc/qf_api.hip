@@ -162,7 +162,7 @@ int pipe_init(qf::Pipe &p, qf_filter *const *fs, uint32_t nf, const qf::Tune &tn
     p.h_rbase[i] = desc[i].rbase;
     for (uint32_t k = 0; k < desc[i].nregions; ++k) rmap[desc[i].rbase + k] = i;
   }
-  p.hist_words = 256ull * 1024ull + 256ull * 8;  // histograms + per-pass digit totals
+  p.hist_words = 256ull * 1024ull + 256ull;  // radix histograms (256 digits x 1024 groups) + digit totals
   const uint64_t tag_words = 8ull * G + 8;        // 3 G tags, 4 G statistics, G carries
   bool ok = hipMalloc(reinterpret_cast<void **>(&p.d_desc), nf * sizeof(qf::FDesc)) == hipSuccess &&
             hipMalloc(reinterpret_cast<void **>(&p.d_rmap), G * sizeof(uint32_t)) == hipSuccess &&

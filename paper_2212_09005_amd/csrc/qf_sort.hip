@@ -17,6 +17,8 @@ namespace {
 constexpr int NT = 256;
 constexpr int NWAVE = NT / 64;
 constexpr uint32_t SORT_MAX_GROUPS = 1024;
+constexpr uint32_t RADIX_BITS = 8;                 // widest digit
+constexpr int RADIX_MAX = 1 << RADIX_BITS;        // digits per pass, at most
 
 __device__ __forceinline__ uint64_t chunk_lo(uint64_t n, uint32_t G, uint32_t g) {
   return (n * g) / G;
@@ -74,26 +76,28 @@ __global__ __launch_bounds__(NT) void k_fill(uint64_t *p, uint64_t n, uint64_t v
     p[i] = v;
 }
 
-// per-group digit histogram, stored digit-major: hist[d * G + g].  With HASH
-// the input is the raw keys and the sorted value is mix64(key) & pmask (the
-// hash is fused into the first pass).
-template <bool HASH>
+// per-group digit histogram, stored digit-major: hist[d * G + g], for digits
+// of nbits <= log2(ND) bits at `shift`.  With HASH the input is the raw keys
+// and the sorted value is mix64(key) & pmask (the hash is fused into the
+// first pass).
+template <bool HASH, int ND>
 __global__ __launch_bounds__(NT) void k_rs_hist(const uint64_t *__restrict__ in, uint64_t n,
-                                                uint32_t G, uint32_t shift, uint64_t pmask,
+                                                uint32_t G, uint32_t shift, uint32_t nbits, uint64_t pmask,
                                                 uint32_t *__restrict__ hist) {
-  __shared__ uint32_t h[NWAVE][256];
+  __shared__ uint32_t h[NWAVE][ND];
   const int tid = threadIdx.x, wv = tid >> 6;
-  for (int d = tid; d < 256; d += NT)
+  for (int d = tid; d < ND; d += NT)
     for (int w = 0; w < NWAVE; ++w) h[w][d] = 0;
   __syncthreads();
   const uint32_t g = blockIdx.x;
+  const uint32_t dmask = (1u << nbits) - 1u;
   const uint64_t lo = chunk_lo(n, G, g), hi = chunk_lo(n, G, g + 1);
   for (uint64_t i = lo + tid; i < hi; i += NT) {
     const uint64_t v = HASH ? (mix64(in[i]) & pmask) : in[i];
-    atomicAdd(&h[wv][(v >> shift) & 255u], 1u);
+    atomicAdd(&h[wv][static_cast<uint32_t>(v >> shift) & dmask], 1u);
   }
   __syncthreads();
-  for (int d = tid; d < 256; d += NT) {
+  for (int d = tid; d < ND; d += NT) {
     uint32_t t = 0;
     for (int w = 0; w < NWAVE; ++w) t += h[w][d];
     hist[static_cast<uint64_t>(d) * G + g] = t;
@@ -160,13 +164,38 @@ __global__ __launch_bounds__(1024) void k_scan_u32(uint32_t *a, uint32_t n, uint
   if (tid == 1023 && total) *total = part[1023];
 }
 
+// Exclusive scan over the ND digits of a work-group, DPT = ND / NT digits per
+// lane (lane t holds digits t DPT .. t DPT + DPT - 1, in order).
+template <int DPT>
+__device__ __forceinline__ void digits_exscan(const uint32_t (&v)[DPT], uint32_t (&ex)[DPT], uint32_t *sh) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  uint32_t sum = 0;
+#pragma unroll
+  for (int j = 0; j < DPT; ++j) sum += v[j];
+  uint32_t inc = sum;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(inc, o);
+    if (lane >= o) inc += t;
+  }
+  if (lane == 63) sh[wv] = inc;
+  __syncthreads();
+  uint32_t run = inc - sum;
+  for (int w = 0; w < wv; ++w) run += sh[w];
+#pragma unroll
+  for (int j = 0; j < DPT; ++j) {
+    ex[j] = run;
+    run += v[j];
+  }
+  __syncthreads();
+}
+
 // Stable scatter of one digit.  Each group takes its chunk in tiles of TILE
 // keys (KPL = TILE / NT per lane): the tile is ordered by digit in LDS (ranks
 // from wave ballots, rounds of 256 keys in index order, so the order is
 // stable), then written out so that each digit's keys of the tile land as
 // one contiguous run -- coalesced stores instead of one 8-byte store per key
-// to a different line.
-template <bool HASH, int TILE>
+// to a different line.  ND digits (256 or 512), DPT per lane.
+template <bool HASH, int TILE, int ND>
 __global__ __launch_bounds__(NT) void k_rs_scatter(const uint64_t *__restrict__ in,
                                                    uint64_t *__restrict__ out, uint64_t n,
                                                    uint32_t G, uint32_t shift, uint32_t nbits,
@@ -174,60 +203,57 @@ __global__ __launch_bounds__(NT) void k_rs_scatter(const uint64_t *__restrict__ 
                                                    const uint32_t *__restrict__ hist,
                                                    const uint32_t *__restrict__ dtot) {
   constexpr int KPL = TILE / NT;
+  constexpr int DPT = ND / NT;
   __shared__ uint64_t tile[TILE];
-  __shared__ uint32_t gpos[256];  // global position of the group's next key of digit d
-  __shared__ uint32_t loff[256];  // start of digit d in the tile
-  __shared__ uint32_t placed[256];
-  __shared__ uint32_t wc[NWAVE][256];
+  __shared__ uint32_t gpos[ND];  // global position of the group's next key of digit d
+  __shared__ uint32_t loff[ND];  // start of digit d in the tile
+  __shared__ uint32_t placed[ND];
+  __shared__ uint32_t wc[NWAVE][ND];
   __shared__ uint32_t sh[NWAVE];
-  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, wv = tid >> 6;
   const uint32_t g = blockIdx.x;
   {
-    // keys with a smaller digit: exclusive scan of the 256 digit totals
-    const uint32_t v = dtot[tid];
-    uint32_t inc = v;
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t t = __shfl_up(inc, o);
-      if (lane >= o) inc += t;
+    // keys with a smaller digit: exclusive scan of the digit totals
+    uint32_t v[DPT], ex[DPT];
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) v[j] = dtot[tid * DPT + j];
+    digits_exscan<DPT>(v, ex, sh);
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+      const int d = tid * DPT + j;
+      gpos[d] = ex[j] + hist[static_cast<uint64_t>(d) * G + g];
+      for (int w = 0; w < NWAVE; ++w) wc[w][d] = 0;
     }
-    if (lane == 63) sh[wv] = inc;
-    __syncthreads();
-    uint32_t ex = inc - v;
-    for (int w = 0; w < wv; ++w) ex += sh[w];
-    gpos[tid] = ex + hist[static_cast<uint64_t>(tid) * G + g];
-    for (int w = 0; w < NWAVE; ++w) wc[w][tid] = 0;
   }
   const uint64_t lo = chunk_lo(n, G, g), hi = chunk_lo(n, G, g + 1);
   const uint32_t dmask = (1u << nbits) - 1u;
   for (uint64_t t0 = lo; t0 < hi; t0 += TILE) {
     const uint32_t cnt = static_cast<uint32_t>(min(static_cast<uint64_t>(TILE), hi - t0));
-    placed[tid] = 0;
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) placed[tid * DPT + j] = 0;
     __syncthreads();
     uint64_t key[KPL];
 #pragma unroll
     for (int k = 0; k < KPL; ++k) {
-      const uint32_t j = k * NT + tid;
+      const uint32_t jj = k * NT + tid;
       key[k] = 0;
-      if (j < cnt) {
-        key[k] = HASH ? (mix64(in[t0 + j]) & pmask) : in[t0 + j];
+      if (jj < cnt) {
+        key[k] = HASH ? (mix64(in[t0 + jj]) & pmask) : in[t0 + jj];
         atomicAdd(&placed[static_cast<uint32_t>(key[k] >> shift) & dmask], 1u);
       }
     }
     __syncthreads();
     {
       // tile-local digit starts: exclusive scan of the tile's digit counts
-      const uint32_t v = placed[tid];
-      uint32_t inc = v;
-      for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t t = __shfl_up(inc, o);
-        if (lane >= o) inc += t;
+      uint32_t v[DPT], ex[DPT];
+#pragma unroll
+      for (int j = 0; j < DPT; ++j) v[j] = placed[tid * DPT + j];
+      digits_exscan<DPT>(v, ex, sh);
+#pragma unroll
+      for (int j = 0; j < DPT; ++j) {
+        loff[tid * DPT + j] = ex[j];
+        placed[tid * DPT + j] = 0;
       }
-      if (lane == 63) sh[wv] = inc;
-      __syncthreads();
-      uint32_t ex = inc - v;
-      for (int w = 0; w < wv; ++w) ex += sh[w];
-      loff[tid] = ex;
-      placed[tid] = 0;
     }
     __syncthreads();
 #pragma unroll
@@ -249,24 +275,27 @@ __global__ __launch_bounds__(NT) void k_rs_scatter(const uint64_t *__restrict__ 
         tile[pos] = key[k];
       }
       __syncthreads();
-      {
+#pragma unroll
+      for (int j = 0; j < DPT; ++j) {
+        const int dd = tid * DPT + j;
         uint32_t t = 0;
         for (int w = 0; w < NWAVE; ++w) {
-          t += wc[w][tid];
-          wc[w][tid] = 0;
+          t += wc[w][dd];
+          wc[w][dd] = 0;
         }
-        placed[tid] += t;
+        placed[dd] += t;
       }
       __syncthreads();
     }
     // the tile in digit order -> each digit's run to its global place
-    for (uint32_t j = tid; j < cnt; j += NT) {
-      const uint64_t v = tile[j];
+    for (uint32_t jj = tid; jj < cnt; jj += NT) {
+      const uint64_t v = tile[jj];
       const uint32_t d = static_cast<uint32_t>(v >> shift) & dmask;
-      out[gpos[d] + (j - loff[d])] = v;
+      out[gpos[d] + (jj - loff[d])] = v;
     }
     __syncthreads();
-    gpos[tid] += placed[tid];
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) gpos[tid * DPT + j] += placed[tid * DPT + j];
   }
 }
 
@@ -396,39 +425,51 @@ hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
+// One LSD pass: histogram, digit offsets, scatter, with ND-digit kernels.
+template <int ND>
+void sort_pass(const uint64_t *in, uint64_t *out, const uint64_t *raw, bool hash, uint64_t n, uint32_t G,
+               uint32_t shift, uint32_t nb, uint64_t pmask, uint32_t *hist, uint32_t *dtot, bool small,
+               hipStream_t s, Timer *t) {
+  if (t) t->begin(QF_PROF_SORT_HIST, s);
+  if (hash)
+    k_rs_hist<true, ND><<<G, NT, 0, s>>>(raw, n, G, shift, nb, pmask, hist);
+  else
+    k_rs_hist<false, ND><<<G, NT, 0, s>>>(in, n, G, shift, nb, 0, hist);
+  if (t) t->end(QF_PROF_SORT_HIST, s);
+  if (t) t->begin(QF_PROF_SORT_SCAN, s);
+  k_rs_offsets<<<ND, NT, 0, s>>>(hist, G, dtot);
+  if (t) t->end(QF_PROF_SORT_SCAN, s);
+  if (t) t->begin(QF_PROF_SORT_SCATTER, s);
+  if (hash && small)
+    k_rs_scatter<true, 2048, ND><<<G, NT, 0, s>>>(raw, out, n, G, shift, nb, pmask, hist, dtot);
+  else if (hash)
+    k_rs_scatter<true, 4096, ND><<<G, NT, 0, s>>>(raw, out, n, G, shift, nb, pmask, hist, dtot);
+  else if (small)
+    k_rs_scatter<false, 2048, ND><<<G, NT, 0, s>>>(in, out, n, G, shift, nb, 0, hist, dtot);
+  else
+    k_rs_scatter<false, 4096, ND><<<G, NT, 0, s>>>(in, out, n, G, shift, nb, 0, hist, dtot);
+  if (t) t->end(QF_PROF_SORT_SCATTER, s);
+}
+
 hipError_t launch_sort(uint64_t *a, uint64_t *b, uint64_t n, uint32_t bits, uint32_t *hist,
                        uint64_t **result, hipStream_t s, const Pipe &pp, const uint64_t *raw, uint64_t pmask) {
   Timer *t = pp.timer;
   const uint32_t G = sort_groups(n, pp.tune.sort_chunk);
   const bool small = pp.tune.sort_tile == 2048;
-  const uint32_t npass = (bits + 7) / 8;
-  // digit totals live after the G * 256 histogram words
-  uint32_t *dtot = hist + 256ull * SORT_MAX_GROUPS;
+  // as few passes as digits of up to RADIX_BITS bits allow, the bits spread
+  // evenly over them (36 bits: one 8-bit and four 7-bit passes; each bit of
+  // a digit costs a wave ballot per key round of the scatter)
+  const uint32_t npass = bits == 0 ? 0 : (bits + RADIX_BITS - 1) / RADIX_BITS;
+  const uint32_t db = npass ? (bits + npass - 1) / npass : 0;
+  // digit totals live after the RADIX_MAX x SORT_MAX_GROUPS histogram words
+  uint32_t *dtot = hist + static_cast<uint64_t>(RADIX_MAX) * SORT_MAX_GROUPS;
   uint64_t *in = a, *out = b;
   for (uint32_t p = 0; p < npass; ++p) {
-    const uint32_t shift = 8 * p;
-    const uint32_t nb = bits - shift < 8 ? bits - shift : 8;
+    const uint32_t shift = db * p;
+    const uint32_t nb = bits - shift < db ? bits - shift : db;
     // with raw keys the first pass hashes them itself (its output goes to b)
     const bool hash = raw && p == 0;
-    if (t) t->begin(QF_PROF_SORT_HIST, s);
-    if (hash)
-      k_rs_hist<true><<<G, NT, 0, s>>>(raw, n, G, shift, pmask, hist);
-    else
-      k_rs_hist<false><<<G, NT, 0, s>>>(in, n, G, shift, 0, hist);
-    if (t) t->end(QF_PROF_SORT_HIST, s);
-    if (t) t->begin(QF_PROF_SORT_SCAN, s);
-    k_rs_offsets<<<256, NT, 0, s>>>(hist, G, dtot);
-    if (t) t->end(QF_PROF_SORT_SCAN, s);
-    if (t) t->begin(QF_PROF_SORT_SCATTER, s);
-    if (hash && small)
-      k_rs_scatter<true, 2048><<<G, NT, 0, s>>>(raw, out, n, G, shift, nb, pmask, hist, dtot);
-    else if (hash)
-      k_rs_scatter<true, 4096><<<G, NT, 0, s>>>(raw, out, n, G, shift, nb, pmask, hist, dtot);
-    else if (small)
-      k_rs_scatter<false, 2048><<<G, NT, 0, s>>>(in, out, n, G, shift, nb, 0, hist, dtot);
-    else
-      k_rs_scatter<false, 4096><<<G, NT, 0, s>>>(in, out, n, G, shift, nb, 0, hist, dtot);
-    if (t) t->end(QF_PROF_SORT_SCATTER, s);
+    sort_pass<RADIX_MAX>(in, out, raw, hash, n, G, shift, nb, pmask, hist, dtot, small, s, t);
     uint64_t *tmp = in;
     in = out;
     out = tmp;

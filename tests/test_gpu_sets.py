@@ -253,3 +253,25 @@ def test_set_updates_restricted_to_listed_filters():
             c.check_all(f"after restricted step {step}")
     c.check_all("after restricted updates")
     c.check_lookups(fid[:5000], keys[:5000], "restricted updates")
+
+
+@pytest.mark.parametrize("qs", [[12, 12, 12, 6], [13, 11, 10, 9, 8, 7]])
+def test_set_invalid_indexes_among_many_keys(qs):
+    # many keys over several sort work-groups, some with filter indexes out of
+    # range (their composite key is all ones): they must sort after every valid
+    # key in every radix pass and leave the valid keys' tables exact
+    qf = _qf()
+    note(f"invalid indexes among many keys, q={qs}")
+    c = SetCase(qs, 8, seed=91)
+    fid, keys = c.tagged(int(0.7 * sum(1 << q for q in qs)), seed=92)
+    bad = c.rng.random(len(fid)) < 0.05
+    fid = fid.copy()
+    fid[bad] = len(qs) + c.rng.integers(0, 5, size=int(bad.sum())).astype(np.int32)
+    c.set.insert(dev_fid(fid), dev(keys))
+    assert c.set.sync() == qf.QF_ERR_ARG
+    for i, o in enumerate(c.os):
+        part = keys[fid == i]
+        if len(part):
+            assert o.insert(part) == 0
+    for i, (f, o) in enumerate(zip(c.fs, c.os)):
+        check_filter(f, o, f"filter {i} with invalid indexes in the batch")
