@@ -438,7 +438,8 @@ def bench_fill(args) -> dict:
 def bench_serve(args) -> dict:
     """Serving: 256 device-resident filters (2^18..2^26 quotients, r = 8 or 16), filled to load 0.5,
     answer Poisson arrivals of mixed requests (70 % query, 25 % insert, 5 % delete) with sizes
-    log-uniform in 1..65,536 keys, HBM budget 64 GB.  A saturation run measures capacity; then
+    log-uniform in 1..65,536 keys, HBM budget 64 GB.  A saturation run measures capacity (and the
+    same request stream replayed as a plain loop of per-request calls gives the baseline); then
     arrivals at 25 / 50 / 90 % of it give ops/s and p50 / p99 latency (submission to completion)."""
     import threading
 
@@ -537,8 +538,11 @@ def bench_serve(args) -> dict:
                 "p99_ms": round(float(np.percentile(lat_ms, 99)), 3)}
 
     nreq = args.serve_requests
-    sat = run(make_requests(nreq, 1), None)
+    sat_reqs = make_requests(nreq, 1)
+    sat = run(sat_reqs, None)
     log(f"serve saturation: {sat}")
+    loop = loop_replay(qs, rs, fill, sat_reqs, qf)
+    log(f"serve, same stream as a loop of per-request calls: {loop}")
     cap_rps = sat["req_per_s"]
     points = []
     for frac in (0.25, 0.5, 0.9):
@@ -548,12 +552,49 @@ def bench_serve(args) -> dict:
         log(f"serve at {frac:.0%} of capacity: {r_}")
     st = srv.stats()
     srv.close()
+    sat["vs_loop"] = round(sat["Bps"] / loop["Bps"], 2)
     return {"metric": "serving: mixed request throughput and latency (256 filters, 2^18..2^26, r=8/16)",
             "value": sat["Bps"], "unit": "B keys/s at saturation", "n_gpus": 1, "higher_is_better": True,
             "dtype": "u64", "data": "synthetic",
             "config": {"workload": f"serve_{nf}filters_q18to26_r8or16_mix70q25i5d", "filters": nf,
                        "requests_per_run": nreq, "budget_bytes": 64 << 30},
-            "saturation": sat, "points": points, "server": st}
+            "saturation": sat, "loop": loop, "points": points, "server": st}
+
+
+def loop_replay(qs, rs, fill, reqs, qf) -> dict:
+    """The plain per-filter launch loop: filters of the same sizes and contents, and the same request
+    stream as direct calls in submission order (keys copied to the device per request, query
+    answers copied back per request, as the server does)."""
+    import torch
+
+    fs = [qf.CQF(int(q), int(r)) for q, r in zip(qs, rs)]
+    dbuf = torch.empty(1 << 22, dtype=torch.int64, device="cuda")
+    for i, k in enumerate(fill):
+        for a in range(0, len(k), 1 << 22):
+            part = k[a:a + (1 << 22)]
+            dbuf[:len(part)].copy_(torch.from_numpy(part.view(np.int64)))
+            fs[i].insert(dbuf[:len(part)])
+    for f in fs:
+        f.reserve(1 << 16)
+    nf_buf = torch.zeros(1, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for op, f, keys in reqs:
+        d = torch.from_numpy(np.ascontiguousarray(keys).view(np.int64)).to("cuda")
+        if op == qf.QFS_INSERT:
+            fs[f].insert(d)
+        elif op == qf.QFS_DELETE:
+            fs[f].delete(d, nf_buf)
+        else:
+            fs[f].query(d).cpu()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for f in fs:
+        assert f.sync() == 0
+        f.close()
+    nkeys = sum(len(k) for _, _, k in reqs)
+    return {"requests": len(reqs), "keys": nkeys, "seconds": round(dt, 4), "Bps": round(nkeys / dt / 1e9, 4),
+            "req_per_s": round(len(reqs) / dt, 1)}
 
 
 def main() -> int:
