@@ -82,3 +82,42 @@ def test_full_size_load_sweep_table_and_step():
     compare(lay2, brute.layout(ms0[0], ms0[1], w.q, w.r), "after the step's delete")
     note(f"step bit-exact ({time.time() - t0:.0f}s)")
     f.close()
+
+
+def test_largest_table_zipf_counts_sampled():
+    # the largest configuration's table (2^30 quotients, r = 16: 5.4 GB for
+    # the two copies), filled by one batch of Zipf(1.1) instances over 2^28
+    # values; the oracle cannot build a table this size in a test, so the
+    # check is exact counts of a sample against the definition: a key's count
+    # is the multiplicity of its fingerprint in the inserted multiset
+    from paper_2212_09005_amd import inputs, qf
+
+    q, r, n = 30, 16, 1 << 26
+    note(f"q={q} r={r}: {n} Zipf instances in one batch")
+    keys = inputs.zipf_keys(3, n, 1.1, 1 << 28)
+    f = qf.CQF(q, r)
+    d = torch.from_numpy(keys.view(np.int64)).to("cuda")
+    f.insert(d)
+    assert f.sync() == 0
+    ms = brute.multiset(brute.fingerprints(keys, q, r))
+    present = keys[np.random.default_rng(5).integers(0, n, size=1 << 19)]
+    probe = np.concatenate([present, inputs.absent_keys(6, 1 << 19)])
+    dp = torch.from_numpy(probe.view(np.int64)).to("cuda")
+    want = brute.counts_of(*ms, brute.fingerprints(probe, q, r))
+    got = f.count(dp).cpu().numpy().view(U64)
+    assert np.array_equal(got, want), f"counts differ at {int(np.count_nonzero(got != want))} keys"
+    assert (got[: 1 << 19] > 0).all()
+    info = f.info()
+    note(f"inserted and counted; batches {info['batches']}")
+    # delete a quarter of the instances and count again
+    drop = keys[inputs.bernoulli_mask(7, n, 0.25)]
+    nf = torch.zeros(1, dtype=torch.int64, device="cuda")
+    f.delete(torch.from_numpy(drop.view(np.int64)).to("cuda"), nf)
+    assert f.sync() == 0
+    assert int(nf.cpu()[0]) == 0
+    ms2, short = brute.merge_multisets(ms, brute.multiset(brute.fingerprints(drop, q, r)), subtract=True)
+    assert int(short) == 0
+    want2 = brute.counts_of(*ms2, brute.fingerprints(probe, q, r))
+    got2 = f.count(dp).cpu().numpy().view(U64)
+    assert np.array_equal(got2, want2), f"counts after delete differ at {int(np.count_nonzero(got2 != want2))} keys"
+    f.close()
