@@ -92,9 +92,21 @@ __global__ __launch_bounds__(NT) void k_rs_hist(const uint64_t *__restrict__ in,
   const uint32_t g = blockIdx.x;
   const uint32_t dmask = (1u << nbits) - 1u;
   const uint64_t lo = chunk_lo(n, G, g), hi = chunk_lo(n, G, g + 1);
-  for (uint64_t i = lo + tid; i < hi; i += NT) {
-    const uint64_t v = HASH ? (mix64(in[i]) & pmask) : in[i];
-    atomicAdd(&h[wv][static_cast<uint32_t>(v >> shift) & dmask], 1u);
+  // (eight loads in flight per lane, then their counts)
+  for (uint64_t i0 = lo + tid; i0 < hi; i0 += 8ull * NT) {
+    uint64_t v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const uint64_t i = i0 + static_cast<uint64_t>(k) * NT;
+      v[k] = i < hi ? in[i] : 0ull;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (i0 + static_cast<uint64_t>(k) * NT < hi) {
+        const uint64_t x = HASH ? (mix64(v[k]) & pmask) : v[k];
+        atomicAdd(&h[wv][static_cast<uint32_t>(x >> shift) & dmask], 1u);
+      }
+    }
   }
   __syncthreads();
   for (int d = tid; d < ND; d += NT) {
@@ -190,11 +202,14 @@ __device__ __forceinline__ void digits_exscan(const uint32_t (&v)[DPT], uint32_t
 }
 
 // Stable scatter of one digit.  Each group takes its chunk in tiles of TILE
-// keys (KPL = TILE / NT per lane): the tile is ordered by digit in LDS (ranks
-// from wave ballots, rounds of 256 keys in index order, so the order is
-// stable), then written out so that each digit's keys of the tile land as
-// one contiguous run -- coalesced stores instead of one 8-byte store per key
-// to a different line.  ND digits (256 or 512), DPT per lane.
+// keys; wave w of the work-group owns the tile's w-th quarter, read in
+// rounds of 64 consecutive keys.  A wave ranks its keys on its own (wave
+// ballots over the digit bits give the rank inside a round, a per-wave LDS
+// counter per digit the keys of earlier rounds), so the only work-group
+// barriers are between the tile's phases: rank, per-digit offsets (tile digit
+// starts, then the waves in order), placement into LDS in digit order, and the
+// copy-out, where each digit's keys of the tile land as one contiguous run
+// (coalesced stores).  The order inside a digit is the input order: stable.
 template <bool HASH, int TILE, int ND>
 __global__ __launch_bounds__(NT) void k_rs_scatter(const uint64_t *__restrict__ in,
                                                    uint64_t *__restrict__ out, uint64_t n,
@@ -202,15 +217,16 @@ __global__ __launch_bounds__(NT) void k_rs_scatter(const uint64_t *__restrict__ 
                                                    uint64_t pmask,
                                                    const uint32_t *__restrict__ hist,
                                                    const uint32_t *__restrict__ dtot) {
-  constexpr int KPL = TILE / NT;
+  constexpr int KPL = TILE / NT;    // rounds per wave
+  constexpr int WQ = TILE / NWAVE;  // keys per wave and tile
   constexpr int DPT = ND / NT;
   __shared__ uint64_t tile[TILE];
   __shared__ uint32_t gpos[ND];  // global position of the group's next key of digit d
   __shared__ uint32_t loff[ND];  // start of digit d in the tile
   __shared__ uint32_t placed[ND];
-  __shared__ uint32_t wc[NWAVE][ND];
+  __shared__ uint32_t wc[NWAVE][ND];  // per wave: keys of digit d (then: its first tile position)
   __shared__ uint32_t sh[NWAVE];
-  const int tid = threadIdx.x, wv = tid >> 6;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const uint32_t g = blockIdx.x;
   {
     // keys with a smaller digit: exclusive scan of the digit totals
@@ -225,40 +241,26 @@ __global__ __launch_bounds__(NT) void k_rs_scatter(const uint64_t *__restrict__ 
       for (int w = 0; w < NWAVE; ++w) wc[w][d] = 0;
     }
   }
+  __syncthreads();
   const uint64_t lo = chunk_lo(n, G, g), hi = chunk_lo(n, G, g + 1);
   const uint32_t dmask = (1u << nbits) - 1u;
+  const uint64_t below = (1ull << lane) - 1ull;
   for (uint64_t t0 = lo; t0 < hi; t0 += TILE) {
     const uint32_t cnt = static_cast<uint32_t>(min(static_cast<uint64_t>(TILE), hi - t0));
-#pragma unroll
-    for (int j = 0; j < DPT; ++j) placed[tid * DPT + j] = 0;
-    __syncthreads();
+    // 1. rank: each wave over its quarter, round by round
     uint64_t key[KPL];
+    uint32_t rk[KPL];
+    // (all of the wave's loads first, so that they are in flight together)
 #pragma unroll
     for (int k = 0; k < KPL; ++k) {
-      const uint32_t jj = k * NT + tid;
-      key[k] = 0;
-      if (jj < cnt) {
-        key[k] = HASH ? (mix64(in[t0 + jj]) & pmask) : in[t0 + jj];
-        atomicAdd(&placed[static_cast<uint32_t>(key[k] >> shift) & dmask], 1u);
-      }
+      const uint32_t jj = wv * WQ + k * 64 + lane;
+      key[k] = jj < cnt ? in[t0 + jj] : 0ull;
     }
-    __syncthreads();
-    {
-      // tile-local digit starts: exclusive scan of the tile's digit counts
-      uint32_t v[DPT], ex[DPT];
-#pragma unroll
-      for (int j = 0; j < DPT; ++j) v[j] = placed[tid * DPT + j];
-      digits_exscan<DPT>(v, ex, sh);
-#pragma unroll
-      for (int j = 0; j < DPT; ++j) {
-        loff[tid * DPT + j] = ex[j];
-        placed[tid * DPT + j] = 0;
-      }
-    }
-    __syncthreads();
 #pragma unroll
     for (int k = 0; k < KPL; ++k) {
-      const bool valid = static_cast<uint32_t>(k * NT + tid) < cnt;
+      const uint32_t jj = wv * WQ + k * 64 + lane;
+      const bool valid = jj < cnt;
+      if (HASH) key[k] = mix64(key[k]) & pmask;
       const uint32_t d = static_cast<uint32_t>(key[k] >> shift) & dmask;
       uint64_t peers = __ballot(valid);
       for (uint32_t b = 0; b < nbits; ++b) {
@@ -266,28 +268,50 @@ __global__ __launch_bounds__(NT) void k_rs_scatter(const uint64_t *__restrict__ 
         const uint64_t bal = __ballot(bit);
         peers &= bit ? bal : ~bal;
       }
-      const uint32_t rank = static_cast<uint32_t>(popc64(peers & lanemask_lt()));
-      if (valid && rank == 0) wc[wv][d] = static_cast<uint32_t>(popc64(peers));
-      __syncthreads();
-      if (valid) {
-        uint32_t pos = loff[d] + placed[d] + rank;
-        for (int w = 0; w < wv; ++w) pos += wc[w][d];
-        tile[pos] = key[k];
-      }
-      __syncthreads();
+      const uint32_t before = valid ? wc[wv][d] : 0u;
+      const uint32_t r = static_cast<uint32_t>(popc64(peers & below));
+      rk[k] = before + r;
+      // (the wave's lanes read the counter before its first lane of the
+      // digit writes it: a wave's LDS accesses complete in program order)
+      if (valid && r == 0) wc[wv][d] = before + static_cast<uint32_t>(popc64(peers));
+    }
+    __syncthreads();
+    // 2. per digit: the tile's digit starts, then each wave's first position
+    {
+      uint32_t v[DPT], ex[DPT];
 #pragma unroll
       for (int j = 0; j < DPT; ++j) {
-        const int dd = tid * DPT + j;
+        const int d = tid * DPT + j;
         uint32_t t = 0;
-        for (int w = 0; w < NWAVE; ++w) {
-          t += wc[w][dd];
-          wc[w][dd] = 0;
-        }
-        placed[dd] += t;
+        for (int w = 0; w < NWAVE; ++w) t += wc[w][d];
+        v[j] = t;
       }
-      __syncthreads();
+      digits_exscan<DPT>(v, ex, sh);
+#pragma unroll
+      for (int j = 0; j < DPT; ++j) {
+        const int d = tid * DPT + j;
+        loff[d] = ex[j];
+        placed[d] = v[j];
+        uint32_t run = ex[j];
+        for (int w = 0; w < NWAVE; ++w) {
+          const uint32_t c = wc[w][d];
+          wc[w][d] = run;
+          run += c;
+        }
+      }
     }
-    // the tile in digit order -> each digit's run to its global place
+    __syncthreads();
+    // 3. the tile in digit order in LDS
+#pragma unroll
+    for (int k = 0; k < KPL; ++k) {
+      const uint32_t jj = wv * WQ + k * 64 + lane;
+      if (jj < cnt) {
+        const uint32_t d = static_cast<uint32_t>(key[k] >> shift) & dmask;
+        tile[wc[wv][d] + rk[k]] = key[k];
+      }
+    }
+    __syncthreads();
+    // 4. each digit's run to its global place
     for (uint32_t jj = tid; jj < cnt; jj += NT) {
       const uint64_t v = tile[jj];
       const uint32_t d = static_cast<uint32_t>(v >> shift) & dmask;
@@ -295,7 +319,12 @@ __global__ __launch_bounds__(NT) void k_rs_scatter(const uint64_t *__restrict__ 
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < DPT; ++j) gpos[tid * DPT + j] += placed[tid * DPT + j];
+    for (int j = 0; j < DPT; ++j) {
+      const int d = tid * DPT + j;
+      gpos[d] += placed[d];
+      for (int w = 0; w < NWAVE; ++w) wc[w][d] = 0;
+    }
+    __syncthreads();
   }
 }
 
@@ -311,6 +340,7 @@ __global__ __launch_bounds__(NT) void k_rle_count(const uint64_t *__restrict__ s
   const uint32_t g = blockIdx.x;
   const uint64_t lo = chunk_lo(n, G, g), hi = chunk_lo(n, G, g + 1);
   uint32_t c = 0;
+#pragma unroll 8
   for (uint64_t i = lo + tid; i < hi; i += NT) c += is_head(s, i);
   for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
   if ((tid & 63) == 0) red[tid >> 6] = c;
