@@ -61,8 +61,11 @@ void free_scratch(qf::Pipe &p) {
   (void)hipFree(p.bufC);
   (void)hipFree(p.bufD);
   (void)hipFree(p.bufE);
+  (void)hipFree(p.hist);
   p.bufA = p.bufB = p.bufC = p.bufD = p.bufE = nullptr;
+  p.hist = nullptr;
   p.cap = 0;
+  p.hist_words = 0;
 }
 
 int ensure_scratch(qf::Pipe &p, uint64_t n, hipStream_t s) {
@@ -70,17 +73,20 @@ int ensure_scratch(qf::Pipe &p, uint64_t n, hipStream_t s) {
   uint64_t cap = 1ull << 16;
   while (cap < n) cap <<= 1;
   if (p.cap) QF_HIP(hipStreamSynchronize(s));
-  p.device_bytes -= 8 * p.cap * sizeof(uint64_t);
+  p.device_bytes -= 8 * p.cap * sizeof(uint64_t) + p.hist_words * sizeof(uint32_t);
   free_scratch(p);
   const size_t bytes = cap * sizeof(uint64_t);
+  const uint64_t hw = qf::sort_count_words(cap);
   if (hipMalloc(&p.bufA, bytes) != hipSuccess || hipMalloc(&p.bufB, bytes) != hipSuccess ||
       hipMalloc(&p.bufC, bytes) != hipSuccess || hipMalloc(&p.bufD, bytes) != hipSuccess ||
-      hipMalloc(&p.bufE, 4 * bytes) != hipSuccess) {
+      hipMalloc(&p.bufE, 4 * bytes) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void **>(&p.hist), hw * sizeof(uint32_t)) != hipSuccess) {
     free_scratch(p);
     return fail(QF_ERR_OOM);
   }
   p.cap = cap;
-  p.device_bytes += 8 * bytes;
+  p.hist_words = hw;
+  p.device_bytes += 8 * bytes + hw * sizeof(uint32_t);
   return QF_OK;
 }
 
@@ -90,7 +96,6 @@ void pipe_free(qf::Pipe &p) {
   (void)hipFree(p.rb);
   (void)hipFree(p.tags);
   (void)hipFree(p.pst);
-  (void)hipFree(p.hist);
   (void)hipFree(p.d_err);
   (void)hipFree(p.d_afil);
   (void)hipFree(p.d_areg);
@@ -162,14 +167,12 @@ int pipe_init(qf::Pipe &p, qf_filter *const *fs, uint32_t nf, const qf::Tune &tn
     p.h_rbase[i] = desc[i].rbase;
     for (uint32_t k = 0; k < desc[i].nregions; ++k) rmap[desc[i].rbase + k] = i;
   }
-  p.hist_words = 256ull * 1024ull + 256ull;  // radix histograms (256 digits x 1024 groups) + digit totals
   const uint64_t tag_words = 8ull * G + 8;        // 3 G tags, 4 G statistics, G carries
   bool ok = hipMalloc(reinterpret_cast<void **>(&p.d_desc), nf * sizeof(qf::FDesc)) == hipSuccess &&
             hipMalloc(reinterpret_cast<void **>(&p.d_rmap), G * sizeof(uint32_t)) == hipSuccess &&
             hipMalloc(reinterpret_cast<void **>(&p.rb), (G + 1) * sizeof(uint64_t)) == hipSuccess &&
             hipMalloc(reinterpret_cast<void **>(&p.tags), tag_words * sizeof(uint64_t)) == hipSuccess &&
             hipMalloc(reinterpret_cast<void **>(&p.pst), qf::ST_WORDS * sizeof(uint64_t)) == hipSuccess &&
-            hipMalloc(reinterpret_cast<void **>(&p.hist), p.hist_words * sizeof(uint32_t)) == hipSuccess &&
             hipMalloc(reinterpret_cast<void **>(&p.d_err), nf * sizeof(int64_t)) == hipSuccess &&
             hipMalloc(reinterpret_cast<void **>(&p.d_afil), nf * sizeof(uint32_t)) == hipSuccess &&
             hipMalloc(reinterpret_cast<void **>(&p.d_areg), G * sizeof(uint32_t)) == hipSuccess;
@@ -184,8 +187,7 @@ int pipe_init(qf::Pipe &p, qf_filter *const *fs, uint32_t nf, const qf::Tune &tn
   p.one = desc[0];
   p.rstat = p.tags + ((3ull * G + 1) & ~1ull);  // 16-byte aligned (read as 16-byte vectors)
   p.cb = reinterpret_cast<int64_t *>(p.tags + 7ull * G + 2);
-  p.device_bytes = nf * sizeof(qf::FDesc) + G * 4 + (G + 1) * 8 + tag_words * 8 + qf::ST_WORDS * 8 +
-                   p.hist_words * 4;
+  p.device_bytes = nf * sizeof(qf::FDesc) + G * 4 + (G + 1) * 8 + tag_words * 8 + qf::ST_WORDS * 8;
   return QF_OK;
 }
 
@@ -236,7 +238,7 @@ int pipe_update(qf::Pipe &p, const uint64_t *keys, const uint32_t *fid, uint64_t
     QF_HIP(qf::launch_sort(p.bufA, p.bufB, n, bits, p.hist, &sorted, s, p, keys, pmask));
   }
   uint64_t *other = sorted == p.bufA ? p.bufB : p.bufA;
-  QF_HIP(qf::launch_rle(sorted, n, other, p.bufC, p.bufD, p.hist, p.pst, s, p));
+  QF_HIP(qf::launch_rle(sorted, n, other, p.bufC, p.bufD, p.hist + 256, p.pst, s, p));
   QF_HIP(qf::launch_bounds(p.bufC, p, s));
   QF_HIP(qf::launch_merge(p, p.bufC, p.bufD, del, not_found, s));
   p.batches += 1;

@@ -62,7 +62,7 @@ struct Pipe {
   uint64_t cap = 0;
   uint64_t *bufA = nullptr, *bufB = nullptr, *bufC = nullptr, *bufD = nullptr;
   uint64_t *bufE = nullptr;   // 32 bytes per key: the merge's per-entry scratch
-  uint32_t *hist = nullptr;   // radix histograms / tile counts
+  uint32_t *hist = nullptr;   // radix digit totals and histograms / tile counts (sized with the scratch)
   uint64_t hist_words = 0;
   uint64_t device_bytes = 0;
   uint64_t batches = 0;
@@ -127,8 +127,14 @@ hipError_t launch_import(qf_filter *f, const uint64_t *occ, const uint64_t *rend
                          const uint16_t *slots, const uint32_t *offs, hipStream_t s);
 
 // sort tiling: G work-groups each own a contiguous chunk of at least
-// `chunk` keys (at most SORT_MAX_GROUPS groups)
+// `chunk` keys (at most SORT_MAX_GROUPS groups; chunks are never below
+// SORT_MIN_CHUNK keys)
+constexpr uint32_t SORT_MAX_GROUPS = 16384;
+constexpr uint32_t SORT_MIN_CHUNK = 4096;
 uint32_t sort_groups(uint64_t n, uint32_t chunk);
+// words of the sort's count buffer for batches of up to cap keys: 256 digit
+// totals, then 256 counts per work-group (also the reduction's per-group counts)
+uint64_t sort_count_words(uint64_t cap);
 int max_region_log2(uint32_t r);
 
 }  // namespace qf

@@ -7,6 +7,8 @@
 // Sec. 5.4: duplicates are reduced to <item, count> pairs before the insert.
 // The sort is an LSD radix sort written for wave64: 8-bit digits, one LDS
 // histogram per wave, stable ranks from wave ballots.
+#include <algorithm>
+
 #include "qf_dev.h"
 #include "qf.h"
 #include "qf_lib.h"
@@ -16,7 +18,6 @@ namespace {
 
 constexpr int NT = 256;
 constexpr int NWAVE = NT / 64;
-constexpr uint32_t SORT_MAX_GROUPS = 1024;
 constexpr uint32_t RADIX_BITS = 8;                 // widest digit
 constexpr int RADIX_MAX = 1 << RADIX_BITS;        // digits per pass, at most
 
@@ -421,6 +422,11 @@ inline uint32_t blocks_for(uint64_t n, uint32_t cap = 65535u * 4u) {
 
 }  // namespace
 
+uint64_t sort_count_words(uint64_t cap) {
+  const uint64_t g = std::min<uint64_t>(SORT_MAX_GROUPS, (cap + SORT_MIN_CHUNK - 1) / SORT_MIN_CHUNK);
+  return static_cast<uint64_t>(RADIX_MAX) * (1 + std::max<uint64_t>(g, 1));
+}
+
 uint32_t sort_groups(uint64_t n, uint32_t chunk) {
   uint64_t g = (n + chunk - 1) / chunk;
   if (g < 1) g = 1;
@@ -491,8 +497,9 @@ hipError_t launch_sort(uint64_t *a, uint64_t *b, uint64_t n, uint32_t bits, uint
   // a digit costs a wave ballot per key round of the scatter)
   const uint32_t npass = bits == 0 ? 0 : (bits + RADIX_BITS - 1) / RADIX_BITS;
   const uint32_t db = npass ? (bits + npass - 1) / npass : 0;
-  // digit totals live after the RADIX_MAX x SORT_MAX_GROUPS histogram words
-  uint32_t *dtot = hist + static_cast<uint64_t>(RADIX_MAX) * SORT_MAX_GROUPS;
+  // the count buffer: RADIX_MAX digit totals, then the G x RADIX_MAX histogram
+  uint32_t *dtot = hist;
+  hist += RADIX_MAX;
   uint64_t *in = a, *out = b;
   for (uint32_t p = 0; p < npass; ++p) {
     const uint32_t shift = db * p;
