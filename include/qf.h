@@ -133,13 +133,18 @@ uint64_t qf_table_bytes(uint32_t q, uint32_t r);
 /* info[0..7] = q, r, N, E, P, region slots, device bytes held, batches run. */
 int qf_info(const qf_t *f, uint64_t *info);
 
-/* Kernel timing (for benchmarks): while enabled, every kernel launch of this
- * filter is bracketed by two HIP events recorded on the launch stream.
+/* Kernel timing (for benchmarks): kinds is a bit mask of (1 << QF_PROF_*)
+ * values (QF_PROF_ALL: every kind; 0 disables timing and drops what was not
+ * read).  While enabled, every kernel launch of this filter of a selected
+ * kind is bracketed by two HIP events recorded on the launch stream (each
+ * pair delays the stream by a few microseconds, so time only the kinds of
+ * interest).  Calling it again while enabled changes the selection.
  * qf_profile_read waits for the recorded events, returns per kind the summed
  * milliseconds ms[k] and the number of launches n[k] since the last read
  * (arrays of QF_PROF_KINDS entries, host memory) and clears them.  The sort
  * kinds count each radix pass as one launch; QF_PROF_REDUCE covers the four
- * small kernels of the duplicate reduction. */
+ * small kernels of the duplicate reduction; QF_PROF_MERGE covers the merge
+ * and its two small companions (old carries before, statistics after). */
 enum {
   QF_PROF_HASH = 0,
   QF_PROF_SORT_HIST = 1,
@@ -149,9 +154,10 @@ enum {
   QF_PROF_BOUNDS = 5,
   QF_PROF_MERGE = 6,
   QF_PROF_LOOKUP = 7,
-  QF_PROF_KINDS = 8
+  QF_PROF_KINDS = 8,
+  QF_PROF_ALL = (1 << QF_PROF_KINDS) - 1
 };
-int qf_profile_enable(qf_t *f, int enable);
+int qf_profile_enable(qf_t *f, int kinds);
 int qf_profile_read(qf_t *f, double *ms, uint64_t *n);
 
 /* ---- filter sets: many filters, one pipeline of launches ------------------
@@ -205,7 +211,8 @@ int qf_set_reserve(qf_set_t *s, uint64_t n, void *stream);
 /* info[0..7] = nf, r, total regions, largest region log2, device bytes held by
  * the set's pipeline, batches run, bits of the composite sort key, 0. */
 int qf_set_info(const qf_set_t *s, uint64_t *info);
-int qf_set_profile_enable(qf_set_t *s, int enable);
+/* Kernel timing of the set's pipeline, as qf_profile_enable / _read. */
+int qf_set_profile_enable(qf_set_t *s, int kinds);
 int qf_set_profile_read(qf_set_t *s, double *ms, uint64_t *n);
 
 /* ---- launch parameters ---------------------------------------------------

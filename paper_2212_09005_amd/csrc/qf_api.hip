@@ -273,6 +273,7 @@ struct EventTimer : qf::Timer {
   struct Pair { int kind; hipEvent_t a, b; };
   std::vector<Pair> pending;
   hipEvent_t open_ev = nullptr;
+  uint32_t mask = QF_PROF_ALL;  // kinds whose launches are bracketed
   double ms[QF_PROF_KINDS] = {};
   uint64_t n[QF_PROF_KINDS] = {};
   hipEvent_t take() {
@@ -285,11 +286,13 @@ struct EventTimer : qf::Timer {
     (void)hipEventCreate(&e);
     return e;
   }
-  void begin(int, hipStream_t s) override {
+  void begin(int kind, hipStream_t s) override {
+    if (!((mask >> kind) & 1u)) return;
     open_ev = take();
     (void)hipEventRecord(open_ev, s);
   }
   void end(int kind, hipStream_t s) override {
+    if (!((mask >> kind) & 1u) || !open_ev) return;
     hipEvent_t e = take();
     (void)hipEventRecord(e, s);
     pending.push_back(Pair{kind, open_ev, e});
@@ -350,9 +353,11 @@ int retune(qf::Pipe &p, qf_filter *const *fs, uint32_t nf, const qf::Tune &tn) {
   return rc;
 }
 
-int profile_enable(qf::Pipe &p, int enable) {
+int profile_enable(qf::Pipe &p, int kinds) {
+  const bool enable = (kinds & QF_PROF_ALL) != 0;
   if (enable && !p.timer) p.timer = new (std::nothrow) EventTimer();
   if (enable && !p.timer) return fail(QF_ERR_OOM);
+  if (enable) static_cast<EventTimer *>(p.timer)->mask = static_cast<uint32_t>(kinds) & QF_PROF_ALL;
   if (!enable && p.timer) {
     (void)static_cast<EventTimer *>(p.timer)->collect();
     delete p.timer;
@@ -703,9 +708,9 @@ int qf_set_info(const qf_set_t *st, uint64_t *info) {
   return QF_OK;
 }
 
-int qf_set_profile_enable(qf_set_t *st, int enable) {
+int qf_set_profile_enable(qf_set_t *st, int kinds) {
   if (!st) return fail(QF_ERR_ARG);
-  return profile_enable(st->pipe, enable);
+  return profile_enable(st->pipe, kinds);
 }
 
 int qf_set_profile_read(qf_set_t *st, double *ms, uint64_t *n) {
@@ -732,9 +737,9 @@ int qf_info(const qf_t *f, uint64_t *info) {
   return QF_OK;
 }
 
-int qf_profile_enable(qf_t *f, int enable) {
+int qf_profile_enable(qf_t *f, int kinds) {
   if (!f) return fail(QF_ERR_ARG);
-  return profile_enable(f->pipe, enable);
+  return profile_enable(f->pipe, kinds);
 }
 
 int qf_profile_read(qf_t *f, double *ms, uint64_t *n) {

@@ -249,8 +249,18 @@ def qf_info(f: int) -> dict:
 PROF_KINDS = ("hash", "sort_hist", "sort_scan", "sort_scatter", "reduce", "bounds", "merge", "lookup")
 
 
-def qf_profile_enable(f: int, enable: bool = True) -> int:
-    return lib().qf_profile_enable(f, 1 if enable else 0)
+def _prof_mask(enable: bool, kinds) -> int:
+    """Bit mask of the timed kinds: every kind, or the named ones."""
+    if not enable:
+        return 0
+    if kinds is None:
+        return (1 << len(PROF_KINDS)) - 1
+    return sum(1 << PROF_KINDS.index(k) for k in set(kinds))
+
+
+def qf_profile_enable(f: int, enable: bool = True, kinds=None) -> int:
+    """Time the launches of the named kinds (default all); enable=False stops."""
+    return lib().qf_profile_enable(f, _prof_mask(enable, kinds))
 
 
 def qf_profile_read(f: int) -> dict:
@@ -412,8 +422,8 @@ def qf_set_info(s: int) -> dict:
     return dict(zip(keys, (int(v) for v in buf)))
 
 
-def qf_set_profile_enable(s: int, enable: bool = True) -> int:
-    return lib().qf_set_profile_enable(s, 1 if enable else 0)
+def qf_set_profile_enable(s: int, enable: bool = True, kinds=None) -> int:
+    return lib().qf_set_profile_enable(s, _prof_mask(enable, kinds))
 
 
 def qf_set_profile_read(s: int) -> dict:

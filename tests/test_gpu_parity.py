@@ -312,3 +312,31 @@ def test_zipf_counting_scaled(q, r, batches):
     short = m.delete(keys[dmask])
     export_ok(f, m.layout(), "zipf delete")
     assert int(nf.item()) == short == 0
+
+
+def test_launch_timer_kind_selection():
+    # the timer brackets only the selected kinds; results are unaffected
+    q, r = 14, 8
+    note("launch timer kind selection")
+    qf = _qf()
+    f = qf.CQF(q, r)
+    o = oqf.OracleQF(q, r)
+    keys = inputs.uniform_keys(5, 6000)
+    assert qf.qf_profile_enable(f.h, True, kinds=("merge", "lookup")) == 0
+    f.insert(dev(keys[:3000]))
+    f.query(dev(keys))
+    prof = qf.qf_profile_read(f.h)
+    assert prof["merge"][1] == 1 and prof["lookup"][1] == 1
+    assert all(prof[k][1] == 0 for k in prof if k not in ("merge", "lookup"))
+    assert prof["merge"][0] > 0.0
+    assert qf.qf_profile_enable(f.h, True) == 0  # every kind
+    f.insert(dev(keys[3000:]))
+    prof = qf.qf_profile_read(f.h)
+    assert prof["merge"][1] == 1 and prof["sort_scatter"][1] >= 1 and prof["reduce"][1] == 1
+    assert prof["lookup"][1] == 0
+    assert qf.qf_profile_enable(f.h, False) == 0
+    f.insert(dev(keys[:10]))
+    assert all(n == 0 for _, n in qf.qf_profile_read(f.h).values())
+    o.insert(keys)
+    o.insert(keys[:10])
+    export_ok(f, o.export(), "after timed and untimed batches")
