@@ -212,7 +212,9 @@ __device__ __forceinline__ void digits_exscan(const uint32_t (&v)[DPT], uint32_t
 // copy-out, where each digit's keys of the tile land as one contiguous run
 // (coalesced stores).  The order inside a digit is the input order: stable.
 template <bool HASH, int TILE, int ND>
-__global__ __launch_bounds__(NT) void k_rs_scatter(const uint64_t *__restrict__ in,
+// (at most 128 VGPRs, so four 4096-key work-groups fit a CU's registers as
+// well as its LDS: a 2^22-key pass of 1024 groups runs in one round)
+__global__ __launch_bounds__(NT, 4) void k_rs_scatter(const uint64_t *__restrict__ in,
                                                    uint64_t *__restrict__ out, uint64_t n,
                                                    uint32_t G, uint32_t shift, uint32_t nbits,
                                                    uint64_t pmask,
