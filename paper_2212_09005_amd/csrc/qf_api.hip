@@ -154,6 +154,7 @@ int pipe_init(qf::Pipe &p, qf_filter *const *fs, uint32_t nf, const qf::Tune &tn
     desc[i] = desc_of(fs[i], static_cast<uint32_t>(G), rl);
     p.h_nreg[i] = desc[i].nregions;
     G += desc[i].nregions;
+    p.fin_slices = std::max(p.fin_slices, (desc[i].nregions + qf::FIN_REG - 1) / qf::FIN_REG);
   }
   if (G >= (1ull << 31)) return fail(QF_ERR_ARG);
   p.G = static_cast<uint32_t>(G);

@@ -44,11 +44,8 @@ enum : int {
   ST_USED = 2,    // used slots of the current table
   ST_DIST = 3,    // distinct fingerprints
   ST_TOTAL = 4,   // total count (mod 2^64)
-  ST_NUSED = 5,   // the same three for the table being written
-  ST_NDIST = 6,
-  ST_NTOTAL = 7,
-  ST_TILE = 8,    // region tile counter of the merge launch
-  ST_DONE = 9,    // finished regions of the merge launch
+  ST_ACC = 5,     // 5..8: the merge launch's statistics, summed over work-groups
+  ST_TICKET = 9,  // work-groups of the launch's finish that are done
   ST_BATCH = 10,  // error bits of the running batch
   ST_NUNIQ = 11,  // distinct fingerprints in the running batch
   ST_BATCHES = 12,

@@ -42,6 +42,7 @@ struct FDesc {
 // fingerprint itself.
 struct Pipe {
   uint32_t nf = 0, G = 0, RL = 0, r = 0;
+  uint32_t fin_slices = 1;    // work-groups per filter of the merge's finish (most regions / FIN_REG)
   uint32_t gbits = 0;         // bits of a global region index
   FDesc *d_desc = nullptr;    // nf
   FDesc one;                  // host copy of the descriptor when nf == 1
@@ -136,5 +137,8 @@ uint32_t sort_groups(uint64_t n, uint32_t chunk);
 // totals, then 256 counts per work-group (also the reduction's per-group counts)
 uint64_t sort_count_words(uint64_t cap);
 int max_region_log2(uint32_t r);
+// the merge's finish: work-group size and regions per work-group
+constexpr uint32_t FIN_NT = 256;
+constexpr uint32_t FIN_REG = 2048;
 
 }  // namespace qf

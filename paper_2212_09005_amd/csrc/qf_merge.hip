@@ -1200,21 +1200,28 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs a) {
     merge_body<T, SINGLE, false>(a, m);
 }
 
-// After the merge, one work-group per filter: sum its regions' statistics;
-// flip its current copy if none of its regions failed, else record the error
-// (all-or-nothing per filter); add its delete shortfall to not_found[f].
-// The first work-group records the launch's epoch as the pipeline's last.
-__global__ __launch_bounds__(1024) void k_finish(const FDesc *__restrict__ desc, const uint32_t *__restrict__ afil,
-                                                 const uint64_t *rstat, int del, uint64_t *not_found,
-                                                 uint64_t *pst) {
-  __shared__ uint64_t sh[4][16];
+// After the merge, per filter: work-group (f, y) sums the statistics of
+// regions [y FIN_REG, (y + 1) FIN_REG) of filter f into the filter's
+// accumulator words; the last of its work-groups (a ticket counter) takes the
+// sums, clears the words for the next launch, flips the filter's current copy
+// if none of its regions failed, else records the error (all-or-nothing per
+// filter), and adds its delete shortfall to not_found[f].  Work-group (0, 0)
+// records the launch's epoch as the pipeline's last.
+__global__ __launch_bounds__(FIN_NT) void k_finish(const FDesc *__restrict__ desc, const uint32_t *__restrict__ afil,
+                                                   const uint64_t *rstat, int del, uint64_t *not_found,
+                                                   uint64_t *pst) {
+  __shared__ uint64_t sh[4][FIN_NT / 64];
   const uint32_t f = afil ? afil[blockIdx.x] : blockIdx.x;
   const FDesc &d = desc[f];
+  const uint32_t nsl = (d.nregions + FIN_REG - 1) / FIN_REG;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) pst[ST_EPOCH] = next_epoch(pst[ST_EPOCH]);
+  if (blockIdx.y >= nsl) return;  // (the whole work-group)
   uint64_t v[4] = {0, 0, 0, 0};
   // (16-byte loads, several regions in flight per lane)
   const u32x4 *rs4 = reinterpret_cast<const u32x4 *>(rstat + 4ull * d.rbase);
+  const uint32_t r1 = min(d.nregions, (blockIdx.y + 1) * FIN_REG);
 #pragma unroll 8
-  for (uint32_t R = threadIdx.x; R < d.nregions; R += 1024) {
+  for (uint32_t R = blockIdx.y * FIN_REG + threadIdx.x; R < r1; R += FIN_NT) {
     const u32x4 a = rs4[2ull * R], b = rs4[2ull * R + 1];
     v[0] += (static_cast<uint64_t>(a[1]) << 32) | a[0];
     v[1] += (static_cast<uint64_t>(a[3]) << 32) | a[2];
@@ -1226,26 +1233,35 @@ __global__ __launch_bounds__(1024) void k_finish(const FDesc *__restrict__ desc,
     if ((threadIdx.x & 63) == 0) sh[k][threadIdx.x >> 6] = v[k];
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint64_t t[4] = {0, 0, 0, 0};
+  if (threadIdx.x != 0) return;
+  uint64_t t[4] = {0, 0, 0, 0};
+  for (int k = 0; k < 4; ++k)
+    for (int w = 0; w < FIN_NT / 64; ++w) t[k] += sh[k][w];
+  uint64_t *state = d.state;
+  if (nsl > 1) {
     for (int k = 0; k < 4; ++k)
-      for (int w = 0; w < 16; ++w) t[k] += sh[k][w];
-    uint64_t *state = d.state;
-    const uint64_t st = state[ST_BATCH];
-    if (st == 0) {
-      state[ST_USED] = t[0];
-      state[ST_DIST] += t[1];
-      state[ST_TOTAL] += t[2];
-      state[ST_CUR] ^= 1ull;
-    } else if (state[ST_ERR] == 0) {
-      state[ST_ERR] = static_cast<uint64_t>((st & BATCH_STALL) ? QF_ERR_STALLED
-                                            : (st & BATCH_FULL) ? QF_ERR_FULL
-                                                                : QF_ERR_COUNT_OVERFLOW);
-    }
-    if (del && not_found) not_found[f] += t[3];
-    state[ST_BATCHES] += 1;
-    if (blockIdx.x == 0) pst[ST_EPOCH] = next_epoch(pst[ST_EPOCH]);
+      if (t[k]) atomicAdd(reinterpret_cast<ull *>(&state[ST_ACC + k]), static_cast<ull>(t[k]));
+    __threadfence();
+    const uint64_t tk = atomicAdd(reinterpret_cast<ull *>(&state[ST_TICKET]), 1ull);
+    if (tk != nsl - 1) return;
+    // the last work-group: every other one's sums are in the words
+    __threadfence();
+    for (int k = 0; k < 4; ++k) t[k] = atomicExch(reinterpret_cast<ull *>(&state[ST_ACC + k]), 0ull);
+    (void)atomicExch(reinterpret_cast<ull *>(&state[ST_TICKET]), 0ull);
   }
+  const uint64_t st = state[ST_BATCH];
+  if (st == 0) {
+    state[ST_USED] = t[0];
+    state[ST_DIST] += t[1];
+    state[ST_TOTAL] += t[2];
+    state[ST_CUR] ^= 1ull;
+  } else if (state[ST_ERR] == 0) {
+    state[ST_ERR] = static_cast<uint64_t>((st & BATCH_STALL) ? QF_ERR_STALLED
+                                          : (st & BATCH_FULL) ? QF_ERR_FULL
+                                                              : QF_ERR_COUNT_OVERFLOW);
+  }
+  if (del && not_found) not_found[f] += t[3];
+  state[ST_BATCHES] += 1;
 }
 
 template <typename T>
@@ -1288,8 +1304,8 @@ hipError_t launch_merge_t(Pipe &p, const uint64_t *ufp, const uint64_t *ucnt, in
   } else {
     k_merge<T, false><<<nreg, NT, 0, s>>>(a);
   }
-  k_finish<<<p.nareg ? p.nafil : p.nf, 1024, 0, s>>>(p.d_desc, p.nareg ? p.d_afil : nullptr, p.rstat, del,
-                                                     not_found, p.pst);
+  k_finish<<<dim3(p.nareg ? p.nafil : p.nf, p.fin_slices), FIN_NT, 0, s>>>(
+      p.d_desc, p.nareg ? p.d_afil : nullptr, p.rstat, del, not_found, p.pst);
   if (p.timer) p.timer->end(QF_PROF_MERGE, s);
   return hipGetLastError();
 }

@@ -275,3 +275,22 @@ def test_set_invalid_indexes_among_many_keys(qs):
             assert o.insert(part) == 0
     for i, (f, o) in enumerate(zip(c.fs, c.os)):
         check_filter(f, o, f"filter {i} with invalid indexes in the batch")
+
+
+def test_set_finish_over_several_work_groups():
+    # a filter with more regions than one finish work-group sums (2^25
+    # quotients: 4096 regions, two work-groups) beside a one-region filter;
+    # the statistics words of the header must match after every batch
+    qs = [25, 12]
+    note(f"statistics summed by several work-groups, q={qs}")
+    c = SetCase(qs, 8, seed=171)
+    fid, keys = c.tagged(600_000, seed=172)
+    c.insert(fid, keys)
+    c.check_all("first batch")
+    fid2, keys2 = c.tagged(400_000, seed=173)
+    c.insert(np.concatenate([fid2, fid[:1000]]), np.concatenate([keys2, keys[:1000]]))
+    c.check_all("second batch with repeats")
+    got_nf, want_nf = c.delete(np.concatenate([fid[:5000], fid2[:100]]),
+                               np.concatenate([keys[:5000], inputs.absent_keys(174, 100)]))
+    assert np.array_equal(got_nf, want_nf)
+    c.check_all("after deletes")
