@@ -16,15 +16,26 @@ namespace {
 
 constexpr int NT = 256;
 
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+
 template <typename T>
 __device__ __forceinline__ uint64_t lookup_one(const Block<T> *__restrict__ b, int64_t nblocks,
                                                int64_t x, uint64_t rem, uint32_t r) {
   const int64_t bi = x >> 6;
   const int bit = static_cast<int>(x & 63);
-  const uint64_t occ = b[bi].occ;
+  // the home block's occupied word, run-end word and offset, requested
+  // together (one line): most runs end and start inside the home block, so
+  // the run-end words below usually come from these registers
+  const u64x2 h = *reinterpret_cast<const u64x2 *>(&b[bi]);
+  const uint32_t off = b[bi].off;
+  // (an empty asm that takes the offset keeps its load in front of the
+  // branch below, in flight with the first one, instead of after it)
+  __asm__ volatile("" : : "v"(off));
+  const uint64_t occ = h.x, rend0 = h.y;
   if (!((occ >> bit) & 1ull)) return 0;
   int d = popc64(occ & ((2ull << bit) - 2ull));  // occupied quotients in (64*bi, x]
-  const int64_t p = (bi << 6) + b[bi].off;
+  const int64_t p = (bi << 6) + off;
+  const auto rend_of = [&](int64_t w) -> uint64_t { return w == bi ? rend0 : b[w].rend; };
   int64_t e;
   if (d == 0) {
     e = p;
@@ -32,7 +43,7 @@ __device__ __forceinline__ uint64_t lookup_one(const Block<T> *__restrict__ b, i
     // d-th run end strictly after p
     int64_t w = (p + 1) >> 6;
     if (w >= nblocks) return 0;
-    uint64_t m = b[w].rend & (~0ull << ((p + 1) & 63));
+    uint64_t m = rend_of(w) & (~0ull << ((p + 1) & 63));
     for (;;) {
       const int pc = popc64(m);
       if (pc >= d) {
@@ -41,7 +52,7 @@ __device__ __forceinline__ uint64_t lookup_one(const Block<T> *__restrict__ b, i
       }
       d -= pc;
       if (++w >= nblocks) return 0;
-      m = b[w].rend;
+      m = rend_of(w);
     }
   }
   // run start: one past the last run end in [x, e-1], else x
@@ -49,7 +60,7 @@ __device__ __forceinline__ uint64_t lookup_one(const Block<T> *__restrict__ b, i
   if (e > x) {
     int64_t w = (e - 1) >> 6;
     const int64_t wx = x >> 6;
-    uint64_t m = b[w].rend & (~0ull >> (63 - ((e - 1) & 63)));
+    uint64_t m = rend_of(w) & (~0ull >> (63 - ((e - 1) & 63)));
     for (;;) {
       if (w == wx) m &= ~0ull << (x & 63);
       if (m) {
@@ -57,7 +68,8 @@ __device__ __forceinline__ uint64_t lookup_one(const Block<T> *__restrict__ b, i
         break;
       }
       if (w == wx) break;
-      m = b[--w].rend;
+      --w;
+      m = rend_of(w);
     }
   }
   struct G {
