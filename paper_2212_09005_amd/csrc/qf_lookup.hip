@@ -18,9 +18,14 @@ constexpr int NT = 256;
 
 typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// ls: null, or the lane's LDS area of 64 bytes (r = 8 only) that receives the
+// home block's slots, requested with its header: the run's slots then come
+// from LDS unless the run lies (partly) in a later block.
 template <typename T>
 __device__ __forceinline__ uint64_t lookup_one(const Block<T> *__restrict__ b, int64_t nblocks,
-                                               int64_t x, uint64_t rem, uint32_t r) {
+                                               int64_t x, uint64_t rem, uint32_t r, u32x4 *ls) {
   const int64_t bi = x >> 6;
   const int bit = static_cast<int>(x & 63);
   // the home block's occupied word, run-end word and offset, requested
@@ -28,6 +33,14 @@ __device__ __forceinline__ uint64_t lookup_one(const Block<T> *__restrict__ b, i
   // the run-end words below usually come from these registers
   const u64x2 h = *reinterpret_cast<const u64x2 *>(&b[bi]);
   const uint32_t off = b[bi].off;
+  if (sizeof(T) == 1 && ls) {
+    const u32x4 *src = reinterpret_cast<const u32x4 *>(b[bi].s);
+    const u32x4 v0 = src[0], v1 = src[1], v2 = src[2], v3 = src[3];
+    ls[0] = v0;
+    ls[1] = v1;
+    ls[2] = v2;
+    ls[3] = v3;
+  }
   // (an empty asm that takes the offset keeps its load in front of the
   // branch below, in flight with the first one, instead of after it)
   __asm__ volatile("" : : "v"(off));
@@ -74,8 +87,12 @@ __device__ __forceinline__ uint64_t lookup_one(const Block<T> *__restrict__ b, i
   }
   struct G {
     const Block<T> *b;
-    __device__ uint64_t slot(int64_t j) const { return b[j >> 6].s[j & 63]; }
-  } g{b};
+    const uint8_t *ls;
+    int64_t bi;
+    __device__ uint64_t slot(int64_t j) const {
+      return (sizeof(T) == 1 && ls && (j >> 6) == bi) ? ls[j & 63] : b[j >> 6].s[j & 63];
+    }
+  } g{b, reinterpret_cast<const uint8_t *>(ls), bi};
   int64_t pos = s;
   while (pos <= e) {
     uint64_t xr, c;
@@ -95,6 +112,9 @@ __global__ __launch_bounds__(NT) void k_lookup(const Block<T> *b0, const Block<T
                                                uint32_t q, uint32_t r, int64_t nblocks,
                                                uint8_t *__restrict__ out8,
                                                uint64_t *__restrict__ out64) {
+  // (one key at a time per lane: each lane stages its home block's slots)
+  __shared__ u32x4 stage[KPL == 1 && sizeof(T) == 1 ? NT * 4 : 1];
+  u32x4 *ls = KPL == 1 && sizeof(T) == 1 ? &stage[threadIdx.x * 4] : nullptr;
   const int cur = static_cast<int>(state[ST_CUR] & 1ull);
   const Block<T> *b = cur ? b1 : b0;
   const uint32_t p = q + r;
@@ -107,7 +127,7 @@ __global__ __launch_bounds__(NT) void k_lookup(const Block<T> *b0, const Block<T
       const uint64_t i = i0 + static_cast<uint64_t>(k) * NT;
       if (i < n) {
         const uint64_t fp = mix64(keys[i]) & pmask;
-        const uint64_t c = lookup_one(b, nblocks, static_cast<int64_t>(fp >> r), fp & rmask, r);
+        const uint64_t c = lookup_one(b, nblocks, static_cast<int64_t>(fp >> r), fp & rmask, r, ls);
         if (COUNT)
           out64[i] = c;
         else
@@ -125,6 +145,8 @@ __global__ __launch_bounds__(NT) void k_lookup_multi(const FDesc *__restrict__ d
                                                      const uint32_t *__restrict__ fid, uint64_t n,
                                                      uint8_t *__restrict__ out8, uint64_t *__restrict__ out64,
                                                      uint64_t *pst) {
+  __shared__ u32x4 stage[KPL == 1 && sizeof(T) == 1 ? NT * 4 : 1];
+  u32x4 *ls = KPL == 1 && sizeof(T) == 1 ? &stage[threadIdx.x * 4] : nullptr;
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * NT * KPL;
   for (uint64_t i0 = static_cast<uint64_t>(blockIdx.x) * NT * KPL + threadIdx.x; i0 < n; i0 += stride) {
 #pragma unroll
@@ -139,7 +161,7 @@ __global__ __launch_bounds__(NT) void k_lookup_multi(const FDesc *__restrict__ d
         const uint32_t p = d.q + d.r;
         const uint64_t fp = mix64(keys[i]) & ((1ull << p) - 1ull);
         c = lookup_one(static_cast<const Block<T> *>(cur ? d.blk[1] : d.blk[0]), d.nblocks,
-                       static_cast<int64_t>(fp >> d.r), fp & ((1ull << d.r) - 1ull), d.r);
+                       static_cast<int64_t>(fp >> d.r), fp & ((1ull << d.r) - 1ull), d.r, ls);
       } else {
         pst[ST_ERR] = static_cast<uint64_t>(static_cast<int64_t>(QF_ERR_ARG));
       }
