@@ -355,36 +355,72 @@ __global__ __launch_bounds__(NT) void k_rle_count(const uint64_t *__restrict__ s
   }
 }
 
+// The run heads of group g's chunk, in order, from output index cnt[g] (the
+// exclusive scan of k_rle_count's head counts).  A round takes RLE_K rows of
+// NT consecutive keys, all requested at once (coalesced).  A key's
+// predecessor comes from the lane before (a shuffle), across waves and rows
+// from each wave's last keys in LDS; wave ballots mark the heads, and one
+// wave scans the RLE_K x NWAVE per-wave head counts (row-major = key order).
+constexpr int RLE_K = 16;
+static_assert(RLE_K * NWAVE == 64, "one wave scans the per-wave head counts");
 __global__ __launch_bounds__(NT) void k_rle_write(const uint64_t *__restrict__ s, uint64_t n,
                                                   uint32_t G, const uint32_t *__restrict__ cnt,
                                                   uint64_t *__restrict__ ufp,
                                                   uint64_t *__restrict__ ustart) {
-  __shared__ uint32_t wsum[NWAVE];
-  __shared__ uint32_t base_s;
-  const int tid = threadIdx.x, wv = tid >> 6;
+  __shared__ uint64_t edge[RLE_K * NWAVE];  // each wave's last key of each row
+  __shared__ uint32_t wcnt[RLE_K * NWAVE];  // heads per (row, wave), then their exclusive prefix
+  __shared__ uint32_t tot_s;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const uint32_t g = blockIdx.x;
   const uint64_t lo = chunk_lo(n, G, g), hi = chunk_lo(n, G, g + 1);
-  if (tid == 0) base_s = cnt[g];
-  __syncthreads();
-  for (uint64_t r0 = lo; r0 < hi; r0 += NT) {
-    const uint64_t i = r0 + tid;
-    const bool h = i < hi && is_head(s, i);
-    const uint64_t bal = __ballot(h);
-    if ((tid & 63) == 0) wsum[wv] = static_cast<uint32_t>(popc64(bal));
-    __syncthreads();
-    uint32_t pos = base_s + static_cast<uint32_t>(popc64(bal & lanemask_lt()));
-    for (int w = 0; w < wv; ++w) pos += wsum[w];
-    if (h) {
-      ufp[pos] = s[i];
-      ustart[pos] = i;
+  const uint64_t lt = lanemask_lt();
+  uint32_t base = cnt[g];
+  for (uint64_t t0 = lo; t0 < hi; t0 += static_cast<uint64_t>(NT) * RLE_K) {
+    uint64_t v[RLE_K];
+#pragma unroll
+    for (int k = 0; k < RLE_K; ++k) {
+      const uint64_t i = t0 + static_cast<uint64_t>(k) * NT + tid;
+      v[k] = i < hi ? s[i] : 0ull;
+    }
+    const uint64_t before0 = (tid == 0 && t0 > 0) ? s[t0 - 1] : 0ull;
+    if (lane == 63) {
+#pragma unroll
+      for (int k = 0; k < RLE_K; ++k) edge[k * NWAVE + wv] = v[k];
     }
     __syncthreads();
-    if (tid == 0) {
-      uint32_t t = 0;
-      for (int w = 0; w < NWAVE; ++w) t += wsum[w];
-      base_s += t;
+    uint64_t bal[RLE_K];
+#pragma unroll
+    for (int k = 0; k < RLE_K; ++k) {
+      const uint64_t i = t0 + static_cast<uint64_t>(k) * NT + tid;
+      const uint64_t up = __shfl_up(v[k], 1);
+      uint64_t before = up;
+      if (lane == 0) before = wv ? edge[k * NWAVE + wv - 1] : (k ? edge[(k - 1) * NWAVE + NWAVE - 1] : before0);
+      const bool h = i < hi && (i == 0 || v[k] != before);
+      bal[k] = __ballot(h);
+      if (lane == 0) wcnt[k * NWAVE + wv] = static_cast<uint32_t>(popc64(bal[k]));
     }
     __syncthreads();
+    if (wv == 0) {
+      const uint32_t c = wcnt[lane];
+      uint32_t inc = c;
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(inc, o);
+        if (lane >= o) inc += t;
+      }
+      wcnt[lane] = inc - c;
+      if (lane == 63) tot_s = inc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < RLE_K; ++k) {
+      if ((bal[k] >> lane) & 1ull) {
+        const uint32_t pos = base + wcnt[k * NWAVE + wv] + static_cast<uint32_t>(popc64(bal[k] & lt));
+        ufp[pos] = v[k];
+        ustart[pos] = t0 + static_cast<uint64_t>(k) * NT + tid;
+      }
+    }
+    base += tot_s;
+    __syncthreads();  // (edge, wcnt and tot_s are rewritten by the next round)
   }
 }
 
