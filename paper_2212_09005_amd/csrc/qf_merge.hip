@@ -866,10 +866,49 @@ __device__ __forceinline__ void merge_body(const MergeArgs &a, const Smem<T> &m)
   const uint32_t r = fd.r;
   const uint64_t lmask = (1ull << (rlog + r)) - 1ull;  // fingerprint bits inside the region
   const uint32_t epoch = next_epoch(a.pst[ST_EPOCH]);
+  // the region's old runs: slots [lo_old, hi_old] (the carries at its two
+  // boundaries).  All of the region's loads below depend only on these and
+  // the words above, so they are requested before the first barrier.
+  const int64_t lo_old = qreg ? a.cb[gR] + 1 : RS;
+  const int64_t hi_old = qreg ? a.cb[gR + 1] : RS - 1;
+  const bool has_old = hi_old >= lo_old;
+  const int64_t bb = has_old ? (lo_old >> 6) : (RS >> 6);
+  const int64_t nblk64 = has_old ? (hi_old >> 6) - bb + 1 : 0;
+  // the staged path: the old runs fit in LDS (and positions in int32)
+  const bool par = ne < (1ull << 31) && nblk64 <= C::CAPW && (bb << 6) - RS < (1ll << 30);
+  const int nblk = par ? static_cast<int>(nblk64) : 0;
+  const int32_t obr = static_cast<int32_t>(par ? (bb << 6) - RS : 0);  // staged base - RS
 
-  for (int w = tid; w < nw_reg; w += NT) {
-    occ_l[w] = qreg ? gob[(RS >> 6) + w].occ : 0ull;
-    chg_l[w] = 0ull;
+  // Every lane first requests all of its staging loads (the region's
+  // occupied words, its first new entries, the old blocks' slots and run-end
+  // words), then writes them to LDS: one memory round trip instead of one per
+  // array.  (Counts per lane are bounded: at most OW <= NT occupied words,
+  // CAPW <= NT run-end words and CAPW * CH <= BCH * NT slot chunks.)
+  static_assert(C::OW <= NT && C::CAPW <= NT, "one occupied and one run-end word per lane");
+  constexpr int BCH = (C::CAPW * C::CH + NT - 1) / NT;
+  constexpr int ECH = 2;  // new entries per lane requested up front
+  const uint64_t ov = (qreg && tid < nw_reg) ? gob[(RS >> 6) + tid].occ : 0ull;
+  uint64_t ef[ECH], ec[ECH];
+#pragma unroll
+  for (int k = 0; k < ECH; ++k) {
+    const uint64_t i = static_cast<uint64_t>(tid) + static_cast<uint64_t>(k) * NT;
+    const bool ok = ne < (1ull << 31) && i < ne;
+    ef[k] = ok ? gufp[rb0 + i] : 0ull;
+    ec[k] = ok ? gucnt[rb0 + i] : 0ull;
+  }
+  u32x4 bv[BCH];
+#pragma unroll
+  for (int k = 0; k < BCH; ++k) {
+    const int idx = tid + k * NT;
+    bv[k] = u32x4{0u, 0u, 0u, 0u};
+    if (par && idx < nblk * C::CH)
+      bv[k] = reinterpret_cast<GPtr<const u32x4>>(gob[bb + idx / C::CH].s)[idx % C::CH];
+  }
+  const uint64_t rv = (par && tid < nblk) ? gob[bb + tid].rend : 0ull;
+
+  if (tid < nw_reg) {
+    occ_l[tid] = ov;
+    chg_l[tid] = 0ull;
   }
   for (int w = tid; w < C::CAPW; w += NT) new_b[w] = 0ull;
   for (int i = tid; i < C::CAP * static_cast<int>(sizeof(T)) / 16; i += NT)
@@ -886,36 +925,33 @@ __device__ __forceinline__ void merge_body(const MergeArgs &a, const Smem<T> &m)
   uint16_t *const cst = SMALL ? cst_l : a.g_st + rb0;
   Fn32 *const gaf = SMALL ? gaf_l : a.g_gaf + rb0;
   if (ne < (1ull << 31)) {
-    for (uint32_t i = tid; i < ne; i += NT) {
+#pragma unroll
+    for (int k = 0; k < ECH; ++k) {
+      const uint32_t i = static_cast<uint32_t>(tid + k * NT);
+      if (i < ne) {
+        nfp[i] = static_cast<uint32_t>(ef[k] & lmask);
+        ncnt[i] = static_cast<uint32_t>(ec[k]);
+      }
+    }
+    // (more than ECH entries per lane: the global-memory path's regions)
+    for (uint32_t i = tid + ECH * NT; i < ne; i += NT) {
       nfp[i] = static_cast<uint32_t>(gufp[rb0 + i] & lmask);
       ncnt[i] = static_cast<uint32_t>(gucnt[rb0 + i]);
     }
   }
-  __syncthreads();
-  const int64_t lo_old = qreg ? a.cb[gR] + 1 : RS;
-  const int64_t hi_old = qreg ? a.cb[gR + 1] : RS - 1;
-  const bool has_old = hi_old >= lo_old;
-  const int64_t bb = has_old ? (lo_old >> 6) : (RS >> 6);
-  const int64_t nblk64 = has_old ? (hi_old >> 6) - bb + 1 : 0;
-  // the staged path: the old runs fit in LDS (and positions in int32)
-  const bool par = ne < (1ull << 31) && nblk64 <= C::CAPW && (bb << 6) - RS < (1ll << 30);
-  const int nblk = par ? static_cast<int>(nblk64) : 0;
-  const int32_t obr = static_cast<int32_t>(par ? (bb << 6) - RS : 0);  // staged base - RS
-
-  if (par && nblk > 0) {
-    // 16-byte chunks of the staged blocks' slots, then their run-end words
-    for (int idx = tid; idx < nblk * C::CH; idx += NT) {
-      const int b = idx / C::CH, c = idx % C::CH;
-      const u32x4 v = reinterpret_cast<GPtr<const u32x4>>(gob[bb + b].s)[c];
-      reinterpret_cast<u32x4 *>(old_s + b * 64)[c] = v;
-    }
-    for (int w = tid; w < nblk; w += NT) {
-      uint64_t v = gob[bb + w].rend;
-      if (w == 0) v &= ~0ull << (lo_old & 63);
-      if (w == nblk - 1) v &= ~0ull >> (63 - (hi_old & 63));
-      old_b[w] = v;
-    }
+  // 16-byte chunks of the staged blocks' slots, then their run-end words
+#pragma unroll
+  for (int k = 0; k < BCH; ++k) {
+    const int idx = tid + k * NT;
+    if (par && idx < nblk * C::CH) reinterpret_cast<u32x4 *>(old_s)[idx] = bv[k];
   }
+  if (par && tid < nblk) {
+    uint64_t v = rv;
+    if (tid == 0) v &= ~0ull << (lo_old & 63);
+    if (tid == nblk - 1) v &= ~0ull >> (63 - (hi_old & 63));
+    old_b[tid] = v;
+  }
+  __syncthreads();
   // changed runs = groups of equal quotient among the new entries, found in
   // rounds of 2 NT entries ([2 tid, 2 tid + 2) per lane; one round unless the
   // region has more than NCAP entries)
