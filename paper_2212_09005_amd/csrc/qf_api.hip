@@ -227,19 +227,24 @@ int pipe_update(qf::Pipe &p, const uint64_t *keys, const uint32_t *fid, uint64_t
     p.nafil = nactive;
     p.nareg = static_cast<uint32_t>(p.h_areg.size());
   }
-  uint64_t *sorted = nullptr;
-  if (fid) {
-    QF_HIP(qf::launch_hash_multi(keys, fid, n, p, p.bufA, s, p.timer));
-    QF_HIP(qf::launch_sort(p.bufA, p.bufB, n, p.gbits + p.RL + p.r, p.hist, &sorted, s, p));
+  // one filter: its composite key is the fingerprint itself, and the sort
+  // hashes the keys on its first read
+  const uint32_t bits = fid ? p.gbits + p.RL + p.r : single_q + p.r;
+  const uint64_t pmask = bits >= 64 ? ~0ull : ((1ull << bits) - 1ull);
+  if (fid) QF_HIP(qf::launch_hash_multi(keys, fid, n, p, p.bufA, s, p.timer));
+  if (n <= qf::SMALL_KEYS) {
+    // small batch: sort and reduction in one work-group
+    QF_HIP(qf::launch_small_prep(fid ? p.bufA : keys, n, bits, pmask, fid == nullptr, p.bufC, p.bufD, p.pst, s,
+                                 p.timer));
   } else {
-    // one filter: its composite key is the fingerprint itself, and the first
-    // sort pass hashes the keys
-    const uint32_t bits = single_q + p.r;
-    const uint64_t pmask = bits >= 64 ? ~0ull : ((1ull << bits) - 1ull);
-    QF_HIP(qf::launch_sort(p.bufA, p.bufB, n, bits, p.hist, &sorted, s, p, keys, pmask));
+    uint64_t *sorted = nullptr;
+    if (fid)
+      QF_HIP(qf::launch_sort(p.bufA, p.bufB, n, bits, p.hist, &sorted, s, p));
+    else
+      QF_HIP(qf::launch_sort(p.bufA, p.bufB, n, bits, p.hist, &sorted, s, p, keys, pmask));
+    uint64_t *other = sorted == p.bufA ? p.bufB : p.bufA;
+    QF_HIP(qf::launch_rle(sorted, n, other, p.bufC, p.bufD, p.hist + 256, p.pst, s, p));
   }
-  uint64_t *other = sorted == p.bufA ? p.bufB : p.bufA;
-  QF_HIP(qf::launch_rle(sorted, n, other, p.bufC, p.bufD, p.hist + 256, p.pst, s, p));
   QF_HIP(qf::launch_bounds(p.bufC, p, s));
   QF_HIP(qf::launch_merge(p, p.bufC, p.bufD, del, not_found, s));
   p.batches += 1;

@@ -104,6 +104,12 @@ hipError_t launch_hash_multi(const uint64_t *keys, const uint32_t *fid, uint64_t
 hipError_t launch_sort(uint64_t *a, uint64_t *b, uint64_t n, uint32_t bits, uint32_t *hist,
                        uint64_t **result, hipStream_t s, const Pipe &p, const uint64_t *raw = nullptr,
                        uint64_t pmask = 0);
+// batches of at most SMALL_KEYS keys: sort and run-length reduction in one
+// work-group (keys hashed on load when hash is set): ufp/ucnt, count in
+// state[ST_NUNIQ]
+constexpr uint32_t SMALL_KEYS = 4096;
+hipError_t launch_small_prep(const uint64_t *in, uint64_t n, uint32_t bits, uint64_t pmask, bool hash,
+                             uint64_t *ufp, uint64_t *ucnt, uint64_t *state, hipStream_t s, Timer *t);
 // run-length reduction of the sorted keys: ufp/ucnt, count in state[ST_NUNIQ]
 hipError_t launch_rle(const uint64_t *sorted, uint64_t n, uint64_t *scratch_start,
                       uint64_t *ufp, uint64_t *ucnt, uint32_t *tile_counts, uint64_t *state,

@@ -433,6 +433,138 @@ __global__ __launch_bounds__(NT) void k_rle_counts(const uint64_t *__restrict__ 
     ucnt[j] = (j + 1 < u ? ustart[j + 1] : n) - ustart[j];
 }
 
+// Batches of at most SMALL_KEYS keys: one work-group sorts them in LDS with
+// the same LSD passes and wave-ballot ranking as the scatter (the keys stay in
+// registers between passes and go through LDS only to be reordered), then
+// reduces runs of equal keys, writing the distinct keys, their counts and
+// their number (state[ST_NUNIQ]).  One launch instead of three per radix pass
+// and four for the reduction, which dominate small updates.  With HASH the
+// input is raw keys and the sorted value is mix64(key) & pmask.
+template <bool HASH>
+__global__ __launch_bounds__(NT) void k_small_prep(const uint64_t *__restrict__ in, uint32_t n, uint32_t bits,
+                                                   uint64_t pmask, uint64_t *__restrict__ ufp,
+                                                   uint64_t *__restrict__ ucnt, uint64_t *state) {
+  constexpr int KPL = SMALL_KEYS / NT;    // rounds of 64 keys per wave
+  constexpr int WQ = SMALL_KEYS / NWAVE;  // keys per wave
+  static_assert(NWAVE * KPL == 64, "one wave scans the per-(wave, round) head counts");
+  static_assert(RADIX_MAX == NT, "one digit per lane");
+  __shared__ uint64_t tile[SMALL_KEYS];
+  __shared__ uint32_t wc[NWAVE][RADIX_MAX];
+  __shared__ uint32_t sh[NWAVE];
+  __shared__ uint32_t rowc[NWAVE * KPL];
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const uint64_t below = (1ull << lane) - 1ull;
+  // key k of a lane has index wv WQ + 64 k + lane (wave-major, then round)
+  uint64_t key[KPL];
+#pragma unroll
+  for (int k = 0; k < KPL; ++k) {
+    const uint32_t j = wv * WQ + k * 64 + lane;
+    key[k] = j < n ? (HASH ? (mix64(in[j]) & pmask) : in[j]) : 0ull;
+  }
+  const uint32_t npass = (bits + RADIX_BITS - 1) / RADIX_BITS;
+  const uint32_t db = npass ? (bits + npass - 1) / npass : 0;
+  for (uint32_t p = 0; p < npass; ++p) {
+    const uint32_t shift = db * p;
+    const uint32_t nb = bits - shift < db ? bits - shift : db;
+    const uint32_t dmask = (1u << nb) - 1u;
+    for (int w = 0; w < NWAVE; ++w) wc[w][tid] = 0;
+    __syncthreads();
+    // 1. rank inside each wave, round by round
+    uint32_t rk[KPL];
+#pragma unroll
+    for (int k = 0; k < KPL; ++k) {
+      const uint32_t j = wv * WQ + k * 64 + lane;
+      const bool valid = j < n;
+      const uint32_t d = static_cast<uint32_t>(key[k] >> shift) & dmask;
+      uint64_t peers = __ballot(valid);
+      for (uint32_t b = 0; b < nb; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bal = __ballot(bit);
+        peers &= bit ? bal : ~bal;
+      }
+      const uint32_t before = valid ? wc[wv][d] : 0u;
+      const uint32_t r = static_cast<uint32_t>(popc64(peers & below));
+      rk[k] = before + r;
+      // (the wave's lanes read the counter before its first lane of the
+      // digit writes it: a wave's LDS accesses complete in program order)
+      if (valid && r == 0) wc[wv][d] = before + static_cast<uint32_t>(popc64(peers));
+    }
+    __syncthreads();
+    // 2. digit starts, then each wave's first position per digit
+    {
+      uint32_t v[1], ex[1];
+      uint32_t t = 0;
+      for (int w = 0; w < NWAVE; ++w) t += wc[w][tid];
+      v[0] = t;
+      digits_exscan<1>(v, ex, sh);
+      uint32_t run = ex[0];
+      for (int w = 0; w < NWAVE; ++w) {
+        const uint32_t c = wc[w][tid];
+        wc[w][tid] = run;
+        run += c;
+      }
+    }
+    __syncthreads();
+    // 3. reorder through LDS
+#pragma unroll
+    for (int k = 0; k < KPL; ++k) {
+      const uint32_t j = wv * WQ + k * 64 + lane;
+      if (j < n) {
+        const uint32_t d = static_cast<uint32_t>(key[k] >> shift) & dmask;
+        tile[wc[wv][d] + rk[k]] = key[k];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < KPL; ++k) {
+      const uint32_t j = wv * WQ + k * 64 + lane;
+      key[k] = j < n ? tile[j] : 0ull;
+    }
+  }
+  // the sorted keys are in tile and, by index, in the lanes' registers:
+  // run heads by wave ballots, their order by one wave's scan of the
+  // per-(wave, round) counts
+  uint64_t hb[KPL];
+#pragma unroll
+  for (int k = 0; k < KPL; ++k) {
+    const uint32_t j = wv * WQ + k * 64 + lane;
+    const bool h = j < n && (j == 0 || key[k] != tile[j - 1]);
+    hb[k] = __ballot(h);
+    if (lane == 0) rowc[wv * KPL + k] = static_cast<uint32_t>(popc64(hb[k]));
+  }
+  __syncthreads();
+  if (wv == 0) {
+    const uint32_t c = rowc[lane];
+    uint32_t inc = c;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t t = __shfl_up(inc, o);
+      if (lane >= o) inc += t;
+    }
+    rowc[lane] = inc - c;
+    if (lane == 63) sh[0] = inc;
+  }
+  __syncthreads();
+  const uint32_t nu = sh[0];
+  // each head's position, in head order, over the (no longer needed) tile
+  uint32_t *const start = reinterpret_cast<uint32_t *>(tile);
+  uint32_t ui[KPL];
+#pragma unroll
+  for (int k = 0; k < KPL; ++k) {
+    ui[k] = rowc[wv * KPL + k] + static_cast<uint32_t>(popc64(hb[k] & below));
+    if ((hb[k] >> lane) & 1ull) start[ui[k]] = wv * WQ + k * 64 + lane;
+  }
+  if (tid == 0) start[nu] = n;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < KPL; ++k) {
+    if ((hb[k] >> lane) & 1ull) {
+      ufp[ui[k]] = key[k];
+      ucnt[ui[k]] = start[ui[k] + 1] - start[ui[k]];
+    }
+  }
+  if (tid == 0) state[ST_NUNIQ] = nu;
+}
+
 // Successor search (Sec. 5.3): rb[g] = first reduced entry whose (composite)
 // key is >= the first key of region g, for the G regions of a pipeline.
 __global__ __launch_bounds__(NT) void k_bounds(const uint64_t *__restrict__ ufp,
@@ -550,6 +682,17 @@ hipError_t launch_sort(uint64_t *a, uint64_t *b, uint64_t n, uint32_t bits, uint
     out = tmp;
   }
   *result = in;
+  return hipGetLastError();
+}
+
+hipError_t launch_small_prep(const uint64_t *in, uint64_t n, uint32_t bits, uint64_t pmask, bool hash,
+                             uint64_t *ufp, uint64_t *ucnt, uint64_t *state, hipStream_t s, Timer *t) {
+  if (t) t->begin(QF_PROF_SORT_SCATTER, s);
+  if (hash)
+    k_small_prep<true><<<1, NT, 0, s>>>(in, static_cast<uint32_t>(n), bits, pmask, ufp, ucnt, state);
+  else
+    k_small_prep<false><<<1, NT, 0, s>>>(in, static_cast<uint32_t>(n), bits, pmask, ufp, ucnt, state);
+  if (t) t->end(QF_PROF_SORT_SCATTER, s);
   return hipGetLastError();
 }
 

@@ -321,7 +321,7 @@ def test_launch_timer_kind_selection():
     qf = _qf()
     f = qf.CQF(q, r)
     o = oqf.OracleQF(q, r)
-    keys = inputs.uniform_keys(5, 6000)
+    keys = inputs.uniform_keys(5, 8000)
     assert qf.qf_profile_enable(f.h, True, kinds=("merge", "lookup")) == 0
     f.insert(dev(keys[:3000]))
     f.query(dev(keys))
@@ -330,13 +330,19 @@ def test_launch_timer_kind_selection():
     assert all(prof[k][1] == 0 for k in prof if k not in ("merge", "lookup"))
     assert prof["merge"][0] > 0.0
     assert qf.qf_profile_enable(f.h, True) == 0  # every kind
+    # more keys than one work-group sorts: radix passes and the reduction
     f.insert(dev(keys[3000:]))
     prof = qf.qf_profile_read(f.h)
     assert prof["merge"][1] == 1 and prof["sort_scatter"][1] >= 1 and prof["reduce"][1] == 1
     assert prof["lookup"][1] == 0
+    # a small batch: one sort-and-reduce launch, counted as a scatter
+    f.insert(dev(keys[:100]))
+    prof = qf.qf_profile_read(f.h)
+    assert prof["sort_scatter"][1] == 1 and prof["sort_hist"][1] == 0 and prof["reduce"][1] == 0
     assert qf.qf_profile_enable(f.h, False) == 0
     f.insert(dev(keys[:10]))
     assert all(n == 0 for _, n in qf.qf_profile_read(f.h).values())
     o.insert(keys)
+    o.insert(keys[:100])
     o.insert(keys[:10])
     export_ok(f, o.export(), "after timed and untimed batches")
