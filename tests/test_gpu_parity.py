@@ -346,3 +346,30 @@ def test_launch_timer_kind_selection():
     o.insert(keys[:100])
     o.insert(keys[:10])
     export_ok(f, o.export(), "after timed and untimed batches")
+
+
+@pytest.mark.parametrize("r", [8, 16])
+def test_batches_around_the_one_group_sort_limit(r):
+    # 4096 keys are sorted and reduced by one work-group, 4097 by the radix
+    # passes; both sides of the limit, with heavy duplicates and deletes
+    q = 16
+    note(f"batches of 4095/4096/4097 keys, r={r}")
+    qf = _qf()
+    rng = np.random.Generator(np.random.PCG64(4096 + r))
+    base = inputs.uniform_keys(90 + r, 20000)
+    f = qf.CQF(q, r)
+    m = Model(q, r)
+    for i, sz in enumerate((4096, 4097, 4095, 4096)):
+        keys = base[rng.integers(0, 3000 if i % 2 else len(base), sz)]
+        f.insert(dev(keys))
+        m.insert(keys)
+        export_ok(f, m.layout(), f"after insert batch {i} ({sz} keys)")
+    for i, sz in enumerate((4096, 4097)):
+        keys = np.concatenate([base[rng.integers(0, 5000, sz - 50)], inputs.absent_keys(91 + i, 50)])
+        nf = torch.zeros(1, dtype=torch.int64, device="cuda")
+        f.delete(dev(keys), nf)
+        short = m.delete(keys)
+        assert int(host(nf)[0]) == int(short), f"delete batch {i}: not-found tally"
+        export_ok(f, m.layout(), f"after delete batch {i} ({sz} keys)")
+    probe = np.concatenate([base[:4000], inputs.absent_keys(93, 4000)])
+    assert np.array_equal(host(f.count(dev(probe))), m.counts(probe))
