@@ -49,7 +49,9 @@ def load_constants(w) -> dict | None:
 
 
 def algorithmic_bytes(kind: str, w, consts: dict | None, lookup_count_share: float) -> float | None:
-    """Bytes the method itself must move per launch of `kind` (roofline section)."""
+    """Bytes the method itself must move per launch of `kind`: a merge reads and writes each
+    changed block once (at its information-theoretic size) and reads its distinct entries; a
+    lookup reads its keys, writes its results and reads each distinct block it touches."""
     m = w.batch
     Bb = 64 * (w.r + 2) // 8 + 1
     if kind == "hash":

@@ -16,7 +16,7 @@ algorithm:
     quotient order, each as far left as possible but not left of its quotient.
   * Sec. 5.3: remainders inside a run are sorted.
   * Sec. 5.4: equal fingerprints are one <item, count> entry.
-Together with the readings listed in the design doc (SplitMix64 finalizer, low p
+Together with the readings taken where the paper is silent (SplitMix64 finalizer, low p
 bits, CQF-style counter encoding, no wrap-around, 10*sqrt(2^q) extra slots,
 offsets per 64-slot block), the table is a pure function of the multiset; this
 module builds it directly: run ends satisfy

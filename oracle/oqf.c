@@ -5,7 +5,7 @@
  * against.  Only tests/, __graft_entry__.smoke() and the cpu_baseline leg of
  * bench.py may load it.  It shares no code, header, table or constant with
  * the HIP library (paper_2212_09005_amd/csrc); the two are written
- * independently from the paper and from the readings listed in the design doc.
+ * independently from the paper and from the readings below where it is silent.
  *
  * What it follows (McCoy, Hofmeyr, Yelick, Pandey, "High-Performance Filters
  * for GPUs", PPoPP'23):
@@ -22,7 +22,7 @@
  * The paper does not print the counter encoding, the metadata layout, the
  * hash or the table end; the readings used here (canonical layout, SplitMix64
  * finalizer, low p bits, CQF-style counter encoding, 10*sqrt(2^q) overflow
- * slots, per-64-slot offsets) are the ones listed in the design doc.
+ * slots, per-64-slot offsets) are written out in full in this file.
  *
  * The algorithm is deliberately naive: every unit update decodes the whole
  * cluster around the target quotient into a list of (quotient, remainder,
