@@ -373,3 +373,36 @@ def test_batches_around_the_one_group_sort_limit(r):
         export_ok(f, m.layout(), f"after delete batch {i} ({sz} keys)")
     probe = np.concatenate([base[:4000], inputs.absent_keys(93, 4000)])
     assert np.array_equal(host(f.count(dev(probe))), m.counts(probe))
+
+
+def test_load_sweep_to_095_at_the_bench_ratio():
+    # the bench's batch-to-table ratio (2^22 keys per 2^28 slots) at 2^20
+    # slots: batches of 2^14 uniform keys up to load 0.95, the table exact
+    # after every fifth batch and at the end, then one bench step (insert,
+    # query, count, delete) at load 0.95 checked against the oracle
+    q, r = 20, 8
+    note("load sweep to 0.95, q=20, batches of 2^14")
+    qf = _qf()
+    f = qf.CQF(q, r)
+    o = oqf.OracleQF(q, r)
+    batch = 1 << 14
+    fill = inputs.uniform_keys(2095, int(0.95 * (1 << q)))
+    parts = [fill[s:s + batch] for s in range(0, len(fill), batch)]
+    for i, part in enumerate(parts):
+        f.insert(dev(part))
+        assert o.insert(part) == 0
+        if i % 5 == 4 or i == len(parts) - 1:
+            export_ok(f, o.export(), f"after batch {i} (load {(i + 1) * batch / (1 << q):.3f})")
+    ins = inputs.uniform_keys(2096, batch)
+    f.insert(dev(ins))
+    assert o.insert(ins) == 0
+    export_ok(f, o.export(), "after the step's insert at load 0.95")
+    qk = inputs.mixed_queries(2097, fill, batch // 2, batch - batch // 2)
+    want = o.count(qk)
+    assert np.array_equal(host(f.count(dev(qk))), want)
+    assert np.array_equal(host(f.query(dev(qk))), (want > 0).astype(np.uint8))
+    nf = torch.zeros(1, dtype=torch.int64, device="cuda")
+    f.delete(dev(ins), nf)
+    rc, short = o.delete(ins)
+    assert rc == 0 and int(host(nf)[0]) == short == 0
+    export_ok(f, o.export(), "after the step's delete")
