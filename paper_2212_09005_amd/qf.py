@@ -493,6 +493,12 @@ class CQFSet:
     def sync(self, stream=None) -> int:
         return qf_set_sync(self.h, stream)
 
+    def errors(self, stream=None) -> tuple[int, np.ndarray]:
+        """Waits for `stream`; (number of filters with a deferred error, each filter's code), cleared."""
+        codes = np.zeros(len(self.filters), dtype=np.int32)
+        n = lib().qf_set_errors(self.h, codes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _stream(stream))
+        return int(n), codes
+
     def info(self) -> dict:
         return qf_set_info(self.h)
 

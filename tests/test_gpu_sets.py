@@ -294,3 +294,29 @@ def test_set_finish_over_several_work_groups():
                                np.concatenate([keys[:5000], inputs.absent_keys(174, 100)]))
     assert np.array_equal(got_nf, want_nf)
     c.check_all("after deletes")
+
+
+def test_set_errors_info_and_reserve():
+    # per-filter deferred errors name the filter that overflowed and are
+    # cleared by the read; the set's info and a reserved scratch hold
+    qf = _qf()
+    qs = [6, 12, 10]
+    note("set errors, info, reserve")
+    c = SetCase(qs, 8, seed=301)
+    c.set.reserve(50_000)
+    info = c.set.info()
+    assert info["nf"] == 3 and info["r"] == 8
+    assert info["regions"] >= len(qs) and info["device_bytes"] > 0
+    # filter 0 (64 quotients + 80 extra slots) receives 400 distinct keys
+    fid = np.concatenate([np.zeros(400, np.int32), np.ones(2000, np.int32), np.full(500, 2, np.int32)])
+    keys = inputs.uniform_keys(302, len(fid), distinct=True)
+    c.set.insert(dev_fid(fid), dev(keys))
+    n, codes = c.set.errors()
+    assert n == 1 and int(codes[0]) == qf.QF_ERR_FULL and int(codes[1]) == 0 and int(codes[2]) == 0
+    n, codes = c.set.errors()
+    assert n == 0 and not codes.any()
+    for i in (1, 2):
+        assert c.os[i].insert(keys[fid == i]) == 0
+    for i, (f, o) in enumerate(zip(c.fs, c.os)):
+        check_filter(f, o, f"after a partial overflow, filter {i}")
+    assert c.set.info()["batches"] == 1
