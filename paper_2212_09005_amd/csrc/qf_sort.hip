@@ -103,9 +103,22 @@ __global__ __launch_bounds__(NT) void k_rs_hist(const uint64_t *__restrict__ in,
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      if (i0 + static_cast<uint64_t>(k) * NT < hi) {
-        const uint64_t x = HASH ? (mix64(v[k]) & pmask) : v[k];
-        atomicAdd(&h[wv][static_cast<uint32_t>(x >> shift) & dmask], 1u);
+      const bool valid = i0 + static_cast<uint64_t>(k) * NT < hi;
+      const uint64_t x = HASH ? (mix64(v[k]) & pmask) : v[k];
+      const uint32_t d = static_cast<uint32_t>(x >> shift) & dmask;
+      // Skewed keys put many lanes of a wave on one digit, and LDS atomics
+      // on one address serialise: the lanes that share the first valid
+      // lane's digit are counted by one atomic of that lane.
+      const uint64_t act = __ballot(valid);
+      if (act) {
+        const uint32_t d0 = static_cast<uint32_t>(__shfl(static_cast<int>(d), __builtin_ctzll(act)));
+        const uint64_t same = __ballot(valid && d == d0);
+        if (valid && d == d0) {
+          if ((same & ((1ull << (threadIdx.x & 63)) - 1ull)) == 0)
+            atomicAdd(&h[wv][d0], static_cast<uint32_t>(popc64(same)));
+        } else if (valid) {
+          atomicAdd(&h[wv][d], 1u);
+        }
       }
     }
   }
