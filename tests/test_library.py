@@ -7,6 +7,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import struct
 import subprocess
 
 import pytest
@@ -33,11 +34,30 @@ def test_every_declared_symbol_is_exported():
     assert set(qf.declared_functions()) <= exported
 
 
+def _offload_targets(path):
+    """Target ids of the device code bundled in a HIP library: clang's offload
+    bundle starts with a 24-byte magic, then a u64 entry count, then per entry
+    u64 offset, u64 size, u64 id length and the id text."""
+    data = open(path, "rb").read()
+    at = data.find(b"__CLANG_OFFLOAD_BUNDLE__")
+    assert at >= 0, "no offload bundle in the library"
+    o = at + 24
+    (n,) = struct.unpack_from("<Q", data, o)
+    o += 8
+    ids = []
+    for _ in range(n):
+        _off, size, idlen = struct.unpack_from("<QQQ", data, o)
+        o += 24
+        ids.append((data[o:o + idlen].decode(), size))
+        o += idlen
+    return ids
+
+
 def test_library_is_built_for_gfx950():
-    out = subprocess.run(["/opt/rocm/bin/roc-obj-ls", qf.LIB_PATH], capture_output=True, text=True)
-    if out.returncode != 0:
-        pytest.skip("roc-obj-ls unavailable")
-    assert "gfx950" in out.stdout
+    ids = _offload_targets(qf.LIB_PATH)
+    device = [(i, size) for i, size in ids if i.startswith("hip")]
+    # one device code object, for gfx950 only, and not empty
+    assert len(device) == 1 and device[0][0].endswith("--gfx950") and device[0][1] > 0, ids
 
 
 def test_argument_errors_return_before_the_device():
