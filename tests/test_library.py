@@ -9,6 +9,7 @@ import ctypes
 import os
 import struct
 import subprocess
+import sys
 
 import pytest
 
@@ -94,3 +95,35 @@ def test_table_bytes():
     assert qf.qf_table_bytes(28, 8) == ((1 << 28) + 163840) // 64 * 128
     assert qf.qf_table_bytes(30, 16) == ((1 << 30) + 327680) // 64 * 160
     assert qf.qf_table_bytes(5, 8) == 0
+
+
+def _run_py(code):
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    return subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120, cwd=root)
+
+
+def test_missing_library_fails_loudly():
+    # with the library path pointing nowhere, the first call raises: there is
+    # no other implementation to fall back to
+    out = _run_py(
+        "from paper_2212_09005_amd import qf\n"
+        "qf.LIB_PATH = '/nonexistent/libqf.so'\n"
+        "qf._lib = None\n"
+        "try:\n"
+        "    qf.lib()\n"
+        "except ImportError as e:\n"
+        "    print('raised:', e)\n"
+    )
+    assert out.returncode == 0, out.stderr
+    assert "raised:" in out.stdout and "no fallback" in out.stdout
+
+
+def test_package_does_not_load_the_oracle():
+    out = _run_py(
+        "import sys\n"
+        "import paper_2212_09005_amd\n"
+        "from paper_2212_09005_amd import qf, inputs, workloads\n"
+        "print(sorted(m for m in sys.modules if m == 'oracle' or m.startswith('oracle.')))\n"
+    )
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "[]"
