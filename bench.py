@@ -9,9 +9,10 @@ delete the inserted batch -- which returns the table to load 0.9.  Inputs are
 resident in HBM before the timed region.
 
 Prints one JSON line: aggregate ops/s over the step (value), the per-operation
-rates, the roofline of the dominant kernel measured with HIP events on its
-launch stream, and the CPU oracle timed on a bounded sample of the same
-workload.
+rates (insert and query from events between the operations of the timed
+steps), the roofline of the dominant kernel measured with HIP events on its
+launch stream, beside the attainable bandwidth of a device-to-device copy, and
+the CPU oracle timed on a bounded sample of the same step at the same size.
 """
 from __future__ import annotations
 
@@ -89,47 +90,82 @@ def measured_traffic(kernel: str) -> float | None:
     return float(rec["bytes"])
 
 
-def cpu_baseline(w, budget_s: float = 20.0) -> dict:
-    """The CPU oracle (single thread) on the same step at a smaller table with
-    the same load and the same batch-to-table ratio."""
-    from oracle import oqf
-    from paper_2212_09005_amd import inputs
+def host_cpu() -> dict:
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "model": model}
 
-    q = 20
-    scale = 1 << (w.q - q)
-    m = max(w.batch // scale, 1)
-    f = oqf.OracleQF(q, w.r)
-    fill = inputs.uniform_keys(w.fill_seed, int(w.load * (1 << q)))
+
+def cpu_baseline(w, fill: np.ndarray, budget_s: float = 20.0, m: int = 1 << 18) -> dict:
+    """The CPU oracle (oracle/oqf.c, one thread, as it stands) on the headline step at the headline
+    size: the table of the same fill keys (built by the definition oracle and loaded, not timed),
+    then steps of insert / query / count / delete with batches of m keys of the same streams
+    (the first m keys of each step's batch), for about budget_s seconds."""
+    from oracle import brute, oqf
+
     t0 = time.perf_counter()
-    for part in np.array_split(fill, 16):
-        assert f.insert(part) == 0
-    t_fill = time.perf_counter() - t0
-    ops = 0
+    ms = brute.multiset(brute.fingerprints(fill, w.q, w.r))
+    o = oqf.OracleQF(w.q, w.r)
+    o.load(brute.layout(ms[0], ms[1], w.q, w.r))
+    del ms
+    t_load = time.perf_counter() - t0
+    op_s = np.zeros(4)
     steps = 0
-    t0 = time.perf_counter()
     while True:
-        ins = inputs.uniform_keys(1000 + steps, m)
-        qk = inputs.mixed_queries(2000 + 10 * steps, fill, m // 2, m - m // 2)
-        assert f.insert(ins) == 0
-        f.query(qk)
-        f.count(qk)
-        rc, nf = f.delete(ins)
-        assert rc == 0
-        ops += 4 * m
+        ins = w.insert_keys(steps)[:m]
+        qk = w.query_keys(steps, fill)[:m]
+        t = [time.perf_counter()]
+        assert o.insert(ins) == 0
+        t.append(time.perf_counter())
+        o.query(qk)
+        t.append(time.perf_counter())
+        o.count(qk)
+        t.append(time.perf_counter())
+        rc, nf = o.delete(ins)
+        t.append(time.perf_counter())
+        assert rc == 0 and nf == 0
+        op_s += np.diff(t)
         steps += 1
-        if time.perf_counter() - t0 > budget_s * 0.5 or steps >= 64:
+        if op_s.sum() > budget_s or steps >= 64:
             break
-    dt = time.perf_counter() - t0
+    total = float(op_s.sum())
+    rates = {k: round(float(m * steps / op_s[i] / 1e9), 6)
+             for i, k in enumerate(("insert", "query", "count", "delete"))}
     return {
-        "value": ops / dt / 1e9,
+        "value": round(4 * m * steps / total / 1e9, 6),
         "unit": "B ops/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"oracle/oqf.c (sequential CQF, 1 thread) at q={q}, r={w.r}, load {w.load}: {steps} steps of "
-                   f"insert/query/count/delete with batches of {m} keys (same batch/table ratio); "
-                   f"fill not timed ({t_fill:.1f}s)"),
-        "ops_per_s": ops / dt,
+        "sample": (f"oracle/oqf.c (sequential CQF, 1 thread) on the headline table (q={w.q}, r={w.r}, load {w.load}, "
+                   f"loaded from the definition layout in {t_load:.0f}s, not timed): {steps} steps of insert / "
+                   f"query / count / delete of {m} keys each (every insert also snapshots the table for "
+                   f"all-or-nothing)"),
+        "rates_Bps": rates,
+        "host": host_cpu(),
     }
+
+
+def copy_bandwidth(torch, nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """Attainable HBM bandwidth: a device-to-device copy of nbytes (read + write), GB/s, best of reps."""
+    src = torch.ones(nbytes // 8, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = 0.0
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        torch.cuda.synchronize()
+        best = max(best, 2 * nbytes / (a.elapsed_time(b) * 1e-3) / 1e9)
+    del src, dst
+    return round(best, 1)
 
 
 def bench_sets(args) -> dict:
@@ -143,25 +179,17 @@ def bench_sets(args) -> dict:
 
     from paper_2212_09005_amd import inputs, qf
 
-    rng = np.random.Generator(np.random.PCG64(5))
-    nf = args.sets_filters
-    qs = rng.integers(10, 21, size=nf)
-    fill_n = np.array([int(0.85 * (1 << int(q))) for q in qs], dtype=np.int64)
-    off = np.concatenate([[0], np.cumsum(fill_n)])
+    from paper_2212_09005_amd.workloads import ManyFilters
+
+    wl = ManyFilters(nf=args.sets_filters, query_log2=args.sets_query_log2)
+    b = wl.build()
+    nf, qs, fill_n, off, keys, fid = wl.nf, b["qs"], b["fill_n"], b["off"], b["keys"], b["fid"]
     total = int(off[-1])
     log(f"c4: {nf} filters, {total} fill keys, {int(sum(1 << int(q) for q in qs))} quotients")
-    keys = inputs.uniform_keys(5, total)
-    fid = np.repeat(np.arange(nf, dtype=np.int32), fill_n)
     d_keys = torch.from_numpy(keys.view(np.int64)).to("cuda")
     d_fid = torch.from_numpy(fid).to("cuda")
-    # queries: filter drawn in proportion to 2^q, half present, half absent
     m = 1 << args.sets_query_log2
-    w = np.array([2.0 ** int(q) for q in qs])
-    qfid = rng.choice(nf, size=m, p=w / w.sum()).astype(np.int32)
-    present = rng.random(m) < 0.5
-    qkeys = inputs.absent_keys(6, m)
-    pidx = off[qfid] + (rng.random(m) * fill_n[qfid]).astype(np.int64)
-    qkeys[present] = keys[pidx[present]]
+    qfid, qkeys, present, rng = b["qfid"], b["qkeys"], b["present"], b["rng"]
     d_qkeys = torch.from_numpy(qkeys.view(np.int64)).to("cuda")
     d_qfid = torch.from_numpy(qfid).to("cuda")
     # the per-filter loop gets its queries already grouped by filter (untimed)
@@ -273,7 +301,7 @@ def bench_sets(args) -> dict:
         "higher_is_better": True,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": f"c4_sets_{nf}filters_q10to20_r8_load0.85", "filters": nf, "fill_keys": total,
+        "config": {"workload": wl.name(), "filters": nf, "fill_keys": total,
                    "queries": m},
         "tuned_graph": {"fill_s": round(t_g_fill, 4), "fill_Bps": round(total / t_g_fill / 1e9, 4),
                         "query_ms": round(t_g_query * 1e3, 3), "query_Bps": round(m / t_g_query / 1e9, 4),
@@ -348,12 +376,13 @@ def bench_zipf(args) -> dict:
 
     from paper_2212_09005_amd import inputs, qf
 
+    from paper_2212_09005_amd.workloads import Counting
+
     sc = args.zipf_scale
-    q, r = 30 - sc, 16
-    n = int(0.9 * (1 << q))
-    universe = 1 << (28 - sc)
+    wl = Counting(q=30 - sc, universe_log2=28 - sc, count_log2=26 - sc)
+    q, r, n, universe = wl.q, wl.r, wl.n, wl.universe
     t0 = time.time()
-    keys = inputs.zipf_keys(3, n, 1.1, universe)
+    keys = inputs.rank_to_key(wl.ranks())
     log(f"zipf: {n} instances generated in {time.time() - t0:.1f}s")
     f = qf.CQF(q, r)
     f.reserve(n)
@@ -365,9 +394,8 @@ def bench_zipf(args) -> dict:
     t_ins = time.perf_counter() - t0
     rc = f.sync()
     assert rc == 0, f"insert failed {rc}"
-    mc = 1 << (26 - sc)
-    ranks = np.random.Generator(np.random.PCG64(4)).integers(1, universe + 1, size=mc)
-    ck = inputs.rank_to_key(ranks)
+    ck = inputs.rank_to_key(wl.count_ranks())
+    mc = len(ck)
     dc = torch.from_numpy(ck.view(np.int64)).to("cuda")
     cout = torch.empty(mc, dtype=torch.int64, device="cuda")
     f.count(dc, cout)
@@ -376,7 +404,7 @@ def bench_zipf(args) -> dict:
     f.count(dc, cout)
     torch.cuda.synchronize()
     t_cnt = time.perf_counter() - t0
-    dk = keys[inputs.bernoulli_mask(5, n, 0.25)]
+    dk = keys[wl.delete_mask()]
     ddel = torch.from_numpy(dk.view(np.int64)).to("cuda")
     nf = torch.zeros(1, dtype=torch.int64, device="cuda")
     torch.cuda.synchronize()
@@ -389,7 +417,7 @@ def bench_zipf(args) -> dict:
     f.close()
     return {"metric": "counting insert / count / delete throughput with Zipf(1.1) keys", "value": round(n / t_ins / 1e9, 4),
             "unit": "B inserts/s", "n_gpus": 1, "higher_is_better": True, "dtype": "u64", "data": "synthetic",
-            "config": {"workload": f"cqf_q{q}_r16_zipf1.1_universe2^{28 - sc}_one_batch", "q": q, "r": r,
+            "config": {"workload": wl.name(), "q": q, "r": r,
                        "instances": n, "count_keys": mc, "delete_instances": int(len(dk))},
             "insert_Bps": round(n / t_ins / 1e9, 4), "count_Bps": round(mc / t_cnt / 1e9, 4),
             "delete_Bps": round(len(dk) / t_del / 1e9, 4), "device_bytes": info["device_bytes"]}
@@ -447,15 +475,14 @@ def bench_serve(args) -> dict:
 
     from paper_2212_09005_amd import inputs, qf
 
-    rng = np.random.Generator(np.random.PCG64(55))
-    nf = args.serve_filters
-    qs = rng.integers(18, 27, size=nf)
-    rs = np.where(rng.random(nf) < 0.5, 8, 16)
+    from paper_2212_09005_amd.workloads import Serving
+
+    wl = Serving(nf=args.serve_filters)
+    nf = wl.nf
+    qs, rs = wl.filters()
     srv = qf.Server(64 << 30, max_round_keys=1 << 22)
     ids = [srv.open(int(q), int(r)) for q, r in zip(qs, rs)]
-    cap_keys = np.array([int(0.95 * (1 << int(q))) for q in qs])
-    fill = [inputs.uniform_keys(7000 + i, int(0.5 * (1 << int(q)))) for i, q in enumerate(qs)]
-    count = np.array([len(k) for k in fill])
+    fill = wl.fill_keys(qs)
     tag = 0
     for i, k in enumerate(fill):
         for a in range(0, len(k), 1 << 22):
@@ -464,39 +491,12 @@ def bench_serve(args) -> dict:
     got = 0
     while got < tag:
         got += len(srv.poll(4096, 100000))
-    log(f"serve: {nf} filters filled to 0.5 ({int(count.sum())} keys)")
-    pool = np.concatenate(fill)
-    pool_off = np.concatenate([[0], np.cumsum(count)])
+    log(f"serve: {nf} filters filled to {wl.load0} ({sum(len(k) for k in fill)} keys)")
+    # per-filter key counts and delete cursors, carried across the request streams
+    state = {"count": np.array([len(k) for k in fill], dtype=np.int64), "dcur": np.zeros(nf, np.int64)}
 
     def make_requests(nreq, seed):
-        g = np.random.Generator(np.random.PCG64(seed))
-        ops = g.choice(3, size=nreq, p=[0.70, 0.25, 0.05])
-        sizes = np.floor(2.0 ** g.uniform(0, 16, size=nreq)).astype(np.int64)
-        fids = g.integers(0, nf, size=nreq)
-        reqs = []
-        for k in range(nreq):
-            f, n = int(fids[k]), int(sizes[k])
-            if ops[k] == 1:  # insert, rerouted when the filter would pass load 0.95
-                if count[f] + n > cap_keys[f]:
-                    room = np.nonzero(count + n <= cap_keys)[0]
-                    if len(room) == 0:
-                        ops[k] = 0
-                    else:
-                        f = int(room[g.integers(0, len(room))])
-                if ops[k] == 1:
-                    keys = inputs.uniform_keys(seed * 1_000_003 + k, n)
-                    count[f] += n
-                    reqs.append((qf.QFS_INSERT, f, keys))
-                    continue
-            if ops[k] == 2:  # delete present keys
-                keys = pool[pool_off[f] + g.integers(0, pool_off[f + 1] - pool_off[f], size=n)]
-                reqs.append((qf.QFS_DELETE, f, keys))
-                continue
-            half = n // 2
-            keys = np.concatenate([pool[pool_off[f] + g.integers(0, pool_off[f + 1] - pool_off[f], size=n - half)],
-                                   inputs.absent_keys(seed * 7 + k, half)])
-            reqs.append((qf.QFS_QUERY, f, keys))
-        return reqs
+        return wl.requests(nreq, seed, qs, fill, state)
 
     def run(reqs, rate):
         """Submit reqs with Poisson arrivals at `rate` requests/s (None = as fast as possible)."""
@@ -558,7 +558,7 @@ def bench_serve(args) -> dict:
     return {"metric": "serving: mixed request throughput and latency (256 filters, 2^18..2^26, r=8/16)",
             "value": sat["Bps"], "unit": "B keys/s at saturation", "n_gpus": 1, "higher_is_better": True,
             "dtype": "u64", "data": "synthetic",
-            "config": {"workload": f"serve_{nf}filters_q18to26_r8or16_mix70q25i5d", "filters": nf,
+            "config": {"workload": wl.name(), "filters": nf,
                        "requests_per_run": nreq, "budget_bytes": 64 << 30},
             "saturation": sat, "loop": loop, "points": points, "server": st}
 
@@ -703,11 +703,15 @@ def main() -> int:
     # The timed region: HIP events on the launch stream bracket only the merge
     # launches (the roofline kernel); every event pair holds the stream for a
     # few microseconds, so the other kernels run unbracketed.
+    # Events recorded on the stream between the operations of each step give
+    # the per-operation rates (insert and query are the metric's two numbers)
+    # from the timed steps themselves.
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
     qf.qf_profile_enable(f.h, True, kinds=("merge",))
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for k in range(args.steps):
-        step(args.warmup + k)
+        step(args.warmup + k, events[k])
     torch.cuda.synchronize()
     t_end = time.perf_counter()
     prof_timed = qf.qf_profile_read(f.h)
@@ -715,18 +719,13 @@ def main() -> int:
     rc = f.sync()
     assert rc == 0, f"deferred error {rc}"
     elapsed = t_end - t_start
-    # Untimed replays of the same steps (each step leaves the table as it
-    # found it): events between the operations, then every kernel kind
-    # bracketed, for the per-operation rates and the kernel breakdown.
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
-    for k in range(args.steps):
-        step(args.warmup + k, events[k])
-    torch.cuda.synchronize()
     op_ms = np.zeros(4)
     for ev in events:
         for j in range(4):
             op_ms[j] += ev[j].elapsed_time(ev[j + 1])
     op_ms /= args.steps
+    # An untimed replay of the same steps (each step leaves the table as it
+    # found it) with every kernel kind bracketed: the kernel breakdown.
     qf.qf_profile_enable(f.h, True)
     for k in range(args.steps):
         step(args.warmup + k)
@@ -766,6 +765,24 @@ def main() -> int:
                     "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "ms_per_launch": round(per_t, 5), "launches": n_t,
                     "time_share": round(ms_t / (elapsed * 1e3), 3)}
+    # whole operations against the same roofline: algorithmic bytes per key
+    # (the key in, the grouping round trip of an update, the changed blocks
+    # read and written, the distinct blocks a lookup reads, the result out)
+    op_roof = None
+    if consts is not None:
+        Bb = 64 * (w.r + 2) // 8 + 1
+        per_key = {"insert": 8.0 + 16.0 + 2.0 * Bb * consts["C_mean"] / m,
+                   "query": 8.0 + 1.0 + Bb * consts["D_mean"] / m,
+                   "count": 8.0 + 8.0 + Bb * consts["D_mean"] / m,
+                   "delete": 8.0 + 16.0 + 2.0 * Bb * consts["C_mean"] / m}
+        op_roof = {}
+        for j, k in enumerate(("insert", "query", "count", "delete")):
+            gbs = per_key[k] * m / (op_ms[j] * 1e-3) / 1e9
+            op_roof[k] = {"alg_bytes_per_key": round(per_key[k], 2), "GBs": round(gbs, 1),
+                          "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    attainable = copy_bandwidth(torch)
+    if roofline is not None:
+        roofline["attainable_copy_GBs"] = attainable
     out = {
         "metric": METRIC,
         "value": round(total_ops / elapsed / 1e9, 4),
@@ -781,6 +798,9 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": w.name(), "q": w.q, "r": w.r, "load": w.load, "batch": m,
                    "ops_per_step": 4 * m},
+        # the metric's two numbers, from the timed steps
+        "insert_Bps": round(m / op_ms[0] / 1e6, 4),
+        "query_Bps": round(m / op_ms[1] / 1e6, 4),
         "rates_Bps": {
             "insert": round(m / op_ms[0] / 1e6, 4),
             "query": round(m / op_ms[1] / 1e6, 4),
@@ -788,17 +808,20 @@ def main() -> int:
             "delete": round(m / op_ms[3] / 1e6, 4),
         },
         "op_ms": {k: round(float(v), 4) for k, v in zip(("insert", "query", "count", "delete"), op_ms)},
+        "op_roofline": op_roof,
+        "attainable_copy_GBs": attainable,
         # every kind bracketed, in an untimed replay of the same steps
         "kernels": kinds,
         "dominant_kernel": dom,
         "roofline": roofline,
     }
+    f.close()
+    del ins, qry
     if not args.no_cpu_baseline:
-        log("timing the CPU oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(w)
+        log("timing the CPU oracle on a bounded sample of the same step")
+        out["cpu_baseline"] = cpu_baseline(w, fill)
     else:
         out["cpu_baseline"] = None
-    f.close()
     print(json.dumps(out), flush=True)
     return 0
 

@@ -177,7 +177,9 @@ int qf_profile_read(qf_t *f, double *ms, uint64_t *n);
  * and surface at qf_set_sync (or qf_sync of that filter).  The set does not
  * own its filters; they must outlive it, and per-filter calls must be stream
  * ordered with set calls.  qf_set_create is synchronous and fails with
- * QF_ERR_ARG for nf == 0, a NULL filter, mixed r, or more than 2^31 regions. */
+ * QF_ERR_ARG for nf == 0, a NULL filter, the same filter listed twice, mixed
+ * r, or more than 2^31 regions (NULL and repeated handles are found before
+ * any handle is read). */
 typedef struct qf_set qf_set_t;
 qf_set_t *qf_set_create(qf_t *const *filters, uint32_t nf);
 void qf_set_destroy(qf_set_t *s); /* NULL-safe; waits for the device */
@@ -315,6 +317,11 @@ int qfs_submit(qfs_t *s, int op, int id, const uint64_t *h_keys, uint64_t n, voi
 /* Closes a filter after its earlier requests; its completion is reported with
  * `tag` like a request's.  Later submissions to it fail with QF_ERR_ARG. */
 int qfs_close(qfs_t *s, int id, uint64_t tag);
+/* Copies filter id's table, as its requests submitted before this call left
+ * it, into the caller's host arrays (as qf_export; sized for the filter's q
+ * and r, kept alive until the completion with `tag` is polled; its status is
+ * qf_export's result).  Later requests of the filter wait for the copy. */
+int qfs_export(qfs_t *s, int id, qf_layout_t *out, uint64_t tag);
 /* Writes up to max completions (tag, status); waits up to wait_us for one if
  * none is ready.  Returns how many were written. */
 int qfs_poll(qfs_t *s, uint64_t *tags, int32_t *status, uint32_t max, int wait_us);

@@ -351,25 +351,13 @@ def _decode_py(run: list[int], p: int, r: int) -> tuple[int, int, int]:
 
 
 def clusters(L: Layout) -> np.ndarray:
-    """Lengths of maximal runs of used slots (clusters, Sec. 5.1)."""
-    q = int(L.header[0])
-    N = 1 << q
-    P = int(L.header[4])
-    occ = bits(L.occ_words, N)
-    rend = bits(L.runend_words, P)
-    rq = np.nonzero(occ)[0]
-    re = np.nonzero(rend)[0]
+    """Lengths of maximal runs of used slots (clusters, Sec. 5.1): a run that
+    starts right after the previous run's end continues its cluster."""
+    rq, rs, re = run_bounds(L)
     if len(rq) == 0:
         return np.zeros(0, dtype=np.int64)
-    # run starts from the canonical rule
-    starts = np.empty(len(rq), dtype=np.int64)
-    prev = -1
-    for i, (x, e) in enumerate(zip(rq, re)):
-        starts[i] = max(int(x), prev + 1)
-        prev = int(e)
     new_cluster = np.ones(len(rq), dtype=bool)
-    new_cluster[1:] = starts[1:] > re[:-1] + 1
-    cid = np.cumsum(new_cluster) - 1
+    new_cluster[1:] = rs[1:] > re[:-1] + 1
     first = np.nonzero(new_cluster)[0]
     last = np.r_[first[1:] - 1, len(rq) - 1]
-    return (re[last] - starts[first] + 1).astype(np.int64)
+    return (re[last] - rs[first] + 1).astype(np.int64)

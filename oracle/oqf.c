@@ -599,6 +599,43 @@ int oqf_export(const oqf_t *f, uint64_t *occ_words, uint64_t *runend_words, uint
   return OQF_OK;
 }
 
+/* Replaces the table by a logical layout (the fields oqf_export writes; the
+ * header's used, distinct and total are taken as given).  The private used
+ * bits follow from the runs: the run of the k-th occupied quotient x ends at
+ * the k-th run end and starts at max(x, previous end + 1) (Sec. 5.1).  Used
+ * to start a timing run from a large table without inserting it key by key.
+ * Returns OQF_ERR_ARG when the occupied quotients and run ends do not pair
+ * up. */
+int oqf_import(oqf_t *f, const uint64_t *occ_words, const uint64_t *runend_words, const uint16_t *slots,
+               const uint64_t *header) {
+  if (!f || !occ_words || !runend_words || !slots || !header) return OQF_ERR_ARG;
+  if (header[0] != f->q || header[1] != f->r) return OQF_ERR_ARG;
+  for (uint64_t x = 0; x < f->N; x++) f->occ[x] = (occ_words[x / 64] >> (x % 64)) & 1;
+  for (uint64_t j = 0; j < f->P; j++) {
+    f->runend[j] = (runend_words[j / 64] >> (j % 64)) & 1;
+    f->slot[j] = slots[j];
+    f->used[j] = 0;
+  }
+  int64_t prev_end = -1;
+  uint64_t j = 0;
+  for (uint64_t x = 0; x < f->N; x++) {
+    if (!f->occ[x]) continue;
+    while (j < f->P && !f->runend[j]) j++;
+    if (j >= f->P) return OQF_ERR_ARG;
+    uint64_t start = (int64_t)x > prev_end + 1 ? x : (uint64_t)(prev_end + 1);
+    if (j < start) return OQF_ERR_ARG;
+    for (uint64_t k = start; k <= j; k++) f->used[k] = 1;
+    prev_end = (int64_t)j;
+    j++;
+  }
+  for (; j < f->P; j++)
+    if (f->runend[j]) return OQF_ERR_ARG;
+  f->used_slots = header[5];
+  f->distinct = header[6];
+  f->total = header[7];
+  return OQF_OK;
+}
+
 /* longest cluster (contiguous used slots), for the cluster-length checks */
 uint64_t oqf_max_cluster(const oqf_t *f) {
   uint64_t best = 0, cur = 0;

@@ -73,6 +73,8 @@ def lib():
         L.oqf_query_batch.argtypes = [vp, vp, u64, vp]
         L.oqf_export.restype = ctypes.c_int
         L.oqf_export.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.oqf_import.restype = ctypes.c_int
+        L.oqf_import.argtypes = [vp, vp, vp, vp, vp]
         L.oqf_max_cluster.restype = u64
         L.oqf_max_cluster.argtypes = [vp]
         L.oqf_encode_entry.restype = u64
@@ -206,6 +208,16 @@ class OracleQF:
         if rc:
             raise RuntimeError("oqf_export failed")
         return Layout(occ, rend, slots, offs, hdr)
+
+    def load(self, lay: Layout) -> None:
+        """Replace the table by a logical layout (e.g. one brute.layout built)."""
+        occ = np.ascontiguousarray(lay.occ_words, dtype=np.uint64)
+        rend = np.ascontiguousarray(lay.runend_words, dtype=np.uint64)
+        slots = np.ascontiguousarray(lay.slots, dtype=np.uint16)
+        hdr = np.ascontiguousarray(lay.header, dtype=np.uint64)
+        rc = lib().oqf_import(self._h, _ptr(occ), _ptr(rend), _ptr(slots), _ptr(hdr))
+        if rc:
+            raise ValueError(f"oqf_import rejected the layout ({rc})")
 
     def max_cluster(self) -> int:
         return int(lib().oqf_max_cluster(self._h))

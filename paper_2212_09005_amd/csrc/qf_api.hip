@@ -579,8 +579,19 @@ qf_set_t *qf_set_create(qf_t *const *filters, uint32_t nf) {
     fail(QF_ERR_ARG);
     return nullptr;
   }
+  // NULL handles and the same handle twice are refused before any handle is
+  // read: two descriptors of one filter would both write its other table
+  // copy and flip its current copy twice in one merge launch
+  std::vector<const qf_t *> seen(filters, filters + nf);
+  std::sort(seen.begin(), seen.end());
   for (uint32_t i = 0; i < nf; ++i) {
-    if (!filters[i] || filters[i]->r != filters[0]->r) {
+    if (!seen[i] || (i > 0 && seen[i] == seen[i - 1])) {
+      fail(QF_ERR_ARG);
+      return nullptr;
+    }
+  }
+  for (uint32_t i = 0; i < nf; ++i) {
+    if (filters[i]->r != filters[0]->r) {
       fail(QF_ERR_ARG);
       return nullptr;
     }

@@ -29,7 +29,8 @@
 
 namespace {
 
-enum { OP_INSERT = QFS_INSERT, OP_DELETE = QFS_DELETE, OP_QUERY = QFS_QUERY, OP_COUNT = QFS_COUNT, OP_CLOSE = 4 };
+enum { OP_INSERT = QFS_INSERT, OP_DELETE = QFS_DELETE, OP_QUERY = QFS_QUERY, OP_COUNT = QFS_COUNT, OP_CLOSE = 4,
+       OP_EXPORT = 5 };
 
 struct Req {
   uint64_t seq;  // submission order
@@ -112,7 +113,8 @@ struct Part {
 struct Round {
   std::vector<Part> parts;
   std::vector<Req *> closes;
-  bool empty() const { return parts.empty() && closes.empty(); }
+  std::vector<Req *> exports;  // table copies to the caller, after the round
+  bool empty() const { return parts.empty() && closes.empty() && exports.empty(); }
 };
 
 // A filter set per r over the open filters, rebuilt when membership changes.
@@ -206,6 +208,15 @@ Round form_round_locked(qf_server *s) {
       // after every earlier request of the filter has completed
       take = !blocked[q->id] && fop.find(q->id) == fop.end();
       if (take) rd.closes.push_back(q);
+      blocked[q->id] = true;
+      if (!take) rest.push_back(q);
+      continue;
+    }
+    if (q->op == OP_EXPORT) {
+      // the same rule as a close, for an admitted filter; later requests of
+      // the filter wait for the next round
+      take = sl.state == Slot::OPEN && !blocked[q->id] && fop.find(q->id) == fop.end();
+      if (take) rd.exports.push_back(q);
       blocked[q->id] = true;
       if (!take) rest.push_back(q);
       continue;
@@ -362,6 +373,12 @@ void complete_round(qf_server *s, Round &rd, Stage &st, int launch_rc) {
     }
     base += p.n;
   }
+  // exports read the table as this round left it (the round launched after
+  // it holds no request of an exported filter)
+  for (Req *e : rd.exports) {
+    qf_t *f = s->slots[e->id].f;
+    e->status = f ? qf_export(f, static_cast<qf_layout_t *>(e->out), s->stream) : QF_ERR_ARG;
+  }
   std::lock_guard<std::mutex> lk(s->mu);
   for (Req *c : rd.closes) {
     Slot &sl = s->slots[c->id];
@@ -381,7 +398,8 @@ void complete_round(qf_server *s, Round &rd, Stage &st, int launch_rc) {
       s->keys += q->keys.size();
     }
   for (Req *c : rd.closes) s->done.push_back(c);
-  s->requests += rd.closes.size();
+  for (Req *e : rd.exports) s->done.push_back(e);
+  s->requests += rd.closes.size() + rd.exports.size();
   for (Part &p : rd.parts) s->requests += p.reqs.size();
   s->rounds += 1;
   s->cv_done.notify_all();
@@ -523,6 +541,29 @@ int qfs_close(qfs_t *s, int id, uint64_t tag) {
       return QF_ERR_ARG;
     }
     s->slots[id].closing = true;
+    q->seq = s->seq++;
+    s->queue.push_back(q);
+  }
+  s->cv_work.notify_all();
+  return QF_OK;
+}
+
+int qfs_export(qfs_t *s, int id, qf_layout_t *out, uint64_t tag) {
+  if (!s || !out || !out->occ_words || !out->runend_words || !out->slots || !out->offsets) return QF_ERR_ARG;
+  Req *q = new (std::nothrow) Req();
+  if (!q) return QF_ERR_OOM;
+  q->op = OP_EXPORT;
+  q->id = id;
+  q->out = out;
+  q->tag = tag;
+  q->status = QF_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (id < 0 || static_cast<size_t>(id) >= s->slots.size() || s->slots[id].closing ||
+        s->slots[id].state == Slot::CLOSED) {
+      delete q;
+      return QF_ERR_ARG;
+    }
     q->seq = s->seq++;
     s->queue.push_back(q);
   }

@@ -10,8 +10,8 @@ counting benchmark uses Zipfian counts, Sec. 6.7):
   * present keys: 63-bit uniform values (top bit 0) from PCG64(seed);
   * absent keys: 63-bit uniform values with the top bit set, from another seed,
     so they can never equal a present key;
-  * Zipf keys: rank k in [1, universe] drawn with P(k) ~ k^-s by numpy's
-    Zipf sampler with ranks above the universe rejected, then mapped to a key
+  * Zipf keys: rank k in [1, universe] drawn with P(k) ~ k^-s by
+    rejection-inversion (Hoermann and Derflinger 1996), then mapped to a key
     by an odd-multiplier bijection (distinct ranks give distinct keys).
 """
 from __future__ import annotations
@@ -73,15 +73,58 @@ def mixed_queries(seed: int, present: np.ndarray, n_present: int, n_absent: int)
 _ZIPF_MUL = U64(0x9E3779B97F4A7C15)  # odd, so k -> k * M is a bijection mod 2^64
 
 
+_ZIPF_CHUNK = 1 << 22
+
+
+def _zipf_chunk(seed: int, j: int, n: int, s: float, universe: int) -> np.ndarray:
+    """n Zipf ranks by rejection-inversion (Hoermann and Derflinger, ACM TOMACS
+    1996): with h(x) = x^-s and its integral H, draw u uniformly from
+    [H(3/2) - h(1), H(universe + 1/2)], invert it to x = H^-1(u), round to k and
+    keep k when u lies in the top h(k) of k's share [H(k - 1/2), H(k + 1/2)]
+    (so P(k) is exactly proportional to h(k); k = 1's share is h(1) long)."""
+    g = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, j])))
+    a = 1.0 - s
+
+    def H(x):
+        return np.expm1(a * np.log(x)) / a
+
+    def Hinv(y):
+        return np.exp(np.log1p(a * y) / a)
+
+    lo = float(H(np.float64(1.5))) - 1.0
+    hi = float(H(np.float64(universe + 0.5)))
+    out = np.empty(n, dtype=np.int64)
+    filled = 0
+    while filled < n:
+        need = n - filled
+        u = hi + g.random(need + need // 16 + 64) * (lo - hi)
+        x = Hinv(u)
+        k = np.clip(np.floor(x + 0.5), 1, universe)
+        ok = u >= H(k + 0.5) - np.exp(-s * np.log(k))
+        k = k[ok][:need].astype(np.int64)
+        out[filled:filled + len(k)] = k
+        filled += len(k)
+    return out
+
+
 def zipf_ranks(seed: int, n: int, s: float = 1.1, universe: int = 1 << 28) -> np.ndarray:
-    """n ranks in [1, universe] with P(k) proportional to k^-s (rejection of k > universe)."""
-    g = _gen(seed)
-    out = np.zeros(0, dtype=np.int64)
-    while len(out) < n:
-        need = n - len(out)
-        k = g.zipf(s, size=int(need * 1.25) + 1024)
-        k = k[k <= universe]
-        out = np.concatenate([out, k[:need]])
+    """n ranks in [1, universe] with P(k) proportional to k^-s (s > 0, s != 1).
+    The stream is cut into chunks of 2^22 draws, chunk j from its own PCG64
+    generator seeded by (seed, j); chunks are drawn on several threads and the
+    result does not depend on how many."""
+    import concurrent.futures as cf
+    import os
+
+    out = np.empty(n, dtype=np.int64)
+    starts = list(range(0, n, _ZIPF_CHUNK))
+
+    def work(j):
+        a = starts[j]
+        b = min(a + _ZIPF_CHUNK, n)
+        out[a:b] = _zipf_chunk(seed, j, b - a, s, universe)
+
+    with cf.ThreadPoolExecutor(max_workers=max(1, min(16, os.cpu_count() or 1))) as ex:
+        list(ex.map(work, range(len(starts))))
     return out
 
 

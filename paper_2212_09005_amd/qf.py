@@ -153,6 +153,7 @@ def lib() -> ctypes.CDLL:
         "qfs_open": (i32, [vp, u32, u32]),
         "qfs_submit": (i32, [vp, i32, i32, vp, u64, vp, u64]),
         "qfs_close": (i32, [vp, i32, u64]),
+        "qfs_export": (i32, [vp, i32, ctypes.POINTER(_Layout), u64]),
         "qfs_poll": (i32, [vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int32), u32, i32]),
         "qfs_stats": (i32, [vp, ctypes.POINTER(ctypes.c_uint64)]),
     }
@@ -574,6 +575,18 @@ class Graph:
 QFS_INSERT, QFS_DELETE, QFS_QUERY, QFS_COUNT = 0, 1, 2, 3
 
 
+class ServedExport:
+    """Host arrays a served filter's table is copied into (Server.export)."""
+
+    def __init__(self, lay: QFLayout):
+        self.lay = lay
+        self.c = _Layout()
+
+    def layout(self) -> QFLayout:
+        self.lay.header[:] = np.frombuffer(bytes(self.c.header), dtype=np.uint64)
+        return self.lay
+
+
 class Server:
     """Device-resident filters answering host requests with continuous batching (qfs_* calls).
     Keys are host numpy uint64 arrays; outputs are host numpy arrays kept alive until completion."""
@@ -619,6 +632,22 @@ class Server:
     def close_filter(self, fid: int, tag: int):
         _check(lib().qfs_close(self.h, fid, tag), "qfs_close")
         self._live[tag] = (None, None)
+
+    def export(self, fid: int, q: int, r: int, tag: int) -> "ServedExport":
+        """qfs_export: the filter's table after its requests submitted so far.  The returned object's
+        layout() is valid once the completion with `tag` has been polled (status QF_OK)."""
+        nblocks = qf_table_bytes(q, r) // (128 if r == 8 else 160)
+        P = nblocks * 64
+        ex = ServedExport(QFLayout(np.zeros((1 << q) // 64, np.uint64), np.zeros(P // 64, np.uint64),
+                                   np.zeros(P, np.uint16), np.zeros(P // 64, np.uint32), np.zeros(8, np.uint64)))
+        c = ex.c
+        c.occ_words = ex.lay.occ_words.ctypes.data
+        c.runend_words = ex.lay.runend_words.ctypes.data
+        c.slots = ex.lay.slots.ctypes.data
+        c.offsets = ex.lay.offsets.ctypes.data
+        _check(lib().qfs_export(self.h, fid, ctypes.byref(c), tag), "qfs_export")
+        self._live[tag] = (ex, None)
+        return ex
 
     def poll(self, max_n: int = 4096, wait_us: int = 1000) -> list[tuple[int, int]]:
         tags = (ctypes.c_uint64 * max_n)()

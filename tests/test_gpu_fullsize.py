@@ -1,11 +1,12 @@
-"""Parity at the benchmark's full size (2^28 quotients, r = 8, load 0.9).
+"""Parity at the benchmark's full size (2^28 quotients, r = 8, load 0.9 and 0.95).
 
 The GPU table is filled with the benchmark's own key stream and batch size
 (the launch configuration bench.py times), exported, and compared bit for bit
 with the canonical table the definition oracle (oracle/brute.py) builds from
 the same multiset; then one benchmark step (insert a batch, query, count,
-delete it) is checked the same way.  The host side needs ~25 GB of memory and
-about a minute per table.
+delete it) is checked the same way, and the fill goes on to load 0.95, where
+the table, the counts and the longest cluster are checked.  The host side
+needs ~25 GB of memory and about a minute per table.
 """
 from __future__ import annotations
 
@@ -16,6 +17,7 @@ import numpy as np
 import pytest
 
 from oracle import brute
+from paper_2212_09005_amd import inputs
 from paper_2212_09005_amd.workloads import C2
 
 torch = pytest.importorskip("torch")
@@ -80,44 +82,35 @@ def test_full_size_load_sweep_table_and_step():
     rc, lay2 = f.export()
     assert rc == 0 and int(nf.item()) == 0
     compare(lay2, brute.layout(ms0[0], ms0[1], w.q, w.r), "after the step's delete")
+    del lay2
     note(f"step bit-exact ({time.time() - t0:.0f}s)")
-    f.close()
 
-
-def test_largest_table_zipf_counts_sampled():
-    # the largest configuration's table (2^30 quotients, r = 16: 5.4 GB for
-    # the two copies), filled by one batch of Zipf(1.1) instances over 2^28
-    # values; the oracle cannot build a table this size in a test, so the
-    # check is exact counts of a sample against the definition: a key's count
-    # is the multiplicity of its fingerprint in the inserted multiset
-    from paper_2212_09005_amd import inputs, qf
-
-    q, r, n = 30, 16, 1 << 26
-    note(f"q={q} r={r}: {n} Zipf instances in one batch")
-    keys = inputs.zipf_keys(3, n, 1.1, 1 << 28)
-    f = qf.CQF(q, r)
-    d = torch.from_numpy(keys.view(np.int64)).to("cuda")
-    f.insert(d)
+    # on to load 0.95 with the same stream and batch size
+    n95 = int(0.95 * (1 << w.q))
+    fill95 = inputs.uniform_keys(w.fill_seed, n95)
+    assert np.array_equal(fill95[: len(fill)], fill)
+    for s in range(len(fill), n95, w.batch):
+        part = fill95[s : s + w.batch]
+        d[: len(part)].copy_(torch.from_numpy(part.view(np.int64)))
+        f.insert(d[: len(part)])
     assert f.sync() == 0
-    ms = brute.multiset(brute.fingerprints(keys, q, r))
-    present = keys[np.random.default_rng(5).integers(0, n, size=1 << 19)]
-    probe = np.concatenate([present, inputs.absent_keys(6, 1 << 19)])
-    dp = torch.from_numpy(probe.view(np.int64)).to("cuda")
-    want = brute.counts_of(*ms, brute.fingerprints(probe, q, r))
-    got = f.count(dp).cpu().numpy().view(U64)
-    assert np.array_equal(got, want), f"counts differ at {int(np.count_nonzero(got != want))} keys"
-    assert (got[: 1 << 19] > 0).all()
-    info = f.info()
-    note(f"inserted and counted; batches {info['batches']}")
-    # delete a quarter of the instances and count again
-    drop = keys[inputs.bernoulli_mask(7, n, 0.25)]
-    nf = torch.zeros(1, dtype=torch.int64, device="cuda")
-    f.delete(torch.from_numpy(drop.view(np.int64)).to("cuda"), nf)
-    assert f.sync() == 0
-    assert int(nf.cpu()[0]) == 0
-    ms2, short = brute.merge_multisets(ms, brute.multiset(brute.fingerprints(drop, q, r)), subtract=True)
-    assert int(short) == 0
-    want2 = brute.counts_of(*ms2, brute.fingerprints(probe, q, r))
-    got2 = f.count(dp).cpu().numpy().view(U64)
-    assert np.array_equal(got2, want2), f"counts after delete differ at {int(np.count_nonzero(got2 != want2))} keys"
+    rc, lay3 = f.export()
+    assert rc == 0
+    del ms0, ms1
+    ms95 = brute.multiset(brute.fingerprints(fill95, w.q, w.r))
+    ref95 = brute.layout(ms95[0], ms95[1], w.q, w.r)
+    compare(lay3, ref95, "at load 0.95")
+    del lay3
+    qk95 = inputs.mixed_queries(2095, fill95, w.batch // 2, w.batch - w.batch // 2)
+    got95 = f.count(torch.from_numpy(qk95.view(np.int64)).cuda()).cpu().numpy().view(U64)
+    assert np.array_equal(got95, brute.counts_of(ms95[0], ms95[1], brute.fingerprints(qk95, w.q, w.r)))
+    # the longest cluster at load 0.95: the paper's 8192-slot regions assume
+    # clusters shorter than a region (Sec. 5.2); the analysis bounds it by
+    # ln(2^q) / (a - ln a - 1), about 15,000 slots here
+    cl = brute.clusters(ref95)
+    bound = w.q * np.log(2) / (0.95 - np.log(0.95) - 1)
+    note(f"load 0.95: table and counts bit-exact; longest cluster {int(cl.max())} slots "
+         f"(8192-slot region: {'shorter' if cl.max() < 8192 else 'longer'}; bound {bound:.0f}) "
+         f"({time.time() - t0:.0f}s)")
+    assert cl.max() < bound
     f.close()

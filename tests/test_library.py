@@ -89,6 +89,19 @@ def test_argument_errors_return_before_the_device():
     L.qf_destroy(None)
 
 
+def test_set_create_refuses_null_and_repeated_handles():
+    # both are found by comparing the handles, before any handle is read, so
+    # stand-in addresses (never dereferenced) exercise the check without a GPU
+    L = qf.lib()
+    buf = (ctypes.c_uint8 * 64)()
+    a = ctypes.addressof(buf)
+    for hs in ([a, a], [a, a + 16, a], [a + 16, 0], [0]):
+        arr = (ctypes.c_void_p * len(hs))(*hs)
+        assert L.qf_set_create(arr, len(hs)) is None
+        assert L.qf_last_error() == qf.QF_ERR_ARG
+    assert L.qf_set_create(None, 2) is None and L.qf_last_error() == qf.QF_ERR_ARG
+
+
 def test_table_bytes():
     # 128-byte blocks (r = 8) or 160-byte blocks (r = 16), offset inside
     assert qf.qf_table_bytes(16, 8) == (65536 + 2560) // 64 * 128

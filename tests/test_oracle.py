@@ -286,6 +286,52 @@ def test_c1_config_no_false_negatives_and_fp_rate():
     assert brute.clusters(L).max() < 8192
 
 
+@pytest.mark.parametrize("q,r,load", [(10, 8, 0.95), (12, 16, 0.9), (14, 8, 0.99)])
+def test_max_cluster_against_slot_scan(q, r, load):
+    # the longest stretch of used slots, three ways: the C oracle's scan of its
+    # own used bits, the vectorised cluster lengths of the canonical layout,
+    # and a plain walk over the slots marked used by the runs [start, end]
+    keys = inputs.uniform_keys(71 + q, int(load * (1 << q)))
+    o = oqf.OracleQF(q, r)
+    assert o.insert(keys) == 0
+    L = o.export()
+    P = int(L.header[4])
+    used = np.zeros(P, dtype=bool)
+    prev = -1
+    ends = iter(np.nonzero(brute.bits(L.runend_words, P))[0])
+    for x in np.nonzero(brute.bits(L.occ_words, 1 << q))[0]:
+        e = int(next(ends))
+        used[max(int(x), prev + 1): e + 1] = True
+        prev = e
+    best = cur = 0
+    for u in used:
+        cur = cur + 1 if u else 0
+        best = max(best, cur)
+    cl = brute.clusters(L)
+    assert o.max_cluster() == best == int(cl.max())
+    assert int(cl.sum()) == int(used.sum()) == int(L.header[5])
+
+
+def test_import_of_the_definition_layout_continues_like_inserts():
+    # a table loaded from brute.layout, then updated by the oracle, equals
+    # the table the oracle builds by inserting everything itself
+    q, r = 12, 8
+    keys = inputs.uniform_keys(81, int(0.9 * (1 << q)))
+    more = inputs.uniform_keys(82, 300)
+    a = oqf.OracleQF(q, r)
+    a.load(brute.layout(*brute.multiset(brute.fingerprints(keys, q, r)), q, r))
+    assert a.max_cluster() == int(brute.clusters(a.export()).max())
+    assert a.insert(more) == 0
+    assert a.delete(keys[:500]) == (0, 0)
+    b = oqf.OracleQF(q, r)
+    assert b.insert(keys) == 0 and b.insert(more) == 0 and b.delete(keys[:500]) == (0, 0)
+    assert a.export().equal(b.export())
+    bad = brute.layout(*brute.multiset(brute.fingerprints(keys[:10], q, r)), q, r)
+    bad.runend_words[-1] |= np.uint64(1) << np.uint64(63)
+    with pytest.raises(ValueError):
+        oqf.OracleQF(q, r).load(bad)
+
+
 def test_cluster_bound_closed_form():
     # Sec. 5.2: longest cluster O(ln 2^q / (alpha - ln alpha - 1)); the paper's
     # example q = 40, alpha = 3/4 gives 736 slots.
@@ -314,6 +360,36 @@ def test_inputs_are_deterministic_and_disjoint():
     # head frequency of a Zipf(1.1) stream: P(1) = 1 / H, H = sum k^-1.1
     H = sum(k ** -1.1 for k in range(1, 200000)) + (200000 ** -0.1) / 0.1
     assert abs((z == 1).mean() - 1 / H) < 0.02
+
+
+def test_zipf_sampler_matches_the_distribution():
+    # rank frequencies of 2^24 draws against P(k) = k^-s / H(s, 2^28) in bins
+    # (chi-square, 9 degrees of freedom, 99.9% critical value 27.9); H is summed
+    # exactly to 10^6 and the rest by the Euler-Maclaurin integral
+    s, U = 1.1, 1 << 28
+    z = inputs.zipf_ranks(3, 1 << 24, s, U)
+    assert z.min() >= 1 and z.max() <= U
+    ks = np.arange(1, 10 ** 6 + 1, dtype=np.float64)
+    w = ks ** -s
+    a = 1 - s
+    tail = ((U + 0.5) ** a - (10 ** 6 + 0.5) ** a) / a
+    Hs = w.sum() + tail
+    edges = [1, 2, 3, 4, 6, 11, 101, 10 ** 4 + 1, 10 ** 6 + 1, U + 1]
+    cum = np.concatenate([[0.0], np.cumsum(w)])
+    probs = []
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        if hi <= 10 ** 6 + 1:
+            probs.append((cum[hi - 1] - cum[lo - 1]) / Hs)
+        else:
+            probs.append(tail / Hs)
+    probs = np.array(probs)
+    assert abs(probs.sum() - 1) < 1e-9
+    counts = np.histogram(z, bins=edges)[0]
+    exp = probs * len(z)
+    chi2 = float(((counts - exp) ** 2 / exp).sum())
+    assert chi2 < 27.9, (chi2, counts, exp)
+    # the stream does not depend on how it is cut into chunks or threads
+    assert np.array_equal(inputs.zipf_ranks(3, 5_000_000, s, U), z[:5_000_000])
 
 
 def test_block_counts_match_brute_force():
