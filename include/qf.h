@@ -54,7 +54,9 @@ enum {
   QF_ERR_STALLED = -6,        /* a merge region waited too long for the carry
                                  of the regions before it (a safety bound
                                  that should never trigger); batch not applied */
-  QF_ERR_BUDGET = -7          /* serving: a filter larger than the HBM budget */
+  QF_ERR_BUDGET = -7,         /* serving: a filter larger than the HBM budget */
+  QF_ERR_LIMIT = -8           /* qf_insert_batch_noalloc: batch larger than
+                                 QF_NOALLOC_MAX_KEYS (nothing happened)        */
 };
 
 /* Logical layout of a table, as host arrays (qf_export / qf_import).
@@ -89,6 +91,20 @@ void qf_destroy(qf_t *f);
  * d_keys: device, n uint64.  All or nothing; QF_ERR_FULL / COUNT_OVERFLOW are
  * deferred to qf_sync. */
 int qf_insert_batch(qf_t *f, const uint64_t *d_keys, uint64_t n, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * insert as qf_insert_batch, with the same result, but the batch scratch is a
+ * fixed device array of the library (about 32 MiB, one per GPU, held until
+ * the process ends) instead of the filter's grow-only area, and the call
+ * allocates nothing.  d_keys: device, n uint64 with n <= QF_NOALLOC_MAX_KEYS;
+ * a larger n returns QF_ERR_LIMIT at once (nothing happens).  Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU (from two
+ * streams, or two host threads, without ordering) race and corrupt each
+ * other.  Errors and all-or-nothing behaviour as qf_insert_batch.  Kernel
+ * timing (qf_profile_enable) does not cover these calls. */
+#define QF_NOALLOC_MAX_KEYS (1ull << 19)
+int qf_insert_batch_noalloc(qf_t *f, const uint64_t *d_keys, uint64_t n, void *stream);
 
 /* Sec. 6.2: d_out[i] = 1 if the fingerprint of d_keys[i] is stored, else 0.
  * d_keys: device, n uint64; d_out: device, n uint8. */

@@ -10,11 +10,21 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "qf.h"
 #include "qf_dev.h"
 #include "qf_lib.h"
+
+// Batch scratch of qf_insert_batch_noalloc: batches of up to 2^19 keys, 64
+// bytes per key (four uint64 arrays of the batch size, the merge's 32-byte
+// per-entry area) plus the radix sort's counts (256 digit totals and 256
+// counts per sort work-group of at least 4096 keys).  About 32 MiB per GPU.
+constexpr uint64_t QF_NOALLOC_KEYS = 1ull << 19;
+constexpr uint64_t QF_NOALLOC_HIST_WORDS = 256ull * (1 + (QF_NOALLOC_KEYS + 4095) / 4096);
+constexpr uint64_t QF_NOALLOC_BYTES = 8 * QF_NOALLOC_KEYS * sizeof(uint64_t) + QF_NOALLOC_HIST_WORDS * sizeof(uint32_t);
+static __device__ __align__(256) uint8_t scratch[QF_NOALLOC_BYTES];
 
 namespace qf {
 int max_region_log2(uint32_t r);
@@ -391,6 +401,37 @@ int profile_read(qf::Pipe &p, double *ms, uint64_t *n) {
   return rc ? fail(rc) : QF_OK;
 }
 
+
+// ---- batch scratch that is never allocated ----------------------------------
+// qf_insert_batch_noalloc runs the same pipeline as qf_insert_batch, with the
+// batch scratch in the file-scope array `scratch` instead of the filter's
+// grow-only area.  Each GPU the library runs on holds its own copy of the
+// array until the process ends.  In host code `scratch` names a host-side
+// stand-in, not device memory: its device address is looked up once per
+// device with that device current (hipGetSymbolAddress) and only that address
+// is handed to kernels.
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+uint8_t *g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// the device address of `scratch` on device dev (looked up on first use)
+int noalloc_scratch(int dev, uint8_t **out) {
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(QF_ERR_ARG);
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    int cur = -1;
+    QF_HIP(hipGetDevice(&cur));
+    if (cur != dev) QF_HIP(hipSetDevice(dev));
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) QF_HIP(hipSetDevice(cur));
+    if (e != hipSuccess || p == nullptr) return fail(QF_ERR_DEVICE);
+    g_noalloc_ptr[dev] = static_cast<uint8_t *>(p);
+  }
+  *out = g_noalloc_ptr[dev];
+  return QF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -448,6 +489,45 @@ void qf_destroy(qf_t *f) {
 
 int qf_insert_batch(qf_t *f, const uint64_t *d_keys, uint64_t n, void *stream) {
   return update(f, d_keys, n, 0, nullptr, stream);
+}
+
+int qf_insert_batch_noalloc(qf_t *f, const uint64_t *d_keys, uint64_t n, void *stream) {
+  if (!f || (n && !d_keys)) return fail(QF_ERR_ARG);
+  if (n == 0) return QF_OK;
+  if (n > QF_NOALLOC_KEYS) return fail(QF_ERR_LIMIT);
+  uint8_t *base = nullptr;
+  const int rc0 = noalloc_scratch(f->device, &base);
+  if (rc0) return rc0;
+  // the filter's pipeline with its scratch pointers swapped for the static
+  // area (capacity QF_NOALLOC_KEYS, so nothing grows) and no launch timer
+  // (its events are created on demand); restored after the launches
+  qf::Pipe &p = f->pipe;
+  const uint64_t cap = p.cap, hw = p.hist_words;
+  uint64_t *const bA = p.bufA, *const bB = p.bufB, *const bC = p.bufC, *const bD = p.bufD, *const bE = p.bufE;
+  uint32_t *const hist = p.hist;
+  qf::Timer *const timer = p.timer;
+  const uint64_t K = QF_NOALLOC_KEYS;
+  uint64_t *const w = reinterpret_cast<uint64_t *>(base);
+  p.bufA = w;
+  p.bufB = w + K;
+  p.bufC = w + 2 * K;
+  p.bufD = w + 3 * K;
+  p.bufE = w + 4 * K;  // 4 K words: 32 bytes per key
+  p.hist = reinterpret_cast<uint32_t *>(w + 8 * K);
+  p.hist_words = QF_NOALLOC_HIST_WORDS;
+  p.cap = K;
+  p.timer = nullptr;
+  const int rc = pipe_update(p, d_keys, nullptr, n, 0, nullptr, static_cast<hipStream_t>(stream), f->q);
+  p.bufA = bA;
+  p.bufB = bB;
+  p.bufC = bC;
+  p.bufD = bD;
+  p.bufE = bE;
+  p.hist = hist;
+  p.hist_words = hw;
+  p.cap = cap;
+  p.timer = timer;
+  return rc;
 }
 
 int qf_delete_batch(qf_t *f, const uint64_t *d_keys, uint64_t n, uint64_t *d_not_found,

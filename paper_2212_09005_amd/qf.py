@@ -26,6 +26,8 @@ QF_ERR_DEVICE = -4
 QF_ERR_COUNT_OVERFLOW = -5
 QF_ERR_STALLED = -6
 QF_ERR_BUDGET = -7
+QF_ERR_LIMIT = -8
+NOALLOC_MAX_KEYS = 1 << 19
 ERRORS = {
     QF_ERR_ARG: "QF_ERR_ARG",
     QF_ERR_FULL: "QF_ERR_FULL",
@@ -34,6 +36,7 @@ ERRORS = {
     QF_ERR_COUNT_OVERFLOW: "QF_ERR_COUNT_OVERFLOW",
     QF_ERR_STALLED: "QF_ERR_STALLED",
     QF_ERR_BUDGET: "QF_ERR_BUDGET",
+    QF_ERR_LIMIT: "QF_ERR_LIMIT",
 }
 
 
@@ -112,6 +115,7 @@ def lib() -> ctypes.CDLL:
         "qf_create": (vp, [u32, u32]),
         "qf_destroy": (None, [vp]),
         "qf_insert_batch": (i32, [vp, vp, u64, vp]),
+        "qf_insert_batch_noalloc": (i32, [vp, vp, u64, vp]),
         "qf_query_batch": (i32, [vp, vp, u64, vp, vp]),
         "qf_count_batch": (i32, [vp, vp, u64, vp, vp]),
         "qf_delete_batch": (i32, [vp, vp, u64, vp, vp]),
@@ -206,6 +210,11 @@ def qf_destroy(f: int) -> None:
 def qf_insert_batch(f: int, keys, stream=None) -> int:
     n = keys.numel()
     return lib().qf_insert_batch(f, _dev_ptr(keys, n, 8) if n else None, n, _stream(stream))
+
+
+def qf_insert_batch_noalloc(f: int, keys, stream=None) -> int:
+    n = keys.numel()
+    return lib().qf_insert_batch_noalloc(f, _dev_ptr(keys, n, 8) if n else None, n, _stream(stream))
 
 
 def qf_query_batch(f: int, keys, out, stream=None) -> int:
@@ -322,6 +331,11 @@ class CQF:
 
     def insert(self, keys, stream=None):
         _check(qf_insert_batch(self.h, keys, stream), "qf_insert_batch")
+
+    def insert_noalloc(self, keys, stream=None):
+        """qf_insert_batch_noalloc: the same insert with the library's fixed
+        device scratch (batches of at most NOALLOC_MAX_KEYS keys)."""
+        _check(qf_insert_batch_noalloc(self.h, keys, stream), "qf_insert_batch_noalloc")
 
     def delete(self, keys, not_found=None, stream=None):
         _check(qf_delete_batch(self.h, keys, not_found, stream), "qf_delete_batch")
