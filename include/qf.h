@@ -176,6 +176,41 @@ enum {
 int qf_profile_enable(qf_t *f, int kinds);
 int qf_profile_read(qf_t *f, double *ms, uint64_t *n);
 
+/* ---- enumeration, union, difference, re-layout --------------------------------
+ * The paper lists enumeration, merging and resizing among the counting quotient
+ * filter's features (Sec. 1, 2) without describing them.  A table stores every
+ * p-bit fingerprint whole (quotient = high q bits, remainder = low r bits), so
+ * these are exact operations on the stored fingerprint multiset.  All are
+ * synchronous (they wait for `stream`) and allocate temporary device memory. */
+
+/* out[0..2] = used slots, distinct fingerprints, total count (mod 2^64) of the
+ * current table (host array). */
+int qf_stats(qf_t *f, uint64_t *out, void *stream);
+
+/* The stored multiset as <fingerprint, count> pairs sorted by fingerprint:
+ * d_fp / d_cnt are device arrays of cap uint64 each; *n (host) gets the number
+ * of pairs (the distinct fingerprints).  cap == 0 only sets *n (the arrays
+ * may be NULL); 0 < cap < *n returns QF_ERR_ARG and writes nothing. */
+int qf_enumerate(qf_t *f, uint64_t *d_fp, uint64_t *d_cnt, uint64_t cap, uint64_t *n, void *stream);
+
+/* Union (subtract = 0: dst gets the multiset sum) or saturating difference
+ * (subtract = 1: for each fingerprint, min(count in dst, count in src) copies
+ * are removed from dst and the shortfall is ADDED to *d_not_found, device, one
+ * uint64, may be NULL) of two filters whose fingerprints have the same length
+ * (dst.q + dst.r == src.q + src.r, QF_ERR_ARG otherwise); src is unchanged
+ * (src == dst doubles or empties the counts).  The source's pairs go through
+ * dst's bulk merge as an already reduced batch: all or nothing, errors
+ * (QF_ERR_FULL, QF_ERR_COUNT_OVERFLOW) deferred to qf_sync(dst).  A count of
+ * 2^32 or more for one fingerprint of src returns QF_ERR_ARG. */
+int qf_merge_into(qf_t *dst, qf_t *src, int subtract, uint64_t *d_not_found, void *stream);
+
+/* A new filter with q quotient bits and r-bit remainders (q + r equal to the
+ * source's, r in {8, 16}) holding the same fingerprint multiset as src: for
+ * example 2^20 quotients with 16-bit remainders into 2^28 quotients with
+ * 8-bit remainders, or back.  NULL on error (qf_last_error; QF_ERR_FULL when
+ * the multiset does not fit the new table). */
+qf_t *qf_resize(qf_t *src, uint32_t q, uint32_t r, void *stream);
+
 /* ---- filter sets: many filters, one pipeline of launches ------------------
  * A set groups nf existing filters with the same r (sizes may differ) so that
  * one batch of keys, each tagged with the index of its filter in the set,

@@ -432,6 +432,37 @@ int noalloc_scratch(int dev, uint8_t **out) {
   return QF_OK;
 }
 
+// enumeration of f into fp / cnt (device, at least cap entries); *n gets the
+// number of pairs; *big whether a count is 2^32 or more.  Synchronous.
+int enumerate_into(qf_filter *f, uint64_t *fp, uint64_t *cnt, uint64_t cap, uint64_t *n, bool *big,
+                   hipStream_t s) {
+  void *scr = nullptr;
+  if (hipMalloc(&scr, qf::enum_scratch_bytes(f)) != hipSuccess) return fail(QF_ERR_OOM);
+  int rc = QF_OK;
+  uint64_t words[2] = {0, 0};
+  if (qf::launch_enum(f, scr, nullptr, nullptr, false, s) != hipSuccess ||
+      hipMemcpyAsync(words, qf::enum_words(f, scr), sizeof(words), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    rc = fail(QF_ERR_DEVICE);
+  } else {
+    *n = words[0];
+    if (cap == 0) {
+      // (only the number of pairs was asked for)
+    } else if (words[0] > cap) {
+      rc = fail(QF_ERR_ARG);
+    } else if (words[0]) {
+      if (qf::launch_enum(f, scr, fp, cnt, true, s) != hipSuccess ||
+          hipMemcpyAsync(words, qf::enum_words(f, scr), sizeof(words), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        rc = fail(QF_ERR_DEVICE);
+      else if (big)
+        *big = words[1] != 0;
+    }
+  }
+  (void)hipFree(scr);
+  return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -640,6 +671,68 @@ int qf_import(qf_t *f, const qf_layout_t *in, void *stream) {
   (void)hipFree(d_slots);
   (void)hipFree(d_offs);
   return rc;
+}
+
+int qf_stats(qf_t *f, uint64_t *out, void *stream) {
+  if (!f || !out) return fail(QF_ERR_ARG);
+  QF_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+  uint64_t st[qf::ST_WORDS];
+  QF_HIP(hipMemcpy(st, f->state, sizeof(st), hipMemcpyDeviceToHost));
+  out[0] = st[qf::ST_USED];
+  out[1] = st[qf::ST_DIST];
+  out[2] = st[qf::ST_TOTAL];
+  return QF_OK;
+}
+
+int qf_enumerate(qf_t *f, uint64_t *d_fp, uint64_t *d_cnt, uint64_t cap, uint64_t *n, void *stream) {
+  if (!f || !n || (cap && (!d_fp || !d_cnt))) return fail(QF_ERR_ARG);
+  return enumerate_into(f, d_fp, d_cnt, cap, n, nullptr, static_cast<hipStream_t>(stream));
+}
+
+int qf_merge_into(qf_t *dst, qf_t *src, int subtract, uint64_t *d_not_found, void *stream) {
+  if (!dst || !src || dst->q + dst->r != src->q + src->r) return fail(QF_ERR_ARG);
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  uint64_t st[qf::ST_WORDS];
+  QF_HIP(hipStreamSynchronize(s));
+  QF_HIP(hipMemcpy(st, src->state, sizeof(st), hipMemcpyDeviceToHost));
+  const uint64_t nsrc = st[qf::ST_DIST];
+  if (nsrc == 0) return QF_OK;
+  if (nsrc > 0xFFFFFFFFull) return fail(QF_ERR_ARG);
+  qf::Pipe &p = dst->pipe;
+  int rc = ensure_scratch(p, nsrc, s);
+  if (rc) return rc;
+  // the source's pairs are the reduced batch: sorted distinct fingerprints
+  // (a single filter's merge key is the fingerprint) and their counts
+  uint64_t n = 0;
+  bool big = false;
+  rc = enumerate_into(src, p.bufC, p.bufD, p.cap, &n, &big, s);
+  if (rc) return rc;
+  if (big) return fail(QF_ERR_ARG);  // counts of 2^32 or more per fingerprint
+  if (n == 0) return QF_OK;
+  QF_HIP(hipMemcpyAsync(p.pst + qf::ST_NUNIQ, &n, sizeof(n), hipMemcpyHostToDevice, s));
+  p.nafil = p.nareg = 0;
+  QF_HIP(qf::launch_bounds(p.bufC, p, s));
+  QF_HIP(qf::launch_merge(p, p.bufC, p.bufD, subtract ? 1 : 0, d_not_found, s));
+  QF_HIP(hipStreamSynchronize(s));  // (n lives on this host stack until the copy is done)
+  p.batches += 1;
+  return QF_OK;
+}
+
+qf_t *qf_resize(qf_t *src, uint32_t q, uint32_t r, void *stream) {
+  if (!src || q + r != src->q + src->r) {
+    fail(QF_ERR_ARG);
+    return nullptr;
+  }
+  qf_t *dst = qf_create(q, r);
+  if (!dst) return nullptr;
+  const int rc = qf_merge_into(dst, src, 0, nullptr, stream);
+  if (rc == QF_OK) {
+    const int e = qf_sync(dst, stream);
+    if (e == QF_OK) return dst;
+    fail(e);
+  }
+  qf_destroy(dst);
+  return nullptr;
 }
 
 int qf_last_error(void) { return g_last_error; }

@@ -143,6 +143,17 @@ uint32_t sort_groups(uint64_t n, uint32_t chunk);
 // totals, then 256 counts per work-group (also the reduction's per-group counts)
 uint64_t sort_count_words(uint64_t cap);
 int max_region_log2(uint32_t r);
+// enumeration (qf_enum.hip): scratch bytes for a filter, and the two passes:
+// write = false counts entries per quotient block and scans them (the total
+// goes to the scratch's total word, read by enum_total); write = true writes
+// the sorted <fingerprint, count> pairs to fp / cnt
+uint64_t enum_scratch_bytes(const qf_filter *f);
+hipError_t launch_enum(qf_filter *f, void *scratch, uint64_t *fp, uint64_t *cnt, bool write, hipStream_t s);
+// device address of the scratch words [total, big count] inside the scratch
+inline uint64_t *enum_words(const qf_filter *f, void *scratch) {
+  const uint64_t nqb = f->N / 64, nseg = (nqb + 4095) / 4096;
+  return reinterpret_cast<uint64_t *>(static_cast<uint8_t *>(scratch) + ((nqb * 4 + 7) / 8) * 8) + nseg;
+}
 // the merge's finish: work-group size and regions per work-group
 constexpr uint32_t FIN_NT = 256;
 constexpr uint32_t FIN_REG = 2048;

@@ -116,6 +116,10 @@ def lib() -> ctypes.CDLL:
         "qf_destroy": (None, [vp]),
         "qf_insert_batch": (i32, [vp, vp, u64, vp]),
         "qf_insert_batch_noalloc": (i32, [vp, vp, u64, vp]),
+        "qf_stats": (i32, [vp, ctypes.POINTER(ctypes.c_uint64), vp]),
+        "qf_enumerate": (i32, [vp, vp, vp, u64, ctypes.POINTER(ctypes.c_uint64), vp]),
+        "qf_merge_into": (i32, [vp, vp, i32, vp, vp]),
+        "qf_resize": (vp, [vp, u32, u32, vp]),
         "qf_query_batch": (i32, [vp, vp, u64, vp, vp]),
         "qf_count_batch": (i32, [vp, vp, u64, vp, vp]),
         "qf_delete_batch": (i32, [vp, vp, u64, vp, vp]),
@@ -367,6 +371,45 @@ class CQF:
 
     def info(self) -> dict:
         return qf_info(self.h)
+
+    @classmethod
+    def _own(cls, h: int, q: int, r: int) -> "CQF":
+        f = cls.__new__(cls)
+        f.q, f.r, f.h = q, r, h
+        return f
+
+    def stats(self, stream=None) -> dict:
+        """qf_stats: used slots, distinct fingerprints, total count."""
+        out = (ctypes.c_uint64 * 3)()
+        _check(lib().qf_stats(self.h, out, _stream(stream)), "qf_stats")
+        return {"used": int(out[0]), "distinct": int(out[1]), "total": int(out[2])}
+
+    def enumerate(self, stream=None):
+        """qf_enumerate: the stored multiset as (fingerprints, counts), two int64
+        device tensors holding uint64 values, sorted by fingerprint."""
+        import torch
+
+        n = ctypes.c_uint64(0)
+        _check(lib().qf_enumerate(self.h, None, None, 0, ctypes.byref(n), _stream(stream)), "qf_enumerate")
+        m = int(n.value)
+        fp = torch.empty(max(m, 1), dtype=torch.int64, device="cuda")
+        cnt = torch.empty(max(m, 1), dtype=torch.int64, device="cuda")
+        if m:
+            _check(lib().qf_enumerate(self.h, fp.data_ptr(), cnt.data_ptr(), m, ctypes.byref(n), _stream(stream)),
+                   "qf_enumerate")
+        return fp[:m], cnt[:m]
+
+    def merge_from(self, src: "CQF", subtract: bool = False, not_found=None, stream=None):
+        """qf_merge_into(self, src): multiset union (or saturating difference)."""
+        nf = None if not_found is None else _dev_ptr(not_found, 1, 8)
+        _check(lib().qf_merge_into(self.h, src.h, 1 if subtract else 0, nf, _stream(stream)), "qf_merge_into")
+
+    def resize(self, q: int, r: int, stream=None) -> "CQF":
+        """qf_resize: a new filter (q, r), q + r unchanged, with the same multiset."""
+        h = lib().qf_resize(self.h, q, r, _stream(stream))
+        if not h:
+            raise QFError(lib().qf_last_error(), f"qf_resize({q}, {r})")
+        return CQF._own(h, q, r)
 
     def reserve(self, n: int, stream=None):
         _check(lib().qf_reserve(self.h, n, _stream(stream)), "qf_reserve")
