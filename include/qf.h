@@ -52,8 +52,9 @@ enum {
   QF_ERR_DEVICE = -4,         /* a HIP runtime call failed                    */
   QF_ERR_COUNT_OVERFLOW = -5, /* a count would exceed 2^64 - 1                */
   QF_ERR_STALLED = -6,        /* a merge region waited too long for the carry
-                                 of the regions before it (a safety bound
-                                 that should never trigger); batch not applied */
+                                 of the regions before it, or a point update
+                                 failed to take its locks 2^20 times (safety
+                                 bounds that should never trigger); not applied */
   QF_ERR_BUDGET = -7,         /* serving: a filter larger than the HBM budget */
   QF_ERR_LIMIT = -8           /* qf_insert_batch_noalloc: batch larger than
                                  QF_NOALLOC_MAX_KEYS (nothing happened)        */
@@ -210,6 +211,28 @@ int qf_merge_into(qf_t *dst, qf_t *src, int subtract, uint64_t *d_not_found, voi
  * 8-bit remainders, or back.  NULL on error (qf_last_error; QF_ERR_FULL when
  * the multiset does not fit the new table). */
 qf_t *qf_resize(qf_t *src, uint32_t q, uint32_t r, void *stream);
+
+/* ---- point updates (Sec. 5.2; the point rows of the API table of Sec. 6) --
+ * One lane per key, in place on the current table: the keys of one call are
+ * applied concurrently and in no set order, each under region locks (4096
+ * slots per lock; a lane never waits while holding one).  Each applied update
+ * has exactly the effect the same key has in a bulk call, so afterwards the
+ * table is the canonical table of the resulting multiset.  Unlike a bulk
+ * call, a point call is NOT all or nothing: each key succeeds or fails on its
+ * own, and when the table is close to full which keys fail depends on the
+ * order in which they land.
+ *   d_status    : device, n int32 per key, may be NULL: 0 = applied,
+ *                 1 = (delete) fingerprint not stored, nothing changed,
+ *                 QF_ERR_FULL / QF_ERR_COUNT_OVERFLOW / QF_ERR_STALLED = not
+ *                 applied.  The first such error is also reported by the
+ *                 next qf_sync.
+ *   d_not_found : as for qf_delete_batch (ADDED to; may be NULL).
+ * Point lookups are qf_query_batch and qf_count_batch, which look every key
+ * up on its own (no sort); a lookup must not run at the same time as point
+ * updates of the same filter (stream order guarantees this). */
+int qf_point_insert(qf_t *f, const uint64_t *d_keys, uint64_t n, int32_t *d_status, void *stream);
+int qf_point_delete(qf_t *f, const uint64_t *d_keys, uint64_t n, int32_t *d_status, uint64_t *d_not_found,
+                    void *stream);
 
 /* ---- filter sets: many filters, one pipeline of launches ------------------
  * A set groups nf existing filters with the same r (sizes may differ) so that

@@ -492,6 +492,9 @@ qf_t *qf_create(uint32_t q, uint32_t r) {
   }
   ok = ok && hipMalloc(reinterpret_cast<void **>(&f->state), qf::ST_WORDS * sizeof(uint64_t)) == hipSuccess &&
        hipMemset(f->state, 0, qf::ST_WORDS * sizeof(uint64_t)) == hipSuccess;
+  const uint64_t lock_bytes = qf::point_lock_words(f->P) * sizeof(uint32_t);
+  ok = ok && hipMalloc(reinterpret_cast<void **>(&f->plocks), lock_bytes) == hipSuccess &&
+       hipMemset(f->plocks, 0, lock_bytes) == hipSuccess;
   if (!ok) {
     qf_destroy(f);
     fail(QF_ERR_OOM);
@@ -503,7 +506,7 @@ qf_t *qf_create(uint32_t q, uint32_t r) {
     fail(QF_ERR_OOM);
     return nullptr;
   }
-  f->table_device_bytes = 2 * qf::table_bytes(f->nblocks, r) + qf::ST_WORDS * 8;
+  f->table_device_bytes = 2 * qf::table_bytes(f->nblocks, r) + qf::ST_WORDS * 8 + lock_bytes;
   return f;
 }
 
@@ -514,6 +517,7 @@ void qf_destroy(qf_t *f) {
     (void)hipFree(f->blk[c]);
   }
   (void)hipFree(f->state);
+  (void)hipFree(f->plocks);
   pipe_free(f->pipe);
   delete f;
 }
@@ -564,6 +568,21 @@ int qf_insert_batch_noalloc(qf_t *f, const uint64_t *d_keys, uint64_t n, void *s
 int qf_delete_batch(qf_t *f, const uint64_t *d_keys, uint64_t n, uint64_t *d_not_found,
                     void *stream) {
   return update(f, d_keys, n, 1, d_not_found, stream);
+}
+
+int qf_point_insert(qf_t *f, const uint64_t *d_keys, uint64_t n, int32_t *d_status, void *stream) {
+  if (!f || (n && !d_keys)) return fail(QF_ERR_ARG);
+  if (n == 0) return QF_OK;
+  QF_HIP(qf::launch_point(f, d_keys, n, 0, d_status, nullptr, static_cast<hipStream_t>(stream)));
+  return QF_OK;
+}
+
+int qf_point_delete(qf_t *f, const uint64_t *d_keys, uint64_t n, int32_t *d_status, uint64_t *d_not_found,
+                    void *stream) {
+  if (!f || (n && !d_keys)) return fail(QF_ERR_ARG);
+  if (n == 0) return QF_OK;
+  QF_HIP(qf::launch_point(f, d_keys, n, 1, d_status, d_not_found, static_cast<hipStream_t>(stream)));
+  return QF_OK;
 }
 
 int qf_query_batch(qf_t *f, const uint64_t *d_keys, uint64_t n, uint8_t *d_out, void *stream) {

@@ -79,6 +79,7 @@ struct qf_filter {
   void *blk[2];             // two table copies (blocks, offsets inside)
   uint64_t *state;          // qf::ST_WORDS device words
   uint64_t table_device_bytes;
+  uint32_t *plocks;         // point updates: one lock word per 4096 slots (zero = free)
   qf::Pipe pipe;            // the single-filter update pipeline
 };
 
@@ -147,6 +148,11 @@ int max_region_log2(uint32_t r);
 // write = false counts entries per quotient block and scans them (the total
 // goes to the scratch's total word, read by enum_total); write = true writes
 // the sorted <fingerprint, count> pairs to fp / cnt
+// point updates (one lane per key, in place): words of the lock array of a
+// table of P slots, and the launch (status, not_found may be null)
+uint64_t point_lock_words(uint64_t P);
+hipError_t launch_point(qf_filter *f, const uint64_t *keys, uint64_t n, int del, int32_t *status,
+                        uint64_t *not_found, hipStream_t s);
 uint64_t enum_scratch_bytes(const qf_filter *f);
 hipError_t launch_enum(qf_filter *f, void *scratch, uint64_t *fp, uint64_t *cnt, bool write, hipStream_t s);
 // device address of the scratch words [total, big count] inside the scratch

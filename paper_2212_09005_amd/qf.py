@@ -123,6 +123,8 @@ def lib() -> ctypes.CDLL:
         "qf_query_batch": (i32, [vp, vp, u64, vp, vp]),
         "qf_count_batch": (i32, [vp, vp, u64, vp, vp]),
         "qf_delete_batch": (i32, [vp, vp, u64, vp, vp]),
+        "qf_point_insert": (i32, [vp, vp, u64, vp, vp]),
+        "qf_point_delete": (i32, [vp, vp, u64, vp, vp, vp]),
         "qf_sync": (i32, [vp, vp]),
         "qf_export": (i32, [vp, ctypes.POINTER(_Layout), vp]),
         "qf_import": (i32, [vp, ctypes.POINTER(_Layout), vp]),
@@ -241,6 +243,19 @@ def qf_delete_batch(f: int, keys, not_found=None, stream=None) -> int:
     return lib().qf_delete_batch(f, _dev_ptr(keys, n, 8) if n else None, n, nf, _stream(stream))
 
 
+def qf_point_insert(f: int, keys, status=None, stream=None) -> int:
+    n = keys.numel()
+    st = _dev_ptr(status, n, 4) if status is not None and n else None
+    return lib().qf_point_insert(f, _dev_ptr(keys, n, 8) if n else None, n, st, _stream(stream))
+
+
+def qf_point_delete(f: int, keys, status=None, not_found=None, stream=None) -> int:
+    n = keys.numel()
+    st = _dev_ptr(status, n, 4) if status is not None and n else None
+    nf = _dev_ptr(not_found, 1, 8) if not_found is not None else None
+    return lib().qf_point_delete(f, _dev_ptr(keys, n, 8) if n else None, n, st, nf, _stream(stream))
+
+
 def qf_sync(f: int, stream=None) -> int:
     return lib().qf_sync(f, _stream(stream))
 
@@ -343,6 +358,14 @@ class CQF:
 
     def delete(self, keys, not_found=None, stream=None):
         _check(qf_delete_batch(self.h, keys, not_found, stream), "qf_delete_batch")
+
+    def point_insert(self, keys, status=None, stream=None):
+        """qf_point_insert: one lane per key, in place, each key on its own
+        (status: optional int32 device tensor, one code per key)."""
+        _check(qf_point_insert(self.h, keys, status, stream), "qf_point_insert")
+
+    def point_delete(self, keys, status=None, not_found=None, stream=None):
+        _check(qf_point_delete(self.h, keys, status, not_found, stream), "qf_point_delete")
 
     def query(self, keys, out=None, stream=None):
         import torch

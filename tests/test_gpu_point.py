@@ -1,0 +1,211 @@
+"""Point updates (qf_point_insert / qf_point_delete) against the definition
+oracle (oracle/brute.py).
+
+Sec. 5.2 and the API table of Sec. 6: a point insert or delete changes the
+filter exactly as the bulk operation on the same key does.  The keys of one
+call land concurrently in an order nobody controls, and the table is a pure
+function of the stored multiset, so after every call the exported table must
+equal, bit for bit, the canonical table of the multiset the applied updates
+define.  Hot spots (one key thousands of times, one lock region crowded) and
+clusters that cross a lock-region boundary (4096 slots) are covered, and so
+are counters that change length (remainder 0 going from count 2 to 3 grows
+its entry by three slots).
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import brute
+from paper_2212_09005_amd import inputs
+from tests.helpers import keys_for_fingerprints
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+U64 = np.uint64
+
+
+def note(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=U64).view(np.int64)).cuda()
+
+
+def compare(lay, ref, what):
+    for name in ("occ_words", "runend_words", "slots", "offsets", "header"):
+        a = np.asarray(getattr(lay, name)).astype(U64)
+        b = np.asarray(getattr(ref, name)).astype(U64)
+        bad = np.nonzero(a != b)[0]
+        assert len(bad) == 0, f"{what}: {name} differs in {len(bad)} places, first {int(bad[0])}"
+
+
+def check(f, ms, q, r, what):
+    rc, lay = f.export()
+    assert rc == 0, what
+    compare(lay, brute.layout(ms[0], ms[1], q, r), what)
+
+
+def counter_keys(seed, q, r, quotients, reps):
+    """Keys of remainders 0 and 1 on the given quotients, each repeated
+    `reps` times (counters that cross every encoding length change)."""
+    fps = []
+    for x in quotients:
+        fps += [x << r, (x << r) | 1]
+    fps = np.array(fps, dtype=U64)
+    keys = keys_for_fingerprints(fps, q, r, seed=seed)
+    return np.repeat(keys, reps)
+
+
+def point_insert(f, keys):
+    st = torch.full((len(keys),), 7, dtype=torch.int32, device="cuda")
+    f.point_insert(dev(keys), status=st)
+    return st.cpu().numpy()
+
+
+def mixed_keys(q, r, seed, load):
+    """load * 2^q uniform keys, then repeats of an eighth of them, a few hot
+    keys and the counter keys: about 1.13 * load * 2^q slots in use."""
+    n = int(load * (1 << q))
+    g = np.random.Generator(np.random.PCG64(seed))
+    base = inputs.uniform_keys(seed, n)
+    rep = base[g.integers(0, n, size=n // 8)]  # small counts
+    hot = np.repeat(base[:3], 300)  # counts above 2^8 - 1
+    ctr = counter_keys(seed + 1, q, r, [5, 6, 100, (1 << q) - 1], 4)
+    return inputs.shuffle(seed + 2, np.concatenate([base, rep, hot, ctr]))
+
+
+@pytest.mark.parametrize("q,r,load", [(14, 8, 0.8), (13, 16, 0.75), (17, 8, 0.8)])
+def test_point_inserts_build_the_canonical_table(q, r, load):
+    from paper_2212_09005_amd import qf
+
+    note(f"point inserts q={q} r={r} load={load}")
+    keys = mixed_keys(q, r, 1000 + q, load)
+    f = qf.CQF(q, r)
+    st = point_insert(f, keys)
+    assert f.sync() == 0
+    assert np.all(st == 0)
+    ms = brute.multiset(brute.fingerprints(keys, q, r))
+    check(f, ms, q, r, "after concurrent point inserts")
+    # point lookups on the table the point inserts built
+    probe = np.concatenate([keys[:5000], inputs.absent_keys(q, 5000)])
+    got = f.count(dev(probe)).cpu().numpy().view(U64)
+    want = brute.counts_of(ms[0], ms[1], brute.fingerprints(probe, q, r))
+    assert np.array_equal(got, want)
+    f.close()
+
+
+@pytest.mark.parametrize("q,r", [(14, 8), (13, 16)])
+def test_point_deletes_saturate_and_count_the_shortfall(q, r):
+    from paper_2212_09005_amd import qf
+
+    note(f"point deletes q={q} r={r}")
+    keys = mixed_keys(q, r, 2000 + q, 0.8)
+    f = qf.CQF(q, r)
+    f.insert(dev(keys))
+    assert f.sync() == 0
+    ms = brute.multiset(brute.fingerprints(keys, q, r))
+    g = np.random.Generator(np.random.PCG64(5))
+    dk = np.concatenate([
+        keys[g.integers(0, len(keys), size=len(keys) // 2)],   # present, some more often than stored
+        np.repeat(keys[:2], 400),                               # drains hot counters past zero
+        counter_keys(2001 + q, q, r, [5, 6, 100, (1 << q) - 1], 3),
+        inputs.absent_keys(77, 3000),
+    ])
+    dk = inputs.shuffle(9, dk)
+    st = torch.full((len(dk),), 7, dtype=torch.int32, device="cuda")
+    nf = torch.zeros(1, dtype=torch.int64, device="cuda")
+    f.point_delete(dev(dk), status=st, not_found=nf)
+    assert f.sync() == 0
+    rest, short = brute.merge_multisets(ms, brute.multiset(brute.fingerprints(dk, q, r)), subtract=True)
+    check(f, rest, q, r, "after concurrent point deletes")
+    s = st.cpu().numpy()
+    assert set(np.unique(s)) <= {0, 1}
+    assert int(nf.item()) == short == int((s == 1).sum())
+    f.close()
+
+
+def test_point_and_bulk_calls_interleave():
+    from paper_2212_09005_amd import qf
+
+    q, r = 15, 8
+    note(f"bulk / point interleaved q={q} r={r}")
+    a = mixed_keys(q, r, 3000, 0.4)
+    b = mixed_keys(q, r, 3001, 0.4)
+    f = qf.CQF(q, r)
+    f.insert(dev(a))
+    st = point_insert(f, b)
+    assert f.sync() == 0 and np.all(st == 0)
+    ms = brute.multiset(brute.fingerprints(np.concatenate([a, b]), q, r))
+    check(f, ms, q, r, "bulk then point inserts")
+    d1, d2 = a[: len(a) // 2], b[: len(b) // 3]
+    f.delete(dev(d1))
+    f.point_delete(dev(d2))
+    assert f.sync() == 0
+    ms = brute.merge_multisets(ms, brute.multiset(brute.fingerprints(np.concatenate([d1, d2]), q, r)),
+                               subtract=True)[0]
+    check(f, ms, q, r, "bulk then point deletes")
+    f.insert(dev(d2))  # a bulk merge on top of a table the point path wrote
+    assert f.sync() == 0
+    ms = brute.merge_multisets(ms, brute.multiset(brute.fingerprints(d2, q, r)))
+    check(f, ms, q, r, "bulk insert after point updates")
+    f.close()
+
+
+def test_hot_region_and_clusters_across_lock_regions():
+    from paper_2212_09005_amd import qf
+
+    q, r = 14, 8
+    note("one crowded lock region; clusters across the 4096-slot boundaries")
+    g = np.random.Generator(np.random.PCG64(11))
+    # quotients packed just below the region boundaries at 4096 and 8192:
+    # their clusters run into the next region
+    xs = np.concatenate([g.integers(4096 - 700, 4096, size=900), g.integers(8192 - 300, 8192 + 50, size=500)])
+    fps = (xs.astype(U64) << U64(r)) | g.integers(0, 1 << r, size=len(xs)).astype(U64)
+    keys = np.concatenate([keys_for_fingerprints(fps, q, r, seed=12), np.repeat(inputs.uniform_keys(13, 1), 5000)])
+    keys = inputs.shuffle(14, keys)
+    f = qf.CQF(q, r)
+    st = point_insert(f, keys)
+    assert f.sync() == 0 and np.all(st == 0)
+    ms = brute.multiset(brute.fingerprints(keys, q, r))
+    check(f, ms, q, r, "crowded inserts")
+    dk = inputs.shuffle(15, keys[: len(keys) // 2])
+    f.point_delete(dev(dk))
+    assert f.sync() == 0
+    ms = brute.merge_multisets(ms, brute.multiset(brute.fingerprints(dk, q, r)), subtract=True)[0]
+    check(f, ms, q, r, "crowded deletes")
+    f.close()
+
+
+def test_point_insert_past_the_last_slot():
+    from paper_2212_09005_amd import qf
+
+    q, r = 10, 8
+    note(f"point inserts past the last slot q={q}")
+    f = qf.CQF(q, r)
+    keys = inputs.uniform_keys(20, 3000)
+    st = point_insert(f, keys)
+    assert f.sync() == qf.QF_ERR_FULL
+    assert set(np.unique(st)) <= {0, qf.QF_ERR_FULL} and (st == qf.QF_ERR_FULL).any()
+    ms = brute.multiset(brute.fingerprints(keys[st == 0], q, r))
+    check(f, ms, q, r, "the applied point inserts of a full table")
+    f.close()
+
+
+@pytest.mark.slow
+def test_point_inserts_at_scale():
+    from paper_2212_09005_amd import qf
+
+    q, r = 22, 8
+    note(f"point inserts q={q} load 0.9")
+    keys = inputs.uniform_keys(30, int(0.9 * (1 << q)))
+    f = qf.CQF(q, r)
+    f.point_insert(dev(keys))
+    assert f.sync() == 0
+    check(f, brute.multiset(brute.fingerprints(keys, q, r)), q, r, "q=22 point inserts")
+    f.close()
