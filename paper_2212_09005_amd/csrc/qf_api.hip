@@ -465,6 +465,10 @@ int enumerate_into(qf_filter *f, uint64_t *fp, uint64_t *cnt, uint64_t cap, uint
 
 }  // namespace
 
+namespace qf {
+int record_error(int code) { return fail(code); }
+}  // namespace qf
+
 extern "C" {
 
 qf_t *qf_create(uint32_t q, uint32_t r) {

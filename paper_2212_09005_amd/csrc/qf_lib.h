@@ -144,15 +144,17 @@ uint32_t sort_groups(uint64_t n, uint32_t chunk);
 // totals, then 256 counts per work-group (also the reduction's per-group counts)
 uint64_t sort_count_words(uint64_t cap);
 int max_region_log2(uint32_t r);
-// enumeration (qf_enum.hip): scratch bytes for a filter, and the two passes:
-// write = false counts entries per quotient block and scans them (the total
-// goes to the scratch's total word, read by enum_total); write = true writes
-// the sorted <fingerprint, count> pairs to fp / cnt
 // point updates (one lane per key, in place): words of the lock array of a
 // table of P slots, and the launch (status, not_found may be null)
 uint64_t point_lock_words(uint64_t P);
 hipError_t launch_point(qf_filter *f, const uint64_t *keys, uint64_t n, int del, int32_t *status,
                         uint64_t *not_found, hipStream_t s);
+// records code as the calling thread's last error (qf_last_error) and returns it
+int record_error(int code);
+// enumeration (qf_enum.hip): scratch bytes for a filter, and the two passes:
+// write = false counts entries per quotient block and scans them (the total
+// goes to the scratch's total word, read by enum_total); write = true writes
+// the sorted <fingerprint, count> pairs to fp / cnt
 uint64_t enum_scratch_bytes(const qf_filter *f);
 hipError_t launch_enum(qf_filter *f, void *scratch, uint64_t *fp, uint64_t *cnt, bool write, hipStream_t s);
 // device address of the scratch words [total, big count] inside the scratch

@@ -166,6 +166,14 @@ def lib() -> ctypes.CDLL:
         "qfs_export": (i32, [vp, i32, ctypes.POINTER(_Layout), u64]),
         "qfs_poll": (i32, [vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int32), u32, i32]),
         "qfs_stats": (i32, [vp, ctypes.POINTER(ctypes.c_uint64)]),
+        "tcf_create": (vp, [u64, i32]),
+        "tcf_destroy": (None, [vp]),
+        "tcf_insert": (i32, [vp, vp, u64, vp, vp]),
+        "tcf_query": (i32, [vp, vp, u64, vp, vp]),
+        "tcf_delete": (i32, [vp, vp, u64, vp, vp]),
+        "tcf_sync": (i32, [vp, vp]),
+        "tcf_info": (i32, [vp, ctypes.POINTER(ctypes.c_uint64), vp]),
+        "tcf_export": (i32, [vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
