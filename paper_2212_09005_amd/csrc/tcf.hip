@@ -84,6 +84,20 @@ __device__ __forceinline__ int64_t wave_sum(int64_t v) {
   for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
   return v;
 }
+// Sum over the work-group (every thread of it must call), valid in thread 0:
+// statistics go to shared words with one atomic per work-group, since
+// millions of same-address atomics (one per wave) queue for milliseconds.
+__device__ __forceinline__ int64_t group_sum(int64_t v) {
+  __shared__ int64_t part[NT / 64];
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int64_t t = 0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < NT / 64; ++w) t += part[w];
+  __syncthreads();
+  return t;
+}
 
 // ---- point form --------------------------------------------------------------
 typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
@@ -237,9 +251,9 @@ __global__ __launch_bounds__(NT) void k_point_insert(uint64_t *tbl, uint64_t nb,
     }
     if (status) status[i] = rc;
   }
-  dheld = wave_sum(dheld);
-  dback = wave_sum(dback);
-  if ((threadIdx.x & 63) == 0) {
+  dheld = group_sum(dheld);
+  dback = group_sum(dback);
+  if (threadIdx.x == 0) {
     if (dheld) qf::atomic_add_u64(&state[TS_HELD], static_cast<uint64_t>(dheld));
     if (dback) qf::atomic_add_u64(&state[TS_BACK], static_cast<uint64_t>(dback));
   }
@@ -281,10 +295,10 @@ __global__ __launch_bounds__(NT) void k_point_delete(uint64_t *tbl, uint64_t nb,
     else
       ++absent;
   }
-  dheld = wave_sum(dheld);
-  dback = wave_sum(dback);
-  absent = wave_sum(absent);
-  if ((threadIdx.x & 63) == 0) {
+  dheld = group_sum(dheld);
+  dback = group_sum(dback);
+  absent = group_sum(absent);
+  if (threadIdx.x == 0) {
     if (dheld) qf::atomic_add_u64(&state[TS_HELD], static_cast<uint64_t>(-dheld));
     if (dback) qf::atomic_add_u64(&state[TS_BACK], static_cast<uint64_t>(-dback));
     if (absent && not_found) qf::atomic_add_u64(not_found, static_cast<uint64_t>(absent));
@@ -386,8 +400,8 @@ __global__ __launch_bounds__(NT) void k_over(uint64_t nb, const uint32_t *__rest
     const uint32_t got = gs2[b + 1] - gs2[b], room = BB - pf[b];
     over = got > room ? got - room : 0;
   }
-  over = wave_sum(over);
-  if ((threadIdx.x & 63) == 0 && over) qf::atomic_add_u64(&state[TS_OVER], static_cast<uint64_t>(over));
+  over = group_sum(over);
+  if (threadIdx.x == 0 && over) qf::atomic_add_u64(&state[TS_OVER], static_cast<uint64_t>(over));
 }
 
 // One wave per block: the sorted union of the tags held, the shortcut items
@@ -460,50 +474,43 @@ __global__ __launch_bounds__(NT) void k_del_step(uint16_t *slots, uint64_t nb, c
                                                  uint64_t n, const uint32_t *__restrict__ gs,
                                                  uint64_t *__restrict__ next, uint64_t *state) {
   __shared__ uint16_t A[4][BB], O[4][BB];
+  __shared__ uint8_t R[4][BB];  // copies removed
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint64_t b = static_cast<uint64_t>(blockIdx.x) * 4 + w;  // (uniform over the wave)
   int64_t done = 0;
-  uint32_t keep0 = 0, keep1 = 0, tot = 0;
+  uint32_t tot = 0, held = 0;
   if (b < nb) {
     const uint32_t v = reinterpret_cast<const uint32_t *>(slots + b * BB)[lane];
     A[w][2 * lane] = static_cast<uint16_t>(v & 0xFFFF);
     A[w][2 * lane + 1] = static_cast<uint16_t>(v >> 16);
+    R[w][2 * lane] = 0;
+    R[w][2 * lane + 1] = 0;
   }
   __syncthreads();
   if (b < nb) {
-    const uint32_t held = lb16(A[w], BB, EMPTY_B);
+    held = lb16(A[w], BB, EMPTY_B);
     const uint64_t *grp = L + gs[b];
     const uint64_t gn = gs[b + 1] - gs[b];
+    // the r-th key of a run of tag t (r = its index minus the run's first)
+    // takes the r-th copy of t in the block, if there is one
     for (uint64_t j = lane; j < gn; j += 64) {
       const uint64_t e = grp[j];
       const uint32_t tag = static_cast<uint32_t>((e >> 24) & 0xFFFF), other = static_cast<uint32_t>(e & 0xFFFFFF);
-      const uint64_t first = lower_bound(grp, gn, (b << 40) | (static_cast<uint64_t>(tag) << 24));
-      const uint32_t copies = ub16(A[w], held, tag) - lb16(A[w], held, tag);
-      const bool ok = j - first < copies;
+      const uint64_t r = j - lower_bound(grp, gn, (b << 40) | (static_cast<uint64_t>(tag) << 24));
+      const uint32_t lo = lb16(A[w], held, tag), copies = ub16(A[w], held, tag) - lo;
+      const bool ok = r < copies;
+      if (ok) R[w][lo + r] = 1;
       done += ok ? 1 : 0;
       next[gs[b] + j] = ok ? SENT
                            : (PHASE == 1 ? comp_of(other, tag, static_cast<uint32_t>(b))
                                          : pair_of(static_cast<uint32_t>(b), other, tag));
     }
-    // slot i (tag t, first copy at lo) stays unless i - lo < min(deletes of
-    // t in this block's keys, copies of t); the keys of tag t lie in
-    // [key, key + 2^24)
-    for (int u = 0; u < 2; ++u) {
-      const uint32_t i = 2 * lane + u;
-      uint32_t keep = 0;
-      if (i < held) {
-        const uint32_t t = A[w][i];
-        const uint32_t lo = lb16(A[w], held, t), cp = ub16(A[w], held, t) - lo;
-        const uint64_t key = (b << 40) | (static_cast<uint64_t>(t) << 24);
-        const uint64_t kd = lower_bound(grp, gn, key + (1ull << 24)) - lower_bound(grp, gn, key);
-        keep = (i - lo) >= (kd < cp ? kd : cp) ? 1u : 0u;
-      }
-      if (u == 0)
-        keep0 = keep;
-      else
-        keep1 = keep;
-    }
-    // place the kept tags: exclusive scan of the per-lane counts
+  }
+  __syncthreads();
+  if (b < nb) {
+    // the kept tags, in order: exclusive scan of the per-lane counts
+    const uint32_t i0 = 2 * lane, i1 = 2 * lane + 1;
+    const uint32_t keep0 = i0 < held && !R[w][i0] ? 1u : 0u, keep1 = i1 < held && !R[w][i1] ? 1u : 0u;
     const uint32_t c = keep0 + keep1;
     uint32_t inc = c;
     for (int d = 1; d < 64; d <<= 1) {
@@ -512,8 +519,8 @@ __global__ __launch_bounds__(NT) void k_del_step(uint16_t *slots, uint64_t nb, c
     }
     tot = __shfl(inc, 63);
     uint32_t pos = inc - c;
-    if (keep0) O[w][pos++] = A[w][2 * lane];
-    if (keep1) O[w][pos] = A[w][2 * lane + 1];
+    if (keep0) O[w][pos++] = A[w][i0];
+    if (keep1) O[w][pos] = A[w][i1];
   }
   __syncthreads();
   if (b < nb) {
@@ -524,8 +531,8 @@ __global__ __launch_bounds__(NT) void k_del_step(uint16_t *slots, uint64_t nb, c
   // entries past the last block's keys (SENT from an earlier step)
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * NT;
   for (uint64_t i = gs[nb] + static_cast<uint64_t>(blockIdx.x) * NT + threadIdx.x; i < n; i += stride) next[i] = SENT;
-  done = wave_sum(done);
-  if (lane == 0 && done) qf::atomic_add_u64(&state[TS_HELD], static_cast<uint64_t>(-done));
+  (void)done;
+  (void)state;
 }
 
 // Bulk delete, last step: the identities in d[0, n) (sorted, SENT last)
@@ -554,9 +561,9 @@ __global__ __launch_bounds__(NT) void k_del_backing(const uint64_t *__restrict__
     tmp[i] = gone ? SENT : v;
     removed = gone ? 1 : 0;
   }
-  absent = wave_sum(absent);
-  removed = wave_sum(removed);
-  if ((threadIdx.x & 63) == 0) {
+  absent = group_sum(absent);
+  removed = group_sum(removed);
+  if (threadIdx.x == 0) {
     if (absent && not_found) qf::atomic_add_u64(not_found, static_cast<uint64_t>(absent));
     if (removed) qf::atomic_add_u64(&state[TS_REMOVED], static_cast<uint64_t>(removed));
   }
@@ -583,6 +590,11 @@ __global__ __launch_bounds__(NT) void k_bulk_query(const uint16_t *__restrict__ 
   }
 }
 
+// after the last sort of a bulk delete: the keys still unmatched are the
+// entries before the first SENT; the others left the blocks
+__global__ void k_held_after_delete(const uint64_t *__restrict__ d, uint64_t n, uint64_t *state) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) state[TS_HELD] -= n - lower_bound(d, n, SENT);
+}
 __global__ void k_add_word(uint64_t *state, int idx, uint64_t v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) state[idx] += v;
 }
@@ -714,6 +726,7 @@ int bulk_delete(tcf_filter *t, const uint64_t *keys, uint64_t n, uint64_t *not_f
   k_gbounds<<<gb, NT, 0, s>>>(t->bufC, n, t->nb, t->gs2);
   k_del_step<2><<<mb, NT, 0, s>>>(t->slots, t->nb, t->bufC, n, t->gs2, t->bufA, t->state);
   if (int rc = sort64(t, t->bufA, t->bufB, n, s)) return rc;
+  k_held_after_delete<<<1, 64, 0, s>>>(t->bufA, n, t->state);
   k_set_words<<<1, 64, 0, s>>>(t->state, TS_REMOVED, 1, 0ull);
   const uint64_t m = n > t->bn ? n : t->bn;
   k_del_backing<<<blocks_for(m), NT, 0, s>>>(t->bufA, n, t->backing, t->bn, t->bk_tmp, not_found, t->state);
