@@ -13,8 +13,8 @@
 //     lane ever waits on another).
 //   * Bulk: the batch is sorted by (primary block, tag, secondary block) with
 //     the library's radix sort; one lane per block plans its shortcut count;
-//     the other items choose a block and are sorted again by (chosen block,
-//     tag, other block); one wave per block merges its three sorted lists
+//     the other items (none while every block is below 3/4) choose a block,
+//     are packed, and are sorted again by (chosen block, tag, other block); one wave per block merges its three sorted lists
 //     (tags held, shortcut items, chosen items) by ranks -- each element's
 //     output index is its own index plus its rank in the other two lists,
 //     found by binary search in LDS -- and writes the 256-byte block back with
@@ -46,7 +46,7 @@ constexpr uint64_t SENT = ~0ull;  // sorts after every real key
 constexpr uint16_t EMPTY_B = 0xFFFF;
 
 // device state words
-enum { TS_ERR = 0, TS_HELD = 1, TS_BACK = 2, TS_OVER = 3, TS_OVPOS = 4, TS_REMOVED = 5, TS_WORDS = 8 };
+enum { TS_ERR = 0, TS_HELD = 1, TS_BACK = 2, TS_OVER = 3, TS_OVPOS = 4, TS_REMOVED = 5, TS_CHOSEN = 6, TS_WORDS = 8 };
 
 // ---- hash ------------------------------------------------------------------
 struct TK {
@@ -360,6 +360,18 @@ __global__ __launch_bounds__(NT) void k_gbounds(const uint64_t *__restrict__ s, 
   gs[b] = static_cast<uint32_t>(lower_bound(s, n, b == nb ? SENT : (b << 40)));
 }
 
+// the same bounds from the other side, for batches at least as large as the
+// block count: entry i (i in [0, n]) writes gs[b] = i for every block b in
+// (block of entry i - 1, block of entry i], SENT and the end counting as nb
+__global__ __launch_bounds__(NT) void k_gbounds_scatter(const uint64_t *__restrict__ s, uint64_t n, uint64_t nb,
+                                                        uint32_t *__restrict__ gs) {
+  const uint64_t i = static_cast<uint64_t>(blockIdx.x) * NT + threadIdx.x;
+  if (i > n) return;
+  const auto blk = [&](uint64_t j) -> uint64_t { return s[j] == SENT ? nb : (s[j] >> 40); };
+  const uint64_t lo = i == 0 ? 0 : blk(i - 1) + 1, hi = i == n ? nb : blk(i);
+  for (uint64_t b = lo; b <= hi; ++b) gs[b] = static_cast<uint32_t>(i);
+}
+
 // per block: shortcut count s and f = held + s
 __global__ __launch_bounds__(NT) void k_plan(const uint16_t *__restrict__ slots, uint64_t nb,
                                              const uint32_t *__restrict__ gs, uint32_t *__restrict__ ps,
@@ -374,21 +386,42 @@ __global__ __launch_bounds__(NT) void k_plan(const uint16_t *__restrict__ slots,
   pf[b] = held + s;
 }
 
-// each item not shortcut: its key for the second sort, the others SENT
+// The items not shortcut, with their keys for the second sort
+// (chosen << 40 | tag << 24 | other), packed at out[0, state[TS_CHOSEN]) in
+// no particular order (the sort orders them): one range per work-group.
 __global__ __launch_bounds__(NT) void k_choose(const uint64_t *__restrict__ s1, uint64_t n,
                                                const uint32_t *__restrict__ gs, const uint32_t *__restrict__ ps,
-                                               const uint32_t *__restrict__ pf, uint64_t *__restrict__ out) {
+                                               const uint32_t *__restrict__ pf, uint64_t *__restrict__ out,
+                                               uint64_t *state) {
+  __shared__ uint32_t wc[NT / 64];
+  __shared__ uint64_t base;
   const uint64_t i = static_cast<uint64_t>(blockIdx.x) * NT + threadIdx.x;
-  if (i >= n) return;
-  const uint64_t c = s1[i];
-  const uint32_t b1 = static_cast<uint32_t>(c >> 40), tag = static_cast<uint32_t>((c >> 24) & 0xFFFF);
-  const uint32_t b2 = static_cast<uint32_t>(c & 0xFFFFFF);
-  if (i - gs[b1] < ps[b1]) {
-    out[i] = SENT;
-    return;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  bool chosen = false;
+  uint64_t key = 0;
+  if (i < n) {
+    const uint64_t c = s1[i];
+    const uint32_t b1 = static_cast<uint32_t>(c >> 40), tag = static_cast<uint32_t>((c >> 24) & 0xFFFF);
+    const uint32_t b2 = static_cast<uint32_t>(c & 0xFFFFFF);
+    if (i - gs[b1] >= ps[b1]) {
+      chosen = true;
+      key = pf[b1] <= pf[b2] ? comp_of(b1, tag, b2) : comp_of(b2, tag, b1);
+    }
   }
-  const bool first = pf[b1] <= pf[b2];
-  out[i] = first ? comp_of(b1, tag, b2) : comp_of(b2, tag, b1);
+  const uint64_t bal = __ballot(chosen);
+  if (lane == 0) wc[w] = static_cast<uint32_t>(popc64(bal));
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t tot = 0;
+    for (int k = 0; k < NT / 64; ++k) {
+      const uint32_t c = wc[k];
+      wc[k] = tot;
+      tot += c;
+    }
+    base = tot ? qf::atomic_add_u64(&state[TS_CHOSEN], tot) : 0;
+  }
+  __syncthreads();
+  if (chosen) out[base + wc[w] + popc64(bal & ((1ull << lane) - 1ull))] = key;
 }
 
 // items beyond each block's free slots: their total in state[TS_OVER]
@@ -417,7 +450,9 @@ __global__ __launch_bounds__(NT) void k_merge_blocks(uint16_t *slots, uint64_t n
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint64_t b = static_cast<uint64_t>(blockIdx.x) * 4 + w;
   uint32_t ha = 0, ns = 0, nc = 0;
-  if (b < nb) {
+  // (a block that receives nothing is neither read nor written)
+  const bool touched = b < nb && (ps[b] != 0 || gs2[b + 1] != gs2[b]);
+  if (touched) {
     ns = ps[b];
     ha = pf[b] - ns;
     const uint32_t got = gs2[b + 1] - gs2[b], room = BB - pf[b];
@@ -437,7 +472,7 @@ __global__ __launch_bounds__(NT) void k_merge_blocks(uint16_t *slots, uint64_t n
   }
   __syncthreads();
   const uint32_t tot = ha + ns + nc;
-  if (b < nb) {
+  if (touched) {
     for (uint32_t j = lane; j < tot; j += 64) {
       uint32_t x, pos;
       if (j < ha) {
@@ -456,7 +491,7 @@ __global__ __launch_bounds__(NT) void k_merge_blocks(uint16_t *slots, uint64_t n
     }
   }
   __syncthreads();
-  if (b < nb) {
+  if (touched) {
     const uint32_t i0 = 2 * lane, i1 = 2 * lane + 1;
     const uint32_t lo = i0 < tot ? O[w][i0] : EMPTY_B, hi = i1 < tot ? O[w][i1] : EMPTY_B;
     reinterpret_cast<uint32_t *>(slots + b * BB)[lane] = lo | (hi << 16);
@@ -479,7 +514,9 @@ __global__ __launch_bounds__(NT) void k_del_step(uint16_t *slots, uint64_t nb, c
   const uint64_t b = static_cast<uint64_t>(blockIdx.x) * 4 + w;  // (uniform over the wave)
   int64_t done = 0;
   uint32_t tot = 0, held = 0;
-  if (b < nb) {
+  // (a block with no keys in this step is neither read nor written)
+  const bool touched = b < nb && gs[b + 1] != gs[b];
+  if (touched) {
     const uint32_t v = reinterpret_cast<const uint32_t *>(slots + b * BB)[lane];
     A[w][2 * lane] = static_cast<uint16_t>(v & 0xFFFF);
     A[w][2 * lane + 1] = static_cast<uint16_t>(v >> 16);
@@ -487,7 +524,7 @@ __global__ __launch_bounds__(NT) void k_del_step(uint16_t *slots, uint64_t nb, c
     R[w][2 * lane + 1] = 0;
   }
   __syncthreads();
-  if (b < nb) {
+  if (touched) {
     held = lb16(A[w], BB, EMPTY_B);
     const uint64_t *grp = L + gs[b];
     const uint64_t gn = gs[b + 1] - gs[b];
@@ -507,7 +544,7 @@ __global__ __launch_bounds__(NT) void k_del_step(uint16_t *slots, uint64_t nb, c
     }
   }
   __syncthreads();
-  if (b < nb) {
+  if (touched) {
     // the kept tags, in order: exclusive scan of the per-lane counts
     const uint32_t i0 = 2 * lane, i1 = 2 * lane + 1;
     const uint32_t keep0 = i0 < held && !R[w][i0] ? 1u : 0u, keep1 = i1 < held && !R[w][i1] ? 1u : 0u;
@@ -523,7 +560,7 @@ __global__ __launch_bounds__(NT) void k_del_step(uint16_t *slots, uint64_t nb, c
     if (keep1) O[w][pos] = A[w][i1];
   }
   __syncthreads();
-  if (b < nb) {
+  if (touched) {
     const uint32_t i0 = 2 * lane, i1 = 2 * lane + 1;
     const uint32_t lo = i0 < tot ? O[w][i0] : EMPTY_B, hi = i1 < tot ? O[w][i1] : EMPTY_B;
     reinterpret_cast<uint32_t *>(slots + b * BB)[lane] = lo | (hi << 16);
@@ -685,23 +722,44 @@ int sort64(tcf_filter *t, uint64_t *a, uint64_t *b, uint64_t n, hipStream_t s) {
   return QF_OK;
 }
 
+// group bounds of sorted keys s[0, n): a scatter from the keys when they are
+// dense (no SENT entries and at least one per block on average: every thread
+// then writes a few entries), else a binary search per block (a scatter over
+// a sparse list would leave one thread to fill the long gaps)
+void group_bounds(tcf_filter *t, const uint64_t *s_, uint64_t n, uint32_t *gs, hipStream_t s, bool dense) {
+  using namespace tcf;
+  if (dense && n >= t->nb)
+    k_gbounds_scatter<<<blocks_for(n + 1), NT, 0, s>>>(s_, n, t->nb, gs);
+  else
+    k_gbounds<<<blocks_for(t->nb + 1), NT, 0, s>>>(s_, n, t->nb, gs);
+}
+
 int bulk_insert(tcf_filter *t, const uint64_t *keys, uint64_t n, hipStream_t s) {
   using namespace tcf;
   if (int rc = ensure_batch(t, n, s)) return rc;
   k_compose<<<blocks_for(n), NT, 0, s>>>(keys, n, t->nb, t->bufA);
   if (int rc = sort64(t, t->bufA, t->bufB, n, s)) return rc;
-  const uint32_t gb = blocks_for(t->nb + 1);
-  k_gbounds<<<gb, NT, 0, s>>>(t->bufA, n, t->nb, t->gs1);
+  group_bounds(t, t->bufA, n, t->gs1, s, true);
   k_plan<<<blocks_for(t->nb), NT, 0, s>>>(t->slots, t->nb, t->gs1, t->ps, t->pf);
-  k_choose<<<blocks_for(n), NT, 0, s>>>(t->bufA, n, t->gs1, t->ps, t->pf, t->bufC);
-  if (int rc = sort64(t, t->bufC, t->bufB, n, s)) return rc;
-  k_gbounds<<<gb, NT, 0, s>>>(t->bufC, n, t->nb, t->gs2);
-  k_set_words<<<1, 64, 0, s>>>(t->state, TS_OVER, 2, 0ull);
-  k_over<<<blocks_for(t->nb), NT, 0, s>>>(t->nb, t->gs2, t->pf, t->state);
-  TCF_HIP(hipMemcpyAsync(t->h_words, t->state + TS_OVER, 8, hipMemcpyDeviceToHost, s));
+  k_set_words<<<1, 64, 0, s>>>(t->state, TS_OVER, 4, 0ull);  // TS_OVER .. TS_CHOSEN
+  k_choose<<<blocks_for(n), NT, 0, s>>>(t->bufA, n, t->gs1, t->ps, t->pf, t->bufC, t->state);
+  TCF_HIP(hipMemcpyAsync(t->h_words, t->state + TS_CHOSEN, 8, hipMemcpyDeviceToHost, s));
   TCF_HIP(hipStreamSynchronize(s));
-  const uint64_t over = t->h_words[0];
-  if (t->bn + over > t->nbt) return qf::record_error(QF_ERR_FULL);
+  // only the items that did not take the shortcut are sorted again (none
+  // while every block is below 3/4 of its slots)
+  const uint64_t m = t->h_words[0];
+  uint64_t over = 0;
+  if (m) {
+    if (int rc = sort64(t, t->bufC, t->bufB, m, s)) return rc;
+    group_bounds(t, t->bufC, m, t->gs2, s, true);
+    k_over<<<blocks_for(t->nb), NT, 0, s>>>(t->nb, t->gs2, t->pf, t->state);
+    TCF_HIP(hipMemcpyAsync(t->h_words, t->state + TS_OVER, 8, hipMemcpyDeviceToHost, s));
+    TCF_HIP(hipStreamSynchronize(s));
+    over = t->h_words[0];
+    if (t->bn + over > t->nbt) return qf::record_error(QF_ERR_FULL);
+  } else {
+    group_bounds(t, t->bufC, 0, t->gs2, s, false);  // all zero: no chosen items
+  }
   k_merge_blocks<<<static_cast<uint32_t>((t->nb + 3) / 4), NT, 0, s>>>(
       t->slots, t->nb, t->bufA, t->gs1, t->bufC, t->gs2, t->ps, t->pf, t->backing, t->bn, t->state);
   if (over) {
@@ -717,13 +775,13 @@ int bulk_insert(tcf_filter *t, const uint64_t *keys, uint64_t n, hipStream_t s) 
 int bulk_delete(tcf_filter *t, const uint64_t *keys, uint64_t n, uint64_t *not_found, hipStream_t s) {
   using namespace tcf;
   if (int rc = ensure_batch(t, n, s)) return rc;
-  const uint32_t gb = blocks_for(t->nb + 1), mb = static_cast<uint32_t>((t->nb + 3) / 4);
+  const uint32_t mb = static_cast<uint32_t>((t->nb + 3) / 4);
   k_compose<<<blocks_for(n), NT, 0, s>>>(keys, n, t->nb, t->bufA);
   if (int rc = sort64(t, t->bufA, t->bufB, n, s)) return rc;
-  k_gbounds<<<gb, NT, 0, s>>>(t->bufA, n, t->nb, t->gs1);
+  group_bounds(t, t->bufA, n, t->gs1, s, true);
   k_del_step<1><<<mb, NT, 0, s>>>(t->slots, t->nb, t->bufA, n, t->gs1, t->bufC, t->state);
   if (int rc = sort64(t, t->bufC, t->bufB, n, s)) return rc;
-  k_gbounds<<<gb, NT, 0, s>>>(t->bufC, n, t->nb, t->gs2);
+  group_bounds(t, t->bufC, n, t->gs2, s, false);
   k_del_step<2><<<mb, NT, 0, s>>>(t->slots, t->nb, t->bufC, n, t->gs2, t->bufA, t->state);
   if (int rc = sort64(t, t->bufA, t->bufB, n, s)) return rc;
   k_held_after_delete<<<1, 64, 0, s>>>(t->bufA, n, t->state);
