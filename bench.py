@@ -465,6 +465,82 @@ def bench_fill(args) -> dict:
             "insert_s": round(times[-1], 4), "query_Bps": round(m / tq / 1e9, 4)}
 
 
+def bench_tcf(args) -> dict:
+    """The two-choice filter at 2^28 slots (the size of the paper's CPU/GPU table, Sec. 6):
+    point form (16-tag blocks) filled to load 0.9 by 2^24-key point calls, then 2^24 positive
+    and 2^24 random (absent) lookups and 2^24 deletes; bulk form (128-tag sorted blocks) filled
+    to load 0.9 by one batch and, on a second filter, by batches of 2^22 keys, then the same
+    lookups.  Every present key must be found."""
+    import torch
+
+    from paper_2212_09005_amd import inputs, tcf
+
+    slots = 1 << 28
+    n = int(0.9 * slots)
+    m = 1 << 24
+
+    def dev(a):
+        return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to("cuda")
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    keys = inputs.uniform_keys(1, n)
+    d = dev(keys)
+    absent = dev(inputs.absent_keys(2, m))
+    pos = dev(keys[:m])
+    out = torch.empty(m, dtype=torch.uint8, device="cuda")
+    res = {}
+    # point form
+    t = tcf.TCF(slots // 16, tcf.TCF_POINT)
+    warm = dev(inputs.uniform_keys(3, 1 << 16))
+    t.insert(warm)
+    t.delete(warm)
+    ti = sum(timed(lambda lo=lo: t.insert(d[lo:lo + m])) for lo in range(0, n, m))
+    assert t.sync() == 0
+    tq = timed(lambda: t.query(pos, out))
+    assert bool(out.all().item()), "point TCF: a present key was not found"
+    tr = timed(lambda: t.query(absent, out))
+    fp = int(out.sum().item())
+    nf = torch.zeros(1, dtype=torch.int64, device="cuda")
+    td = timed(lambda: t.delete(pos, not_found=nf))
+    info = t.info()
+    res["point"] = {"insert_Bps": round(n / ti / 1e9, 3), "query_pos_Bps": round(m / tq / 1e9, 3),
+                    "query_rand_Bps": round(m / tr / 1e9, 3), "delete_Bps": round(m / td / 1e9, 3),
+                    "false_pos_rate": round(fp / m, 6), "backing_fraction": round(info["backing_used"] / n, 6),
+                    "deletes_not_found": int(nf.item())}
+    t.close()
+    # bulk form, one batch
+    t = tcf.TCF(slots // 128, tcf.TCF_BULK)
+    t.insert(warm)
+    t.delete(warm)
+    ti = timed(lambda: t.insert(d))
+    tq = timed(lambda: t.query(pos, out))
+    assert bool(out.all().item()), "bulk TCF: a present key was not found"
+    tr = timed(lambda: t.query(absent, out))
+    fp = int(out.sum().item())
+    td = timed(lambda: t.delete(pos[: 1 << 22]))
+    res["bulk_one_batch"] = {"insert_Bps": round(n / ti / 1e9, 3), "query_pos_Bps": round(m / tq / 1e9, 3),
+                             "query_rand_Bps": round(m / tr / 1e9, 3),
+                             "delete_2p22_Bps": round((1 << 22) / td / 1e9, 3), "false_pos_rate": round(fp / m, 6)}
+    t.close()
+    # bulk form, batches of 2^22
+    t = tcf.TCF(slots // 128, tcf.TCF_BULK)
+    b = 1 << 22
+    ti = sum(timed(lambda lo=lo: t.insert(d[lo:lo + b])) for lo in range(0, n, b))
+    res["bulk_batches_2p22"] = {"insert_Bps": round(n / ti / 1e9, 3)}
+    t.close()
+    return {"metric": "two-choice filter at 2^28 slots: point and bulk insert / lookup rates",
+            "value": res["point"]["insert_Bps"], "unit": "B point inserts/s", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "u64", "data": "synthetic",
+            "config": {"workload": "tcf_2p28_slots_load_0.9", "slots": slots, "keys": n, "lookups": m},
+            **res}
+
+
 def bench_serve(args) -> dict:
     """Serving: 256 device-resident filters (2^18..2^26 quotients, r = 8 or 16), filled to load 0.5,
     answer Poisson arrivals of mixed requests (70 % query, 25 % insert, 5 % delete) with sizes
@@ -608,10 +684,10 @@ def main() -> int:
     ap.add_argument("--load", type=float, default=0.9)
     ap.add_argument("--batch-log2", type=int, default=22)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["c2", "sweep", "fill", "zipf", "c4", "serve"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "sweep", "fill", "zipf", "c4", "serve", "tcf"], default="c2",
                     help="c2: the single-filter step (default); sweep: load sweep to 0.95; fill: one-batch fill "
                          "to 0.9; zipf: one-batch counting with skew (2^30, r=16); c4: many filters, set vs "
-                         "per-filter loop; serve: the serving loop")
+                         "per-filter loop; serve: the serving loop; tcf: the two-choice filter at 2^28 slots")
     ap.add_argument("--serve-filters", type=int, default=256)
     ap.add_argument("--serve-requests", type=int, default=4000)
     ap.add_argument("--zipf-scale", type=int, default=0)
@@ -635,7 +711,7 @@ def main() -> int:
         assert torch.cuda.is_available(), "bench.py needs a GPU"
         torch.cuda.set_device(0)
         fn = {"c4": bench_sets, "sweep": bench_sweep, "fill": bench_fill, "zipf": bench_zipf,
-              "serve": bench_serve}[args.workload]
+              "serve": bench_serve, "tcf": bench_tcf}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return 0
 
