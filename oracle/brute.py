@@ -221,6 +221,32 @@ def layout(ufp: np.ndarray, cnt: np.ndarray, q: int, r: int) -> Layout:
     return Layout(occ_words, rend_words, slots, offsets, header)
 
 
+def kv_fingerprints(keys: np.ndarray, values: np.ndarray, q: int, r: int, vbits: int) -> np.ndarray:
+    """Value association (the library's reading; the paper names the feature
+    only): the key's fingerprint of q + r - vbits bits followed by the value's
+    low vbits bits, a p = q + r bit fingerprint of the pair."""
+    fk = fingerprints(keys, q, r - vbits)
+    return (fk << U64(vbits)) | (np.asarray(values, dtype=U64) & U64((1 << vbits) - 1))
+
+
+def kv_lookup(ufp: np.ndarray, cnt: np.ndarray, keys: np.ndarray, q: int, r: int, vbits: int):
+    """Per key: the smallest value stored with its fingerprint (2^64 - 1 when
+    none) and the number of distinct values, from the multiset {ufp: cnt} of
+    pair fingerprints (the pairs of one key fingerprint fk are the fingerprints
+    in [fk << vbits, (fk << vbits) + 2^vbits - 1])."""
+    ufp = np.asarray(ufp, dtype=U64)
+    lo = fingerprints(keys, q, r - vbits) << U64(vbits)
+    hi = lo | U64((1 << vbits) - 1)
+    a = np.searchsorted(ufp, lo, "left")
+    b = np.searchsorted(ufp, hi, "right")
+    n = (b - a).astype(np.int64)
+    val = np.full(len(lo), np.iinfo(np.uint64).max, dtype=U64)
+    hit = n > 0
+    if len(ufp):
+        val[hit] = ufp[a[hit]] & U64((1 << vbits) - 1)
+    return val, n
+
+
 def counts_of(ufp: np.ndarray, cnt: np.ndarray, fps: np.ndarray) -> np.ndarray:
     """Multiplicity of each queried fingerprint (0 when absent)."""
     fps = np.asarray(fps, dtype=U64)

@@ -431,3 +431,37 @@ def test_block_counts_match_brute_force():
             s, e = runs[x]
             touched.update(range(s // 64, e // 64 + 1))
     assert brute.query_blocks(L1, fps) == len(touched)
+
+
+# ------------------------------------------------------- value association ----
+def test_kv_lookup_by_hand_and_by_brute_force():
+    # q = 2, r = 8, vbits = 3: a pair's fingerprint is the key's 7-bit
+    # fingerprint (2 + 5 bits) then 3 value bits.  Keys crafted for key
+    # fingerprints 0b0010110 and 0b1100001.
+    q, r, v = 2, 8, 3
+    ka = keys_for_fingerprints(np.array([0b0010110], dtype=U64), q, r - v, seed=1)[0]
+    kb = keys_for_fingerprints(np.array([0b1100001], dtype=U64), q, r - v, seed=2)[0]
+    keys = np.array([ka, ka, ka, kb, ka], dtype=U64)
+    vals = np.array([5, 2, 5, 7, 11], dtype=U64)  # 11 mod 8 = 3
+    fps = brute.kv_fingerprints(keys, vals, q, r, v)
+    assert [int(x) for x in fps] == [0b0010110101, 0b0010110010, 0b0010110101, 0b1100001111, 0b0010110011]
+    ufp, cnt = brute.multiset(fps)
+    absent = keys_for_fingerprints(np.array([0b0010111], dtype=U64), q, r - v, seed=3)
+    val, n = brute.kv_lookup(ufp, cnt, np.concatenate([[ka, kb], absent]), q, r, v)
+    # key a holds values {2, 3, 5} (5 twice), key b holds {7}, the third none
+    assert [int(x) for x in val] == [2, 7, 2**64 - 1] and list(n) == [3, 1, 0]
+    # brute force over random pairs: per key fingerprint, the set of values
+    g = np.random.Generator(np.random.PCG64(4))
+    q, r, v = 6, 16, 5
+    keys = inputs.uniform_keys(5, 300)[g.integers(0, 300, size=2000)]
+    vals = g.integers(0, 1 << 12, size=2000).astype(U64)
+    ufp, cnt = brute.multiset(brute.kv_fingerprints(keys, vals, q, r, v))
+    fk = brute.fingerprints(keys, q, r - v)
+    want = {}
+    for k, x in zip(fk.tolist(), (vals & U64(31)).tolist()):
+        want.setdefault(k, set()).add(x)
+    probe = np.concatenate([keys[:500], inputs.absent_keys(6, 200)])
+    val, n = brute.kv_lookup(ufp, cnt, probe, q, r, v)
+    for k, x, c in zip(brute.fingerprints(probe, q, r - v).tolist(), val.tolist(), n.tolist()):
+        s = want.get(k, set())
+        assert c == len(s) and (x == min(s) if s else x == 2**64 - 1)
