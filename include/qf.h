@@ -212,6 +212,36 @@ int qf_merge_into(qf_t *dst, qf_t *src, int subtract, uint64_t *d_not_found, voi
  * the multiset does not fit the new table). */
 qf_t *qf_resize(qf_t *src, uint32_t q, uint32_t r, void *stream);
 
+/* ---- value association --------------------------------------------------
+ * The paper names value association among the CQF's features (Sec. 1, 2)
+ * without describing it.  Here a filter made by qf_create_kv keeps a small
+ * value with every key: the slot's r bits hold the key's remainder of
+ * r - vbits bits followed by vbits value bits, so the table stores the
+ * multiset of <key fingerprint (q + r - vbits bits), value> pairs, one entry
+ * per distinct pair with its count, and stays the canonical table of that
+ * multiset (qf_export).  A key may carry several values; the false-positive
+ * rate is that of a plain filter with r - vbits remainder bits.  On such a
+ * filter the plain insert / delete / query / count / point calls and filter
+ * sets return QF_ERR_ARG; qf_stats, qf_enumerate (pairs as composite
+ * fingerprints), qf_merge_into (both with the same vbits) and qf_resize
+ * (which keeps vbits; r must exceed it) work as for plain filters. */
+
+/* A value-associating filter: 1 <= vbits < r, r in {8, 16}, q as qf_create. */
+qf_t *qf_create_kv(uint32_t q, uint32_t r, uint32_t vbits);
+
+/* Insert / delete the pairs <d_keys[i], d_values[i] mod 2^vbits> as a batch
+ * (all or nothing, errors deferred to qf_sync, as qf_insert_batch /
+ * qf_delete_batch; not-found pairs ADDED to *d_not_found, may be NULL). */
+int qf_kv_insert_batch(qf_t *f, const uint64_t *d_keys, const uint64_t *d_values, uint64_t n, void *stream);
+int qf_kv_delete_batch(qf_t *f, const uint64_t *d_keys, const uint64_t *d_values, uint64_t n,
+                       uint64_t *d_not_found, void *stream);
+
+/* d_value[i] = the smallest value stored with key i's fingerprint, or
+ * 2^64 - 1 when there is none; d_nvalues[i] (uint32, may be NULL) = how many
+ * distinct values are stored with it. */
+int qf_kv_lookup_batch(qf_t *f, const uint64_t *d_keys, uint64_t n, uint64_t *d_value, uint32_t *d_nvalues,
+                       void *stream);
+
 /* ---- point updates (Sec. 5.2; the point rows of the API table of Sec. 6) --
  * One lane per key, in place on the current table: the keys of one call are
  * applied concurrently and in no set order, each under region locks (4096

@@ -211,9 +211,12 @@ bool capturing(hipStream_t s) {
 
 // hash -> radix sort -> reduction -> region bounds -> merge, on stream s.
 // fid == nullptr: the pipeline has one filter and keys are its own.
+// values != nullptr (one filter): value association, the fingerprints are
+// the keys' q + r - vbits bit fingerprints followed by the values' low bits.
 int pipe_update(qf::Pipe &p, const uint64_t *keys, const uint32_t *fid, uint64_t n, int del,
                 uint64_t *not_found, hipStream_t s, uint32_t single_q, const qf_set *set = nullptr,
-                const uint32_t *h_active = nullptr, uint32_t nactive = 0) {
+                const uint32_t *h_active = nullptr, uint32_t nactive = 0, const uint64_t *values = nullptr,
+                uint32_t vbits = 0) {
   // under capture: scratch must be reserved, lists and timers are refused
   if (capturing(s) && (n > p.cap || h_active || p.timer)) return fail(QF_ERR_ARG);
   int rc = ensure_scratch(p, n, s);
@@ -241,14 +244,19 @@ int pipe_update(qf::Pipe &p, const uint64_t *keys, const uint32_t *fid, uint64_t
   // hashes the keys on its first read
   const uint32_t bits = fid ? p.gbits + p.RL + p.r : single_q + p.r;
   const uint64_t pmask = bits >= 64 ? ~0ull : ((1ull << bits) - 1ull);
+  // pre: the fingerprints (or composite keys) are computed into bufA first
+  const bool pre = fid || values;
   if (fid) QF_HIP(qf::launch_hash_multi(keys, fid, n, p, p.bufA, s, p.timer));
+  if (values) {
+    const uint32_t kb = single_q + p.r - vbits;
+    QF_HIP(qf::launch_kv_compose(keys, values, n, (1ull << kb) - 1ull, vbits, p.bufA, s, p.timer));
+  }
   if (n <= qf::SMALL_KEYS) {
     // small batch: sort and reduction in one work-group
-    QF_HIP(qf::launch_small_prep(fid ? p.bufA : keys, n, bits, pmask, fid == nullptr, p.bufC, p.bufD, p.pst, s,
-                                 p.timer));
+    QF_HIP(qf::launch_small_prep(pre ? p.bufA : keys, n, bits, pmask, !pre, p.bufC, p.bufD, p.pst, s, p.timer));
   } else {
     uint64_t *sorted = nullptr;
-    if (fid)
+    if (pre)
       QF_HIP(qf::launch_sort(p.bufA, p.bufB, n, bits, p.hist, &sorted, s, p));
     else
       QF_HIP(qf::launch_sort(p.bufA, p.bufB, n, bits, p.hist, &sorted, s, p, keys, pmask));
@@ -265,7 +273,7 @@ int check_filter(const qf_filter *f) { return f ? QF_OK : fail(QF_ERR_ARG); }
 
 int update(qf_filter *f, const uint64_t *keys, uint64_t n, int del, uint64_t *not_found,
            void *stream) {
-  if (!f || (n && !keys)) return fail(QF_ERR_ARG);
+  if (!f || (n && !keys) || f->vbits) return fail(QF_ERR_ARG);
   if (n == 0) return QF_OK;
   if (n > 0xFFFFFFFFull) return fail(QF_ERR_ARG);
   return pipe_update(f->pipe, keys, nullptr, n, del, not_found, static_cast<hipStream_t>(stream), f->q);
@@ -531,7 +539,7 @@ int qf_insert_batch(qf_t *f, const uint64_t *d_keys, uint64_t n, void *stream) {
 }
 
 int qf_insert_batch_noalloc(qf_t *f, const uint64_t *d_keys, uint64_t n, void *stream) {
-  if (!f || (n && !d_keys)) return fail(QF_ERR_ARG);
+  if (!f || (n && !d_keys) || f->vbits) return fail(QF_ERR_ARG);
   if (n == 0) return QF_OK;
   if (n > QF_NOALLOC_KEYS) return fail(QF_ERR_LIMIT);
   uint8_t *base = nullptr;
@@ -575,7 +583,7 @@ int qf_delete_batch(qf_t *f, const uint64_t *d_keys, uint64_t n, uint64_t *d_not
 }
 
 int qf_point_insert(qf_t *f, const uint64_t *d_keys, uint64_t n, int32_t *d_status, void *stream) {
-  if (!f || (n && !d_keys)) return fail(QF_ERR_ARG);
+  if (!f || (n && !d_keys) || f->vbits) return fail(QF_ERR_ARG);
   if (n == 0) return QF_OK;
   QF_HIP(qf::launch_point(f, d_keys, n, 0, d_status, nullptr, static_cast<hipStream_t>(stream)));
   return QF_OK;
@@ -583,23 +591,58 @@ int qf_point_insert(qf_t *f, const uint64_t *d_keys, uint64_t n, int32_t *d_stat
 
 int qf_point_delete(qf_t *f, const uint64_t *d_keys, uint64_t n, int32_t *d_status, uint64_t *d_not_found,
                     void *stream) {
-  if (!f || (n && !d_keys)) return fail(QF_ERR_ARG);
+  if (!f || (n && !d_keys) || f->vbits) return fail(QF_ERR_ARG);
   if (n == 0) return QF_OK;
   QF_HIP(qf::launch_point(f, d_keys, n, 1, d_status, d_not_found, static_cast<hipStream_t>(stream)));
   return QF_OK;
 }
 
 int qf_query_batch(qf_t *f, const uint64_t *d_keys, uint64_t n, uint8_t *d_out, void *stream) {
-  if (!f || (n && (!d_keys || !d_out))) return fail(QF_ERR_ARG);
+  if (!f || (n && (!d_keys || !d_out)) || f->vbits) return fail(QF_ERR_ARG);
   if (n == 0) return QF_OK;
   QF_HIP(qf::launch_lookup(f, d_keys, n, d_out, nullptr, static_cast<hipStream_t>(stream)));
   return QF_OK;
 }
 
 int qf_count_batch(qf_t *f, const uint64_t *d_keys, uint64_t n, uint64_t *d_out, void *stream) {
-  if (!f || (n && (!d_keys || !d_out))) return fail(QF_ERR_ARG);
+  if (!f || (n && (!d_keys || !d_out)) || f->vbits) return fail(QF_ERR_ARG);
   if (n == 0) return QF_OK;
   QF_HIP(qf::launch_lookup(f, d_keys, n, nullptr, d_out, static_cast<hipStream_t>(stream)));
+  return QF_OK;
+}
+
+qf_t *qf_create_kv(uint32_t q, uint32_t r, uint32_t vbits) {
+  if (vbits < 1 || vbits >= r) {
+    fail(QF_ERR_ARG);
+    return nullptr;
+  }
+  qf_t *f = qf_create(q, r);
+  if (f) f->vbits = vbits;
+  return f;
+}
+
+int qf_kv_insert_batch(qf_t *f, const uint64_t *d_keys, const uint64_t *d_values, uint64_t n, void *stream) {
+  if (!f || !f->vbits || (n && (!d_keys || !d_values))) return fail(QF_ERR_ARG);
+  if (n == 0) return QF_OK;
+  if (n > 0xFFFFFFFFull) return fail(QF_ERR_ARG);
+  return pipe_update(f->pipe, d_keys, nullptr, n, 0, nullptr, static_cast<hipStream_t>(stream), f->q, nullptr,
+                     nullptr, 0, d_values, f->vbits);
+}
+
+int qf_kv_delete_batch(qf_t *f, const uint64_t *d_keys, const uint64_t *d_values, uint64_t n,
+                       uint64_t *d_not_found, void *stream) {
+  if (!f || !f->vbits || (n && (!d_keys || !d_values))) return fail(QF_ERR_ARG);
+  if (n == 0) return QF_OK;
+  if (n > 0xFFFFFFFFull) return fail(QF_ERR_ARG);
+  return pipe_update(f->pipe, d_keys, nullptr, n, 1, d_not_found, static_cast<hipStream_t>(stream), f->q, nullptr,
+                     nullptr, 0, d_values, f->vbits);
+}
+
+int qf_kv_lookup_batch(qf_t *f, const uint64_t *d_keys, uint64_t n, uint64_t *d_value, uint32_t *d_nvalues,
+                       void *stream) {
+  if (!f || !f->vbits || (n && (!d_keys || !d_value))) return fail(QF_ERR_ARG);
+  if (n == 0) return QF_OK;
+  QF_HIP(qf::launch_kv_lookup(f, d_keys, n, d_value, d_nvalues, static_cast<hipStream_t>(stream)));
   return QF_OK;
 }
 
@@ -713,7 +756,7 @@ int qf_enumerate(qf_t *f, uint64_t *d_fp, uint64_t *d_cnt, uint64_t cap, uint64_
 }
 
 int qf_merge_into(qf_t *dst, qf_t *src, int subtract, uint64_t *d_not_found, void *stream) {
-  if (!dst || !src || dst->q + dst->r != src->q + src->r) return fail(QF_ERR_ARG);
+  if (!dst || !src || dst->q + dst->r != src->q + src->r || dst->vbits != src->vbits) return fail(QF_ERR_ARG);
   const hipStream_t s = static_cast<hipStream_t>(stream);
   uint64_t st[qf::ST_WORDS];
   QF_HIP(hipStreamSynchronize(s));
@@ -742,12 +785,13 @@ int qf_merge_into(qf_t *dst, qf_t *src, int subtract, uint64_t *d_not_found, voi
 }
 
 qf_t *qf_resize(qf_t *src, uint32_t q, uint32_t r, void *stream) {
-  if (!src || q + r != src->q + src->r) {
+  if (!src || q + r != src->q + src->r || r <= src->vbits) {
     fail(QF_ERR_ARG);
     return nullptr;
   }
   qf_t *dst = qf_create(q, r);
   if (!dst) return nullptr;
+  dst->vbits = src->vbits;
   const int rc = qf_merge_into(dst, src, 0, nullptr, stream);
   if (rc == QF_OK) {
     const int e = qf_sync(dst, stream);
@@ -787,7 +831,7 @@ qf_set_t *qf_set_create(qf_t *const *filters, uint32_t nf) {
     }
   }
   for (uint32_t i = 0; i < nf; ++i) {
-    if (filters[i]->r != filters[0]->r) {
+    if (filters[i]->r != filters[0]->r || filters[i]->vbits) {
       fail(QF_ERR_ARG);
       return nullptr;
     }

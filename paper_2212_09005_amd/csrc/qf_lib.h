@@ -80,6 +80,7 @@ struct qf_filter {
   uint64_t *state;          // qf::ST_WORDS device words
   uint64_t table_device_bytes;
   uint32_t *plocks;         // point updates: one lock word per 4096 slots (zero = free)
+  uint32_t vbits;           // value association: value bits at the low end of each remainder (0: none)
   qf::Pipe pipe;            // the single-filter update pipeline
 };
 
@@ -96,6 +97,12 @@ uint64_t table_bytes(uint64_t nblocks, uint32_t r);
 
 hipError_t launch_hash(const uint64_t *keys, uint64_t n, uint64_t pmask, uint64_t *fp,
                        hipStream_t s, Timer *t);
+// value association: fp[i] = (hash(keys[i]) & kmask) << vbits | (values[i] & (2^vbits - 1))
+hipError_t launch_kv_compose(const uint64_t *keys, const uint64_t *values, uint64_t n, uint64_t kmask,
+                             uint32_t vbits, uint64_t *fp, hipStream_t s, Timer *t);
+// value association lookups: smallest value (or ~0) and number of distinct values per key
+hipError_t launch_kv_lookup(qf_filter *f, const uint64_t *keys, uint64_t n, uint64_t *value, uint32_t *nvalues,
+                            hipStream_t s);
 // composite keys of a filter set: key i belongs to filter fid[i]
 hipError_t launch_hash_multi(const uint64_t *keys, const uint32_t *fid, uint64_t n, const Pipe &p,
                              uint64_t *out, hipStream_t s, Timer *t);

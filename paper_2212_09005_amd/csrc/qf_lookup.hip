@@ -20,12 +20,14 @@ typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
+// The entries of quotient x's run in remainder order, each offered to
+// visit(remainder, count) until it returns true; returns whether x has a run.
 // ls: null, or the lane's LDS area of 64 bytes (r = 8 only) that receives the
 // home block's slots, requested with its header: the run's slots then come
 // from LDS unless the run lies (partly) in a later block.
-template <typename T>
-__device__ __forceinline__ uint64_t lookup_one(const Block<T> *__restrict__ b, int64_t nblocks,
-                                               int64_t x, uint64_t rem, uint32_t r, u32x4 *ls) {
+template <typename T, class V>
+__device__ __forceinline__ bool visit_run(const Block<T> *__restrict__ b, int64_t nblocks, int64_t x, uint32_t r,
+                                          u32x4 *ls, V &visit) {
   const int64_t bi = x >> 6;
   const int bit = static_cast<int>(x & 63);
   // the home block's occupied word, run-end word and offset, requested
@@ -45,7 +47,7 @@ __device__ __forceinline__ uint64_t lookup_one(const Block<T> *__restrict__ b, i
   // branch below, in flight with the first one, instead of after it)
   __asm__ volatile("" : : "v"(off));
   const uint64_t occ = h.x, rend0 = h.y;
-  if (!((occ >> bit) & 1ull)) return 0;
+  if (!((occ >> bit) & 1ull)) return false;
   int d = popc64(occ & ((2ull << bit) - 2ull));  // occupied quotients in (64*bi, x]
   const int64_t p = (bi << 6) + off;
   const auto rend_of = [&](int64_t w) -> uint64_t { return w == bi ? rend0 : b[w].rend; };
@@ -55,7 +57,7 @@ __device__ __forceinline__ uint64_t lookup_one(const Block<T> *__restrict__ b, i
   } else {
     // d-th run end strictly after p
     int64_t w = (p + 1) >> 6;
-    if (w >= nblocks) return 0;
+    if (w >= nblocks) return false;
     uint64_t m = rend_of(w) & (~0ull << ((p + 1) & 63));
     for (;;) {
       const int pc = popc64(m);
@@ -64,7 +66,7 @@ __device__ __forceinline__ uint64_t lookup_one(const Block<T> *__restrict__ b, i
         break;
       }
       d -= pc;
-      if (++w >= nblocks) return 0;
+      if (++w >= nblocks) return false;
       m = rend_of(w);
     }
   }
@@ -97,10 +99,54 @@ __device__ __forceinline__ uint64_t lookup_one(const Block<T> *__restrict__ b, i
   while (pos <= e) {
     uint64_t xr, c;
     pos = dec_entry(g, pos, e, r, xr, c);
-    if (xr == rem) return c;
-    if (xr > rem) return 0;
+    if (visit(xr, c)) break;
   }
-  return 0;
+  return true;
+}
+
+// the count of remainder rem in quotient x's run (0 if none)
+template <typename T>
+__device__ __forceinline__ uint64_t lookup_one(const Block<T> *__restrict__ b, int64_t nblocks,
+                                               int64_t x, uint64_t rem, uint32_t r, u32x4 *ls) {
+  uint64_t res = 0;
+  auto v = [&](uint64_t xr, uint64_t c) {
+    if (xr == rem) res = c;
+    return xr >= rem;
+  };
+  visit_run(b, nblocks, x, r, ls, v);
+  return res;
+}
+
+// Value association: the remainders of a key's entries are
+// (key remainder << vbits) | value, so the values of a key are the entries of
+// its run with remainders in [lo, lo + 2^vbits); the smallest and how many
+// distinct ones there are.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_kv_lookup(const Block<T> *b0, const Block<T> *b1, const uint64_t *state,
+                                                  const uint64_t *__restrict__ keys, uint64_t n, uint32_t q,
+                                                  uint32_t r, uint32_t vbits, int64_t nblocks,
+                                                  uint64_t *__restrict__ value, uint32_t *__restrict__ nvalues) {
+  const Block<T> *b = (state[ST_CUR] & 1ull) ? b1 : b0;
+  const uint32_t rk = r - vbits;  // key remainder bits
+  const uint64_t kmask = (1ull << (q + rk)) - 1ull, vmask = (1ull << vbits) - 1ull;
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * NT;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * NT + threadIdx.x; i < n; i += stride) {
+    const uint64_t fk = mix64(keys[i]) & kmask;
+    const uint64_t lo = (fk & ((1ull << rk) - 1ull)) << vbits, hi = lo | vmask;
+    uint64_t first = ~0ull;
+    uint32_t cnt = 0;
+    auto v = [&](uint64_t xr, uint64_t) {
+      if (xr > hi) return true;
+      if (xr >= lo) {
+        if (cnt == 0) first = xr & vmask;
+        ++cnt;
+      }
+      return false;
+    };
+    visit_run(b, nblocks, static_cast<int64_t>(fk >> rk), r, static_cast<u32x4 *>(nullptr), v);
+    value[i] = first;
+    if (nvalues) nvalues[i] = cnt;
+  }
 }
 
 // KPL keys per lane, NT apart (coalesced key loads and result stores; the
@@ -290,6 +336,20 @@ hipError_t launch_lookup(qf_filter *f, const uint64_t *keys, uint64_t n, uint8_t
                          uint64_t *out64, hipStream_t s) {
   if (f->r == 8) return lookup_t<uint8_t>(f, keys, n, out8, out64, s);
   return lookup_t<uint16_t>(f, keys, n, out8, out64, s);
+}
+
+hipError_t launch_kv_lookup(qf_filter *f, const uint64_t *keys, uint64_t n, uint64_t *value, uint32_t *nvalues,
+                            hipStream_t s) {
+  const int64_t nb = static_cast<int64_t>(f->nblocks);
+  if (f->r == 8)
+    k_kv_lookup<uint8_t><<<grid_for(n), NT, 0, s>>>(static_cast<const Block<uint8_t> *>(f->blk[0]),
+                                                    static_cast<const Block<uint8_t> *>(f->blk[1]), f->state, keys,
+                                                    n, f->q, f->r, f->vbits, nb, value, nvalues);
+  else
+    k_kv_lookup<uint16_t><<<grid_for(n), NT, 0, s>>>(static_cast<const Block<uint16_t> *>(f->blk[0]),
+                                                     static_cast<const Block<uint16_t> *>(f->blk[1]), f->state,
+                                                     keys, n, f->q, f->r, f->vbits, nb, value, nvalues);
+  return hipGetLastError();
 }
 
 hipError_t launch_export(qf_filter *f, uint64_t *occ, uint64_t *rend, uint16_t *slots,

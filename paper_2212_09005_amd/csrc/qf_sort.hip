@@ -36,6 +36,17 @@ __global__ __launch_bounds__(NT) void k_hash(const uint64_t *__restrict__ keys, 
     fp[i] = mix64(keys[i]) & pmask;
 }
 
+// Value association: the fingerprint of (key i, value i) is the key's
+// fingerprint of q + r - vbits bits followed by the value's low vbits bits.
+__global__ __launch_bounds__(NT) void k_kv_compose(const uint64_t *__restrict__ keys,
+                                                   const uint64_t *__restrict__ values, uint64_t n,
+                                                   uint64_t kmask, uint32_t vbits, uint64_t *__restrict__ fp) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * NT;
+  const uint64_t vmask = (1ull << vbits) - 1ull;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * NT + threadIdx.x; i < n; i += stride)
+    fp[i] = ((mix64(keys[i]) & kmask) << vbits) | (values[i] & vmask);
+}
+
 // Composite keys of a filter set: key i goes to filter fid[i]; its
 // fingerprint's region becomes a global region index in the high bits, the
 // fingerprint bits inside the region stay in the low RL + r bits.  A filter
@@ -621,6 +632,14 @@ hipError_t launch_hash(const uint64_t *keys, uint64_t n, uint64_t pmask, uint64_
                        hipStream_t s, Timer *t) {
   if (t) t->begin(QF_PROF_HASH, s);
   k_hash<<<blocks_for(n), NT, 0, s>>>(keys, n, pmask, fp);
+  if (t) t->end(QF_PROF_HASH, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_kv_compose(const uint64_t *keys, const uint64_t *values, uint64_t n, uint64_t kmask,
+                             uint32_t vbits, uint64_t *fp, hipStream_t s, Timer *t) {
+  if (t) t->begin(QF_PROF_HASH, s);
+  k_kv_compose<<<blocks_for(n), NT, 0, s>>>(keys, values, n, kmask, vbits, fp);
   if (t) t->end(QF_PROF_HASH, s);
   return hipGetLastError();
 }

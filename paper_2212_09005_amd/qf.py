@@ -124,6 +124,10 @@ def lib() -> ctypes.CDLL:
         "qf_count_batch": (i32, [vp, vp, u64, vp, vp]),
         "qf_delete_batch": (i32, [vp, vp, u64, vp, vp]),
         "qf_point_insert": (i32, [vp, vp, u64, vp, vp]),
+        "qf_create_kv": (vp, [u32, u32, u32]),
+        "qf_kv_insert_batch": (i32, [vp, vp, vp, u64, vp]),
+        "qf_kv_delete_batch": (i32, [vp, vp, vp, u64, vp, vp]),
+        "qf_kv_lookup_batch": (i32, [vp, vp, u64, vp, vp, vp]),
         "qf_point_delete": (i32, [vp, vp, u64, vp, vp, vp]),
         "qf_sync": (i32, [vp, vp]),
         "qf_export": (i32, [vp, ctypes.POINTER(_Layout), vp]),
@@ -367,6 +371,41 @@ class CQF:
     def delete(self, keys, not_found=None, stream=None):
         _check(qf_delete_batch(self.h, keys, not_found, stream), "qf_delete_batch")
 
+    @classmethod
+    def kv(cls, q: int, r: int, vbits: int) -> "CQF":
+        """qf_create_kv: a filter that keeps a vbits-bit value with every key."""
+        h = lib().qf_create_kv(q, r, vbits)
+        if not h:
+            raise QFError(lib().qf_last_error(), "qf_create_kv")
+        f = cls._own(h, q, r)
+        f.vbits = vbits
+        return f
+
+    def kv_insert(self, keys, values, stream=None):
+        n = keys.numel()
+        _check(lib().qf_kv_insert_batch(self.h, _dev_ptr(keys, n, 8) if n else None,
+                                        _dev_ptr(values, n, 8) if n else None, n, _stream(stream)),
+               "qf_kv_insert_batch")
+
+    def kv_delete(self, keys, values, not_found=None, stream=None):
+        n = keys.numel()
+        nf = _dev_ptr(not_found, 1, 8) if not_found is not None else None
+        _check(lib().qf_kv_delete_batch(self.h, _dev_ptr(keys, n, 8) if n else None,
+                                        _dev_ptr(values, n, 8) if n else None, n, nf, _stream(stream)),
+               "qf_kv_delete_batch")
+
+    def kv_lookup(self, keys, stream=None):
+        """(smallest value per key as int64 bits, 2^64 - 1 when none; number of distinct values)."""
+        import torch
+
+        n = keys.numel()
+        val = torch.empty(n, dtype=torch.int64, device=keys.device)
+        nv = torch.empty(n, dtype=torch.int32, device=keys.device)
+        if n:
+            _check(lib().qf_kv_lookup_batch(self.h, _dev_ptr(keys, n, 8), n, _dev_ptr(val, n, 8),
+                                            _dev_ptr(nv, n, 4), _stream(stream)), "qf_kv_lookup_batch")
+        return val, nv
+
     def point_insert(self, keys, status=None, stream=None):
         """qf_point_insert: one lane per key, in place, each key on its own
         (status: optional int32 device tensor, one code per key)."""
@@ -440,7 +479,9 @@ class CQF:
         h = lib().qf_resize(self.h, q, r, _stream(stream))
         if not h:
             raise QFError(lib().qf_last_error(), f"qf_resize({q}, {r})")
-        return CQF._own(h, q, r)
+        f = CQF._own(h, q, r)
+        f.vbits = getattr(self, "vbits", 0)
+        return f
 
     def reserve(self, n: int, stream=None):
         _check(lib().qf_reserve(self.h, n, _stream(stream)), "qf_reserve")
