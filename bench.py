@@ -465,6 +465,53 @@ def bench_fill(args) -> dict:
             "insert_s": round(times[-1], 4), "query_Bps": round(m / tq / 1e9, 4)}
 
 
+def bench_point(args) -> dict:
+    """Point updates of the counting quotient filter (qf_point_insert / qf_point_delete, one
+    lane per key in place under region locks) at 2^q quotients, r = 8: fill an empty filter
+    to load 0.9 with calls of 2^23 keys, then delete the first 2^23 keys with one point call.
+    The table afterwards must hold exactly what a bulk insert of the same keys gives (stats)."""
+    import torch
+
+    from paper_2212_09005_amd import inputs, qf
+
+    q, r = args.q, 8
+    n = int(0.9 * (1 << q))
+    chunk = 1 << 23
+    f = qf.CQF(q, r)
+    warm = torch.from_numpy(inputs.uniform_keys(3, 1 << 16).view(np.int64)).to("cuda")
+    f.point_insert(warm)
+    f.point_delete(warm)
+    assert f.sync() == 0
+    t_all, rates = 0.0, []
+    first = None
+    for lo in range(0, n, chunk):
+        k = inputs.uniform_keys(100 + lo // chunk, min(chunk, n - lo))
+        d = torch.from_numpy(k.view(np.int64)).to("cuda")
+        if first is None:
+            first = d
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f.point_insert(d)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        t_all += dt
+        rates.append((round(f.stats()["used"] / (1 << q), 3), round(len(k) / dt / 1e6, 1)))
+    assert f.sync() == 0
+    nf = torch.zeros(1, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f.point_delete(first, not_found=nf)
+    torch.cuda.synchronize()
+    t_del = time.perf_counter() - t0
+    assert f.sync() == 0 and int(nf.item()) == 0
+    f.close()
+    return {"metric": "point inserts (one lane per key, region locks) from empty to load 0.9",
+            "value": round(n / t_all / 1e6, 1), "unit": "M inserts/s", "n_gpus": 1, "higher_is_better": True,
+            "dtype": "u64", "data": "synthetic",
+            "config": {"workload": f"cqf_q{q}_r8_point_fill_0.9", "q": q, "r": r, "keys": n, "call_keys": chunk},
+            "by_fill_Mps": rates[::4] + [rates[-1]], "delete_Mps": round(chunk / t_del / 1e6, 1)}
+
+
 def bench_tcf(args) -> dict:
     """The two-choice filter at 2^28 slots (the size of the paper's CPU/GPU table, Sec. 6):
     point form (16-tag blocks) filled to load 0.9 by 2^24-key point calls, then 2^24 positive
@@ -684,10 +731,12 @@ def main() -> int:
     ap.add_argument("--load", type=float, default=0.9)
     ap.add_argument("--batch-log2", type=int, default=22)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["c2", "sweep", "fill", "zipf", "c4", "serve", "tcf"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "sweep", "fill", "zipf", "c4", "serve", "tcf", "point"],
+                    default="c2",
                     help="c2: the single-filter step (default); sweep: load sweep to 0.95; fill: one-batch fill "
                          "to 0.9; zipf: one-batch counting with skew (2^30, r=16); c4: many filters, set vs "
-                         "per-filter loop; serve: the serving loop; tcf: the two-choice filter at 2^28 slots")
+                         "per-filter loop; serve: the serving loop; tcf: the two-choice filter at 2^28 slots; point: "
+                         "point inserts of the counting filter to load 0.9")
     ap.add_argument("--serve-filters", type=int, default=256)
     ap.add_argument("--serve-requests", type=int, default=4000)
     ap.add_argument("--zipf-scale", type=int, default=0)
@@ -711,7 +760,7 @@ def main() -> int:
         assert torch.cuda.is_available(), "bench.py needs a GPU"
         torch.cuda.set_device(0)
         fn = {"c4": bench_sets, "sweep": bench_sweep, "fill": bench_fill, "zipf": bench_zipf,
-              "serve": bench_serve, "tcf": bench_tcf}[args.workload]
+              "serve": bench_serve, "tcf": bench_tcf, "point": bench_point}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return 0
 

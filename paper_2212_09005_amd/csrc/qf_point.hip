@@ -16,12 +16,13 @@
 //     lanes spinning on one lock do not slow the others).  At most one lane
 //     per two lock regions is in flight; the other keys wait their turn in a
 //     grid-stride loop.  An update locks the region of its quotient and plans
-//     its change; if the change (or a slot it read to plan it) reaches a
-//     later region, it also takes the locks up to that region, in increasing
-//     order and keeping what it holds, and plans again.  Everything an update
-//     reads or writes lies at or after the first slot of its quotient's
-//     64-slot block (runs never start before their quotient), so the held
-//     regions cover it.
+//     its change from the held regions only; where the change (or the plan)
+//     needs a slot after them, it takes the next region's lock, in
+//     increasing order and keeping what it holds, and plans again.  Nothing
+//     after the held regions is read (it may be another lane's update half
+//     done), and everything an update reads or writes lies at or after the
+//     first slot of its quotient's 64-slot block (runs never start before
+//     their quotient), so the held regions cover it.
 //   * Insert: the fingerprint's run grows by g slots (a new run or entry: 1;
 //     a counter that needs more digits: 1, or 3 for remainder 0 going from
 //     count 2 to 3).  Each slot of growth moves the slots from the growth point
@@ -72,28 +73,35 @@ struct PT {
     uint64_t &w = b[x >> 6].occ;
     w = v ? (w | (1ull << (x & 63))) : (w & ~(1ull << (x & 63)));
   }
-  // first occupied quotient in [from, N), or -1
-  __device__ int64_t next_occ(int64_t from) const {
-    if (from >= N) return -1;
+  // first occupied quotient in [from, lim] (lim clipped to N - 1), or -1.
+  // Every caller bounds the scan by the position that matters: an unbounded
+  // scan of a sparse table walks millions of words.
+  __device__ int64_t next_occ_le(int64_t from, int64_t lim) const {
+    if (lim > N - 1) lim = N - 1;
+    if (from > lim) return -1;
     int64_t w = from >> 6;
+    const int64_t wl = lim >> 6;
     uint64_t m = b[w].occ & (~0ull << (from & 63));
-    const int64_t nw = N >> 6;
-    while (!m) {
-      if (++w >= nw) return -1;
-      m = b[w].occ;
+    for (;;) {
+      if (w == wl) m &= ~0ull >> (63 - (lim & 63));
+      if (m) return (w << 6) + ctz64(m);
+      if (w == wl) return -1;
+      m = b[++w].occ;
     }
-    return (w << 6) + ctz64(m);
   }
-  // first run end in [from, P), or -1
-  __device__ int64_t next_re(int64_t from) const {
-    if (from >= P) return -1;
+  // first run end in [from, lim] (lim clipped to P - 1), or -1
+  __device__ int64_t next_re_le(int64_t from, int64_t lim) const {
+    if (lim > P - 1) lim = P - 1;
+    if (from > lim) return -1;
     int64_t w = from >> 6;
+    const int64_t wl = lim >> 6;
     uint64_t m = b[w].rend & (~0ull << (from & 63));
-    while (!m) {
-      if (++w >= nb) return -1;
-      m = b[w].rend;
+    for (;;) {
+      if (w == wl) m &= ~0ull >> (63 - (lim & 63));
+      if (m) return (w << 6) + ctz64(m);
+      if (w == wl) return -1;
+      m = b[++w].rend;
     }
-    return (w << 6) + ctz64(m);
   }
   // last run end in [lo, hi], or -1 (0 <= lo <= hi)
   __device__ int64_t prev_re(int64_t lo, int64_t hi) const {
@@ -111,8 +119,9 @@ struct PT {
   // first slot i of x's block, else some value in [that end, i - 1]: a run of
   // x starts at max(x, end_before(x) + 1) either way.  From the block offset
   // (which locates the run of the last occupied quotient <= i) and the runs
-  // of the block's occupied quotients below x.
-  __device__ int64_t end_before(int64_t x) const {
+  // of the block's occupied quotients below x.  hend + 1 when the answer
+  // needs slots after hend (then x's run starts after hend too).
+  __device__ int64_t end_before(int64_t x, int64_t hend) const {
     const int64_t bi = x >> 6, i = bi << 6;
     const uint64_t ow = b[bi].occ;
     const int64_t O = b[bi].off;
@@ -124,14 +133,17 @@ struct PT {
     } else {
       // quotient i's run ends at i + O; run ends before that in the block
       // belong to quotients below i
+      if (i + O > hend) return hend + 1;
       c = O > 0 ? prev_re(i, i + O - 1) : -1;
       if (c < 0) c = i - 1;
     }
+    if (c > hend) return hend + 1;
     uint64_t m = x > i ? (ow & ((1ull << (x - i)) - 1ull)) : 0ull;
     while (m) {
       const int64_t y = i + ctz64(m);
       m &= m - 1;
-      c = next_re(max(y, c + 1));
+      c = next_re_le(max(y, c + 1), hend);
+      if (c < 0) return hend + 1;
     }
     return c;
   }
@@ -212,14 +224,14 @@ __device__ void fix_offsets(const PT<T> &t, int64_t from, int64_t last, int64_t 
   }
   int64_t y = y0, ey = e0;
   while (i <= last) {
-    const int64_t ny = t.next_occ(y + 1);
+    const int64_t ny = t.next_occ_le(y + 1, last);  // (only quotients <= last matter)
     while (i <= last && (ny < 0 || i < ny)) {
       t.b[i >> 6].off = static_cast<uint32_t>(max(ey - i, static_cast<int64_t>(0)));
       i += 64;
     }
     if (i > last) break;
     y = ny;
-    ey = t.next_re(max(ny, ey + 1));
+    ey = t.next_re_le(max(ny, ey + 1), last);
   }
 }
 
@@ -237,53 +249,51 @@ struct Delta {
 // reaches (or read to plan it) when that lies after hi.
 template <typename T>
 __device__ int insert_step(const PT<T> &t, int64_t x, uint64_t rem, int64_t hi, int64_t *need, Delta &dl) {
-  // the plan
+  // The plan reads nothing after the held regions' last slot hend: where it
+  // would, it asks for the next region (PT_MORE) and is made again.  (What
+  // lies after hend may be another lane's update half done; a walk over it
+  // can run far past the cluster's true end.)  With the table's last region
+  // held, running past it means the table is full.
+  const int64_t hend = min(((hi + 1) << PLOCK_LOG) - 1, t.P - 1);
+  const bool at_end = hend == t.P - 1;
+  const int beyond = at_end ? PT_FULL : PT_MORE;
+  *need = hi + 1;
   const bool has = t.occ(x);
-  const int64_t eb = t.end_before(x);
+  const int64_t eb = t.end_before(x, hend);
+  if (eb >= hend) return beyond;
   const int64_t s = max(x, eb + 1);  // where x's run starts (or will)
   int64_t e = s - 1, epos = s, elen = 0;
   uint64_t c = 0;
   bool found = false;
   if (has) {
-    e = t.next_re(s);
-    if (e < 0) return PT_FULL;  // (not in a consistent table)
+    e = t.next_re_le(s, hend);
+    if (e < 0) return beyond;
     found = find_entry(t, s, e, rem, &epos, &elen, &c);
     if (found && c == ~0ull) return PT_OVF;
   }
   const int64_t sh = found ? epos + elen : epos;  // the growth point
   const int g = found ? static_cast<int>(enc_len(rem, c + 1, t.r)) - static_cast<int>(elen) : 1;
-  // z[k]: the (k+1)-th empty slot at or after sh.  (Runs beyond the held
-  // regions may be in the middle of another lane's update when read here:
-  // such a plan only decides which locks to take next.  A walk that runs
-  // off the table end takes every lock up to the end before it reports a
-  // full table.)
+  // z[k]: the (k+1)-th empty slot at or after sh.  The run of the next
+  // occupied quotient y after ylast starts at pe + 1 when y <= pe + 1 (the
+  // cluster goes on), else slot pe + 1 is empty.
   int64_t z[3] = {0, 0, 0};
-  int64_t last = max(e, sh);
-  bool to_end = false;
   if (g > 0) {
-    int64_t pe = e;
-    int64_t y = t.next_occ(x + 1);
-    for (int k = 0; k < g && !to_end; ++k) {
-      while (y >= 0 && y <= pe + 1) {  // y's run starts at pe + 1
-        const int64_t ne = t.next_re(pe + 1);
-        if (ne < 0) {
-          to_end = true;
-          break;
-        }
+    int64_t pe = e, ylast = x;
+    for (int k = 0; k < g; ++k) {
+      for (;;) {
+        if (pe + 1 > hend) return beyond;
+        const int64_t y = t.next_occ_le(ylast + 1, pe + 1);
+        if (y < 0) break;
+        const int64_t ne = t.next_re_le(pe + 1, hend);
+        if (ne < 0) return beyond;
         pe = ne;
-        y = t.next_occ(y + 1);
+        ylast = y;
       }
       z[k] = pe + 1;
-      if (z[k] >= t.P) to_end = true;
       pe = z[k];
     }
-    last = to_end ? t.P - 1 : z[g - 1];
   }
-  if ((last >> PLOCK_LOG) > hi) {
-    *need = last >> PLOCK_LOG;  // plan again once those locks are held
-    return PT_MORE;
-  }
-  if (to_end) return PT_FULL;
+  const int64_t last = g > 0 ? z[g - 1] : e;  // (<= hend)
   // the change
   for (int k = 0; k < g; ++k) {
     for (int64_t j = z[k] - 1; j >= sh; --j) t.set_slot(j + 1, t.slot(j));
@@ -318,45 +328,46 @@ __device__ int insert_step(const PT<T> &t, int64_t x, uint64_t rem, int64_t hi, 
 // One delete of fingerprint (x, rem), like insert_step.
 template <typename T>
 __device__ int delete_step(const PT<T> &t, int64_t x, uint64_t rem, int64_t hi, int64_t *need, Delta &dl) {
-  // the plan
+  // the plan (reads bounded by hend as for insert_step)
+  const int64_t hend = min(((hi + 1) << PLOCK_LOG) - 1, t.P - 1);
+  const bool at_end = hend == t.P - 1;
+  *need = hi + 1;
   if (!t.occ(x)) return PT_ABSENT;
-  const int64_t eb = t.end_before(x);
+  const int64_t eb = t.end_before(x, hend);
+  if (eb >= hend) return at_end ? PT_ABSENT : PT_MORE;  // (at the end: not in a consistent table)
   const int64_t s = max(x, eb + 1);
-  const int64_t e = t.next_re(s);
-  if (e < 0) return PT_ABSENT;  // (not in a consistent table)
+  const int64_t e = t.next_re_le(s, hend);
+  if (e < 0) return at_end ? PT_ABSENT : PT_MORE;
   int64_t epos, elen;
   uint64_t c;
   if (!find_entry(t, s, e, rem, &epos, &elen, &c)) return PT_ABSENT;
   const int64_t nlen = c > 1 ? static_cast<int64_t>(enc_len(rem, c - 1, t.r)) : 0;
   const int64_t d = elen - nlen;                     // slots the run loses
   const bool gone = nlen == 0 && e - s + 1 == elen;  // the run goes
-  const int64_t y1 = t.next_occ(x + 1);
   int64_t last = e;
   if (d > 0) {
     // each following run of the cluster starts at pe_old + 1 and moves to
     // max(its quotient, pe_new + 1); the first that stays ends the walk
-    // (as for insert, a walk over runs outside the held regions only
-    // decides which locks to take; one that finds no run end takes them
-    // all up to the table end)
-    int64_t pe_new = gone ? eb : e - d, pe_old = e, y = y1;
-    bool to_end = false;
-    while (y >= 0 && y <= pe_old + 1) {
+    int64_t pe_new = gone ? eb : e - d, pe_old = e, ylast = x;
+    for (;;) {
+      if (pe_old + 1 > hend) {
+        if (at_end) break;  // no slot after the last one
+        return PT_MORE;
+      }
+      const int64_t y = t.next_occ_le(ylast + 1, pe_old + 1);
+      if (y < 0) break;
       const int64_t so = pe_old + 1, sn = max(y, pe_new + 1);
       if (sn == so) break;
-      const int64_t eo = t.next_re(so);
+      const int64_t eo = t.next_re_le(so, hend);
       if (eo < 0) {
-        to_end = true;
-        break;
+        if (at_end) break;  // (not in a consistent table)
+        return PT_MORE;
       }
       pe_new = sn + (eo - so);
       pe_old = eo;
-      y = t.next_occ(y + 1);
+      ylast = y;
     }
-    last = to_end ? t.P - 1 : pe_old;
-  }
-  if ((last >> PLOCK_LOG) > hi) {
-    *need = last >> PLOCK_LOG;
-    return PT_MORE;
+    last = pe_old;
   }
   // the change: the entry (shorter, or gone) and the rest of x's run
   if (nlen > 0) {
@@ -372,11 +383,13 @@ __device__ int delete_step(const PT<T> &t, int64_t x, uint64_t rem, int64_t hi, 
       t.set_re(e - d, true);
     // the following runs, moved left in order; the gap a run leaves before
     // the next one's new start is cleared
-    int64_t pn = gone ? eb : e - d, po = e, y = y1, e1 = -1;
-    while (y >= 0 && y <= po + 1) {
+    int64_t pn = gone ? eb : e - d, po = e, ylast = x, e1 = -1;
+    for (;;) {
+      const int64_t y = t.next_occ_le(ylast + 1, po + 1);
+      if (y < 0) break;
       const int64_t so = po + 1, sn = max(y, pn + 1);
       if (sn == so) break;
-      const int64_t eo = t.next_re(so);
+      const int64_t eo = t.next_re_le(so, last);
       if (eo < 0) break;
       for (int64_t j = pn + 1; j < sn; ++j) t.set_slot(j, 0);
       for (int64_t j = so; j <= eo; ++j) t.set_slot(sn + (j - so), t.slot(j));
@@ -386,11 +399,11 @@ __device__ int delete_step(const PT<T> &t, int64_t x, uint64_t rem, int64_t hi, 
       if (e1 < 0) e1 = en;
       pn = en;
       po = eo;
-      y = t.next_occ(y + 1);
+      ylast = y;
     }
     for (int64_t j = pn + 1; j <= po; ++j) t.set_slot(j, 0);
     if (gone)
-      fix_offsets(t, x, po, eb, y1, e1);
+      fix_offsets(t, x, po, eb, t.next_occ_le(x + 1, po), e1);
     else
       fix_offsets(t, x, po, eb, x, e - d);
     dl.used -= d;
@@ -432,8 +445,11 @@ __device__ int point_update(const PT<T> &t, uint32_t q, uint64_t key, bool del, 
     if (!blocked) {
       int64_t need = want;
       rc = del ? delete_step(t, x, rem, hi, &need, dl) : insert_step(t, x, rem, hi, &need, dl);
+      // one more region per plan: the plan is exact up to the held regions'
+      // end, and what it read beyond may be another lane's update half done
+      // (taking every lock such a plan asks for could hold most of the table)
       if (rc == PT_MORE)
-        want = need;
+        want = hi + 1;
       else
         unlock_range(t.locks, R0, hi);
       backoff = 0;

@@ -24,5 +24,5 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 def test_help_lists_every_workload():
     out = _bench("--help")
     assert out.returncode == 0
-    for w in ("c2", "sweep", "fill", "zipf", "c4", "serve", "tcf"):
+    for w in ("c2", "sweep", "fill", "zipf", "c4", "serve", "tcf", "point"):
         assert w in out.stdout

@@ -209,3 +209,29 @@ def test_point_inserts_at_scale():
     assert f.sync() == 0
     check(f, brute.multiset(brute.fingerprints(keys, q, r)), q, r, "q=22 point inserts")
     f.close()
+
+
+@pytest.mark.slow
+def test_point_deletes_at_scale_after_a_point_fill():
+    from paper_2212_09005_amd import qf
+
+    q, r = 24, 8
+    note(f"point fill to 0.9 then 2^21 point deletes q={q}")
+    n = int(0.9 * (1 << q))
+    f = qf.CQF(q, r)
+    keys = []
+    for i, lo in enumerate(range(0, n, 1 << 22)):
+        k = inputs.uniform_keys(40 + i, min(1 << 22, n - lo))
+        keys.append(k)
+        f.point_insert(dev(k))
+    assert f.sync() == 0
+    dk = keys[0][: 1 << 21]
+    st = torch.full((len(dk),), 7, dtype=torch.int32, device="cuda")
+    nf = torch.zeros(1, dtype=torch.int64, device="cuda")
+    f.point_delete(dev(dk), status=st, not_found=nf)
+    assert f.sync() == 0 and int(nf.item()) == 0 and (st.cpu().numpy() == 0).all()
+    allk = np.concatenate(keys)
+    ms = brute.merge_multisets(brute.multiset(brute.fingerprints(allk, q, r)),
+                               brute.multiset(brute.fingerprints(dk, q, r)), subtract=True)[0]
+    check(f, ms, q, r, "point fill then point deletes at q=24")
+    f.close()
