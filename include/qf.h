@@ -44,6 +44,11 @@ extern "C" {
 
 typedef struct qf_filter qf_t;
 
+/* Largest q a filter may have (2^30 quotients, about 2.7 GB per table copy
+ * at r = 16): every size the library accepts is one the CPU checker can
+ * build and compare bit for bit. */
+#define QF_Q_MAX 30
+
 enum {
   QF_OK = 0,
   QF_ERR_ARG = -1,            /* bad argument (nothing happened)              */
@@ -79,7 +84,7 @@ typedef struct qf_layout {
   uint32_t *offsets;
 } qf_layout_t;
 
-/* Sec. 5.1: a table of 2^q quotients with r-bit remainders.  q in [6, 31],
+/* Sec. 5.1: a table of 2^q quotients with r-bit remainders.  q in [6, QF_Q_MAX],
  * r in {8, 16}.  Returns NULL on error (see qf_last_error()).  The new filter
  * is empty and lives on the current HIP device. */
 qf_t *qf_create(uint32_t q, uint32_t r);

@@ -480,7 +480,7 @@ int record_error(int code) { return fail(code); }
 extern "C" {
 
 qf_t *qf_create(uint32_t q, uint32_t r) {
-  if (q < 6 || q > 31 || (r != 8 && r != 16)) {
+  if (q < 6 || q > QF_Q_MAX || (r != 8 && r != 16)) {
     fail(QF_ERR_ARG);
     return nullptr;
   }
@@ -976,7 +976,7 @@ int qf_set_profile_read(qf_set_t *st, double *ms, uint64_t *n) {
 }
 
 uint64_t qf_table_bytes(uint32_t q, uint32_t r) {
-  if (q < 6 || q > 31 || (r != 8 && r != 16)) return 0;
+  if (q < 6 || q > QF_Q_MAX || (r != 8 && r != 16)) return 0;
   const uint64_t P = (1ull << q) + extra_slots(q);
   return qf::table_bytes(P / 64, r);
 }

@@ -486,7 +486,7 @@ void qfs_destroy(qfs_t *s) {
 }
 
 int qfs_open(qfs_t *s, uint32_t q, uint32_t r) {
-  if (!s || q < 6 || q > 31 || (r != 8 && r != 16)) return QF_ERR_ARG;
+  if (!s || q < 6 || q > QF_Q_MAX || (r != 8 && r != 16)) return QF_ERR_ARG;
   const uint64_t b = filter_bytes(q, r);
   std::lock_guard<std::mutex> lk(s->mu);
   if (b > s->budget) return QF_ERR_BUDGET;

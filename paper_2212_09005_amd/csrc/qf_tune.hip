@@ -234,7 +234,7 @@ extern "C" int qf_autotune_set(const uint32_t *qs, uint32_t nf, uint32_t r, doub
                                qf_tuning_t *best, double *ms) {
   if (!qs || nf == 0 || !best || (r != 8 && r != 16) || !(load > 0.0 && load < 1.0)) return QF_ERR_ARG;
   for (uint32_t i = 0; i < nf; ++i)
-    if (qs[i] < 6 || qs[i] > 31) return QF_ERR_ARG;
+    if (qs[i] < 6 || qs[i] > QF_Q_MAX) return QF_ERR_ARG;
   std::vector<uint64_t> key{r, static_cast<uint64_t>(load * 1e9), n_query};
   key.insert(key.end(), qs, qs + nf);
   {

@@ -66,6 +66,9 @@ def test_argument_errors_return_before_the_device():
     assert L.qf_create(5, 8) is None and L.qf_last_error() == qf.QF_ERR_ARG
     assert L.qf_create(12, 7) is None and L.qf_last_error() == qf.QF_ERR_ARG
     assert L.qf_create(32, 8) is None and L.qf_last_error() == qf.QF_ERR_ARG
+    # q = 31 is refused too: the CPU checker builds tables up to q = 30 only
+    assert L.qf_create(31, 8) is None and L.qf_last_error() == qf.QF_ERR_ARG
+    assert L.qfs_open(None, 12, 8) == qf.QF_ERR_ARG
     assert L.qf_insert_batch(None, None, 5, None) == qf.QF_ERR_ARG
     assert L.qf_query_batch(None, None, 5, None, None) == qf.QF_ERR_ARG
     assert L.qf_count_batch(None, None, 5, None, None) == qf.QF_ERR_ARG
@@ -108,6 +111,7 @@ def test_table_bytes():
     assert qf.qf_table_bytes(28, 8) == ((1 << 28) + 163840) // 64 * 128
     assert qf.qf_table_bytes(30, 16) == ((1 << 30) + 327680) // 64 * 160
     assert qf.qf_table_bytes(5, 8) == 0
+    assert qf.qf_table_bytes(31, 8) == 0
 
 
 def _run_py(code):
