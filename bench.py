@@ -151,6 +151,122 @@ def cpu_baseline(w, fill: np.ndarray, budget_s: float = 20.0, m: int = 1 << 18) 
     }
 
 
+def host_threads() -> int:
+    """Threads for the all-core oracle runs: the host's cores, at most 16 (one GPU's share of a
+    shared host)."""
+    return max(1, min(os.cpu_count() or 1, 16))
+
+
+def shard(items, weight, threads: int) -> list:
+    """Items spread over threads, heaviest first to the least-loaded thread."""
+    shards, load = [[] for _ in range(threads)], [0] * threads
+    for i in sorted(items, key=weight, reverse=True):
+        t = load.index(min(load))
+        shards[t].append(i)
+        load[t] += weight(i)
+    return shards
+
+
+def pool_time(fn, shards, threads: int) -> float:
+    """Wall seconds of fn over the shards on a pool of threads (the oracle's calls release the
+    interpreter lock, so independent filters run in parallel)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(fn, shards))
+    return time.perf_counter() - t0
+
+
+def cpu_baseline_sets(b: dict, nf: int, order, qoff, got_set, budget_keys: int = 1 << 25) -> dict:
+    """The CPU oracle (oracle/oqf.c as it stands) on a sample of the many-filter workload, with
+    independent filters spread over all host threads (one shard of filters per thread): every
+    stride-th filter, about budget_keys fill keys in all, filled in one batch each and then asked
+    its share of the routed queries.  Its answers must equal the GPU set's for the same keys."""
+    from oracle import oqf
+
+    qs, off, keys, qkeys = b["qs"], b["off"], b["keys"], b["qkeys"]
+    threads = host_threads()
+    stride = max(1, -(-int(off[-1]) // budget_keys))
+    sample = list(range(0, nf, stride))
+    shards = shard(sample, lambda i: int(off[i + 1] - off[i]), threads)
+    fs, ans = {}, {}
+
+    def qidx(i):
+        return order[int(qoff[i]):int(qoff[i + 1])]
+
+    def fill(sh):
+        for i in sh:
+            o = oqf.OracleQF(int(qs[i]), 8)
+            assert o.insert(keys[int(off[i]):int(off[i + 1])]) == 0
+            fs[i] = o
+
+    def query(sh):
+        for i in sh:
+            ans[i] = fs[i].query(qkeys[qidx(i)])
+
+    t_fill = pool_time(fill, shards, threads)
+    t_query = pool_time(query, shards, threads)
+    for i in sample:
+        assert np.array_equal(ans[i], got_set[qidx(i)]), f"filter {i}: oracle and GPU answers differ"
+    n_fill = int(sum(int(off[i + 1] - off[i]) for i in sample))
+    n_query = int(sum(len(qidx(i)) for i in sample))
+    del fs
+    return {"value": round(n_fill / t_fill / 1e9, 6), "unit": "B inserts/s", "cores": threads, "kind": "oracle",
+            "query_Bps": round(n_query / t_query / 1e9, 6),
+            "sample": (f"oracle/oqf.c on every {stride}-th filter ({len(sample)} filters of q {int(min(qs[sample]))}"
+                       f"..{int(max(qs[sample]))}, {n_fill} fill keys in one batch each, then their {n_query} routed "
+                       f"queries), filters spread over {threads} threads; answers equal the GPU set's"),
+            "host": host_cpu()}
+
+
+def cpu_baseline_serve(qs, rs, fill, reqs, qmax: int = 20) -> dict:
+    """The CPU oracle (oracle/oqf.c as it stands) serving the same request stream restricted to the
+    filters of at most 2^qmax quotients, filters spread over all host threads (each thread replays
+    its filters' requests in submission order).  The filters are filled beforehand (not timed)."""
+    from oracle import oqf
+
+    threads = host_threads()
+    sample = [i for i in range(len(qs)) if int(qs[i]) <= qmax]
+    mine = {i: [] for i in sample}
+    for op, f, keys in reqs:
+        if f in mine:
+            mine[f].append((op, keys))
+    shards = shard(sample, lambda i: sum(len(k) for _, k in mine[i]) + (1 << int(qs[i])) // 8, threads)
+    fs = {}
+
+    def build(sh):
+        for i in sh:
+            o = oqf.OracleQF(int(qs[i]), int(rs[i]))
+            assert o.insert(fill[i]) == 0
+            fs[i] = o
+
+    def serve(sh):
+        from paper_2212_09005_amd import qf
+
+        for i in sh:
+            o = fs[i]
+            for op, keys in mine[i]:
+                if op == qf.QFS_INSERT:
+                    assert o.insert(keys) == 0
+                elif op == qf.QFS_DELETE:
+                    assert o.delete(keys)[0] == 0
+                else:
+                    o.query(keys)
+
+    pool_time(build, shards, threads)
+    dt = pool_time(serve, shards, threads)
+    nreq = sum(len(v) for v in mine.values())
+    nkeys = sum(len(k) for v in mine.values() for _, k in v)
+    del fs
+    return {"value": round(nkeys / dt / 1e9, 6), "unit": "B keys/s", "cores": threads, "kind": "oracle",
+            "req_per_s": round(nreq / dt, 1),
+            "sample": (f"oracle/oqf.c serving the saturation stream's {nreq} requests ({nkeys} keys) to the "
+                       f"{len(sample)} filters of q <= {qmax}, filled beforehand (not timed), filters spread over "
+                       f"{threads} threads, each filter's requests in order"),
+            "host": host_cpu()}
+
+
 def copy_bandwidth(torch, nbytes: int = 1 << 30, reps: int = 5) -> float:
     """Attainable HBM bandwidth: a device-to-device copy of nbytes (read + write), GB/s, best of reps."""
     src = torch.ones(nbytes // 8, dtype=torch.int64, device="cuda")
@@ -293,6 +409,11 @@ def bench_sets(args) -> dict:
     fp_rate = float(got_set[~present].mean())
     for f in fs_loop:
         f.close()
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("c4: timing the CPU oracle on a sample of the filters, all host threads")
+        cpu = cpu_baseline_sets(b, nf, order, qoff, got_set)
+        log(f"c4 oracle: {cpu}")
     res = {
         "metric": "filter-set fill and query throughput (4096 filters of 2^10..2^20 quotients, r=8, load 0.85)",
         "value": round(total / t_g_fill / 1e9, 4),
@@ -314,6 +435,7 @@ def bench_sets(args) -> dict:
                     "tuned_graph_fill": round(t_loop_fill / t_g_fill, 2),
                     "tuned_graph_query": round(t_loop_query / t_g_query, 2)},
         "absent_positive_rate": round(fp_rate, 6),
+        "cpu_baseline": cpu,
     }
     return res
 
@@ -668,6 +790,10 @@ def bench_serve(args) -> dict:
     log(f"serve saturation: {sat}")
     loop = loop_replay(qs, rs, fill, sat_reqs, qf)
     log(f"serve, same stream as a loop of per-request calls: {loop}")
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_serve(qs, rs, fill, sat_reqs)
+        log(f"serve oracle: {cpu}")
     cap_rps = sat["req_per_s"]
     points = []
     for frac in (0.25, 0.5, 0.9):
@@ -683,7 +809,7 @@ def bench_serve(args) -> dict:
             "dtype": "u64", "data": "synthetic",
             "config": {"workload": wl.name(), "filters": nf,
                        "requests_per_run": nreq, "budget_bytes": 64 << 30},
-            "saturation": sat, "loop": loop, "points": points, "server": st}
+            "saturation": sat, "loop": loop, "points": points, "server": st, "cpu_baseline": cpu}
 
 
 def loop_replay(qs, rs, fill, reqs, qf) -> dict:

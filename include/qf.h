@@ -93,6 +93,13 @@ qf_t *qf_create(uint32_t q, uint32_t r);
  * NULL is ignored. */
 void qf_destroy(qf_t *f);
 
+/* Batch limits of the update calls (insert, delete, and their set and
+ * value-association forms): at most 2^32 - 1 keys per batch (a larger n
+ * returns QF_ERR_ARG at once).  An update sorts its batch in the filter's
+ * scratch area, 64 bytes per key, grown on demand and kept (QF_ERR_OOM when
+ * the device cannot hold it): a one-batch insert of 9.66e8 keys needs about
+ * 62 GB beside the two table copies.  qf_reserve grows it ahead of time. */
+
 /* Sec. 5.3-5.4: insert one instance of each key (duplicates are counted).
  * d_keys: device, n uint64.  All or nothing; QF_ERR_FULL / COUNT_OVERFLOW are
  * deferred to qf_sync. */
