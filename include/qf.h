@@ -408,7 +408,12 @@ void qf_graph_destroy(qf_graph_t *g); /* NULL-safe */
  * the leading run of its waiting requests with one operation; all filters'
  * shares of one operation (and r) run as one filter-set batch, so requests
  * that arrive while others are on the device join the next round, and the
- * next round is assembled and launched while the current one runs.  Per
+ * next round is assembled and launched while the current one runs.  A
+ * filter's updates of a round with no more keys than it has 4096-slot lock
+ * regions, and no way to fill the slots past its last quotient (3 per key
+ * against a bound of those in use), are applied in place by point updates,
+ * at a cost that follows the keys; the others go through the bulk merge,
+ * which rewrites the filter.  Both give the same table.  Per
  * filter the effects and answers are those of executing its requests one by
  * one in submission order (linearizable in admission order); requests on
  * different filters are independent.  Filters are admitted in open order
@@ -441,8 +446,10 @@ int qfs_export(qfs_t *s, int id, qf_layout_t *out, uint64_t tag);
 /* Writes up to max completions (tag, status); waits up to wait_us for one if
  * none is ready.  Returns how many were written. */
 int qfs_poll(qfs_t *s, uint64_t *tags, int32_t *status, uint32_t max, int wait_us);
-/* st[0..7] = rounds, requests completed, keys processed, filters open,
- * filters waiting for admission, bytes in use, budget, requests waiting. */
+/* st[0..9] = rounds, requests completed, keys processed, filters open,
+ * filters waiting for admission, bytes in use, budget, requests waiting,
+ * update requests applied in place (point updates), update requests merged
+ * in bulk. */
 int qfs_stats(qfs_t *s, uint64_t *st);
 
 #ifdef __cplusplus

@@ -136,6 +136,9 @@ hipError_t launch_lookup_multi(const Pipe &p, const uint64_t *keys, const uint32
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
 // copy each filter's deferred error word to err[f] and clear it
 hipError_t launch_take_errors(const Pipe &p, int64_t *err, hipStream_t s);
+// tail[i] = used slots past the last quotient of the pipeline's filter i
+// (they form one stretch from N), on the filter's current copy
+hipError_t launch_take_tails(const Pipe &p, int64_t *tail, hipStream_t s);
 hipError_t launch_export(qf_filter *f, uint64_t *occ, uint64_t *rend, uint16_t *slots,
                          uint32_t *offs, hipStream_t s);
 hipError_t launch_import(qf_filter *f, const uint64_t *occ, const uint64_t *rend,
@@ -154,6 +157,8 @@ int max_region_log2(uint32_t r);
 // point updates (one lane per key, in place): words of the lock array of a
 // table of P slots, and the launch (status, not_found may be null)
 uint64_t point_lock_words(uint64_t P);
+// lock regions of a point update on a table of P slots
+uint64_t point_regions(uint64_t P);
 hipError_t launch_point(qf_filter *f, const uint64_t *keys, uint64_t n, int del, int32_t *status,
                         uint64_t *not_found, hipStream_t s);
 // records code as the calling thread's last error (qf_last_error) and returns it

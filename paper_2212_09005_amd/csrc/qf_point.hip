@@ -528,6 +528,8 @@ hipError_t point_t(qf_filter *f, const uint64_t *keys, uint64_t n, int del, int3
 
 uint64_t point_lock_words(uint64_t P) { return ((P >> PLOCK_LOG) + 2) * PLOCK_STRIDE; }
 
+uint64_t point_regions(uint64_t P) { return (P >> PLOCK_LOG) + 1; }
+
 hipError_t launch_point(qf_filter *f, const uint64_t *keys, uint64_t n, int del, int32_t *status,
                         uint64_t *not_found, hipStream_t s) {
   if (f->r == 8) return point_t<uint8_t>(f, keys, n, del, status, not_found, s);

@@ -64,15 +64,21 @@ struct Stage {
   hipEvent_t done = nullptr;
   // per-filter deferred errors of the round, gathered on the stream after
   // the round's launches (nerr words per set, sets in order of r)
+  // and, behind them, each filter's used slots past its last quotient
   int64_t *d_err = nullptr, *h_err = nullptr;
+  int64_t *d_tail = nullptr, *h_tail = nullptr;
   uint32_t nerr = 0;
   bool alloc_err(uint32_t n) {
     (void)hipFree(d_err);
     (void)hipHostFree(h_err);
-    d_err = h_err = nullptr;
+    (void)hipFree(d_tail);
+    (void)hipHostFree(h_tail);
+    d_err = h_err = d_tail = h_tail = nullptr;
     nerr = n;
     return n == 0 || (hipMalloc(reinterpret_cast<void **>(&d_err), n * 8) == hipSuccess &&
-                      hipHostMalloc(reinterpret_cast<void **>(&h_err), n * 8, 0) == hipSuccess);
+                      hipHostMalloc(reinterpret_cast<void **>(&h_err), n * 8, 0) == hipSuccess &&
+                      hipMalloc(reinterpret_cast<void **>(&d_tail), n * 8) == hipSuccess &&
+                      hipHostMalloc(reinterpret_cast<void **>(&h_tail), n * 8, 0) == hipSuccess);
   }
   bool alloc(uint64_t n) {
     cap = n;
@@ -98,20 +104,27 @@ struct Stage {
     if (done) (void)hipEventDestroy(done);
     (void)hipFree(d_err);
     (void)hipHostFree(h_err);
+    (void)hipFree(d_tail);
+    (void)hipHostFree(h_tail);
   }
 };
 
 // One (r, operation) batch of a round: the requests and their key offsets.
+// An update part is ordered by path, then filter: first the filters updated
+// in place (point updates), then those merged in bulk.
 struct Part {
   uint32_t r;
   int op;
   std::vector<Req *> reqs;
   std::vector<uint64_t> off;  // offset of each request's keys in the stage
   uint64_t n = 0;
+  std::vector<char> pt;       // update parts: the request is applied in place
+  uint64_t n_point = 0;       // keys of the part updated in place (a prefix)
 };
 
 struct Round {
   std::vector<Part> parts;
+  std::map<int, uint64_t> ins;  // keys inserted per filter id
   std::vector<Req *> closes;
   std::vector<Req *> exports;  // table copies to the caller, after the round
   bool empty() const { return parts.empty() && closes.empty() && exports.empty(); }
@@ -140,6 +153,11 @@ struct qf_server {
   std::map<uint32_t, SetOf> sets;  // by r
   bool sets_dirty = true;
   uint64_t rounds = 0, requests = 0, keys = 0, seq = 0;
+  uint64_t upd_point = 0, upd_bulk = 0;  // update requests by path
+  // serving thread only: per filter id, a bound on its used slots past the
+  // last quotient (measured after each update round, plus 3 per key
+  // inserted since)
+  std::map<int, uint64_t> tail_hi;
   int device = 0;
 };
 
@@ -282,8 +300,54 @@ Round form_round_locked(qf_server *s) {
   return rd;
 }
 
+// Choose each update's path.  A filter's keys of the round are applied in
+// place (point updates: one lane per key under region locks, cost following
+// the keys) when there are no more of them than the filter has lock regions
+// (so lanes seldom wait for one another) and they cannot run out of room:
+// each key adds at most 3 used slots, and the used slots past the last
+// quotient form one stretch whose length is bounded by tail_hi, so
+// tail_hi + 3 n + 3 <= E keeps every shift inside the table and no key can
+// fail for lack of room (the request stays all or nothing).  The rest go
+// through the bulk merge, which rewrites every block of the filter.  The
+// part is reordered (in-place filters first, then by filter, each filter's
+// requests in submission order) so that each filter's keys lie together.
+void plan_updates(qf_server *s, Round &rd) {
+  for (Part &p : rd.parts) {
+    if (p.op != OP_INSERT && p.op != OP_DELETE) continue;
+    SetOf &so = s->sets[p.r];
+    std::map<int, uint64_t> nk;
+    for (Req *q : p.reqs) nk[q->id] += q->keys.size();
+    std::map<int, char> inplace;
+    for (auto &kv : nk) {
+      const qf_filter *f = so.set->fs[so.idx[kv.first]];
+      const uint64_t n = kv.second, room = f->P - f->N;
+      const uint64_t t = s->tail_hi[kv.first];
+      inplace[kv.first] = n > 0 && n <= qf::point_regions(f->P) && t + 3 * n + 3 <= room;
+      if (p.op == OP_INSERT) {
+        rd.ins[kv.first] += n;
+        s->tail_hi[kv.first] = t + 3 * n;
+      }
+    }
+    std::stable_sort(p.reqs.begin(), p.reqs.end(), [&inplace](Req *a, Req *b) {
+      const char pa = inplace.at(a->id), pb = inplace.at(b->id);
+      if (pa != pb) return pa > pb;
+      return a->id < b->id;
+    });
+    p.pt.assign(p.reqs.size(), 0);
+    p.n_point = 0;
+    uint64_t o = 0;
+    for (size_t k = 0; k < p.reqs.size(); ++k) {
+      p.off[k] = o;
+      o += p.reqs[k]->keys.size();
+      p.pt[k] = inplace.at(p.reqs[k]->id);
+      if (p.pt[k]) p.n_point = o;
+    }
+  }
+}
+
 // Enqueue a round on the stream (no waiting).
 int launch_round(qf_server *s, Round &rd, Stage &st) {
+  plan_updates(s, rd);
   uint64_t base = 0;
   for (Part &p : rd.parts) {
     SetOf &so = s->sets[p.r];
@@ -307,16 +371,34 @@ int launch_round(qf_server *s, Round &rd, Stage &st) {
     const uint32_t *f = st.d_fid + base;
     int rc = QF_OK;
     if (p.op == OP_INSERT || p.op == OP_DELETE) {
-      // merge only the filters this part touches
+      SetOf &so = s->sets[p.r];
+      // in place: one launch per filter over its keys (errors go to the
+      // filter's error word, as a merge's do)
+      for (size_t a = 0; a < p.reqs.size() && p.pt[a] && !rc;) {
+        const int id = p.reqs[a]->id;
+        size_t e = a;
+        while (e < p.reqs.size() && p.pt[e] && p.reqs[e]->id == id) ++e;
+        const uint64_t lo = p.off[a], hi = e < p.reqs.size() ? p.off[e] : p.n;
+        if (hi > lo && qf::launch_point(so.set->fs[so.idx[id]], k + lo, hi - lo, p.op == OP_DELETE, nullptr,
+                                        nullptr, s->stream) != hipSuccess)
+          rc = QF_ERR_DEVICE;
+        a = e;
+      }
+      // in bulk: merge only the filters of the rest of the part
       std::vector<uint32_t> act;
-      for (Req *q : p.reqs) act.push_back(s->sets[p.r].idx[q->id]);
+      for (size_t a = 0; a < p.reqs.size(); ++a)
+        if (!p.pt[a] && !p.reqs[a]->keys.empty()) act.push_back(so.idx[p.reqs[a]->id]);
       std::sort(act.begin(), act.end());
       act.erase(std::unique(act.begin(), act.end()), act.end());
-      if (p.op == OP_INSERT)
-        rc = qf_set_insert_some(set, act.data(), static_cast<uint32_t>(act.size()), f, k, p.n, s->stream);
-      else
-        rc = qf_set_delete_some(set, act.data(), static_cast<uint32_t>(act.size()), f, k, p.n, nullptr,
-                                s->stream);
+      const uint64_t np = p.n_point, nb = p.n - p.n_point;
+      if (!rc && !act.empty()) {
+        if (p.op == OP_INSERT)
+          rc = qf_set_insert_some(set, act.data(), static_cast<uint32_t>(act.size()), f + np, k + np, nb,
+                                  s->stream);
+        else
+          rc = qf_set_delete_some(set, act.data(), static_cast<uint32_t>(act.size()), f + np, k + np, nb,
+                                  nullptr, s->stream);
+      }
     }
     if (p.op == OP_QUERY) {
       rc = qf_set_query_batch(set, f, k, p.n, st.d_out8 + base, s->stream);
@@ -337,17 +419,22 @@ int launch_round(qf_server *s, Round &rd, Stage &st) {
   if (updates && st.nerr) {
     uint32_t o = 0;
     for (auto &kv : s->sets) {
-      if (qf::launch_take_errors(kv.second.set->pipe, st.d_err + o, s->stream) != hipSuccess) return QF_ERR_DEVICE;
+      if (qf::launch_take_errors(kv.second.set->pipe, st.d_err + o, s->stream) != hipSuccess ||
+          qf::launch_take_tails(kv.second.set->pipe, st.d_tail + o, s->stream) != hipSuccess)
+        return QF_ERR_DEVICE;
       o += static_cast<uint32_t>(kv.second.ids.size());
     }
-    if (hipMemcpyAsync(st.h_err, st.d_err, st.nerr * 8, hipMemcpyDeviceToHost, s->stream) != hipSuccess)
+    if (hipMemcpyAsync(st.h_err, st.d_err, st.nerr * 8, hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
+        hipMemcpyAsync(st.h_tail, st.d_tail, st.nerr * 8, hipMemcpyDeviceToHost, s->stream) != hipSuccess)
       return QF_ERR_DEVICE;
   }
   return hipEventRecord(st.done, s->stream) == hipSuccess ? QF_OK : QF_ERR_DEVICE;
 }
 
 // Wait for a launched round, copy outputs, set statuses, run its closes.
-void complete_round(qf_server *s, Round &rd, Stage &st, int launch_rc) {
+// next: the round launched after it, if any (its inserts count against the
+// room measured at the end of this one).
+void complete_round(qf_server *s, Round &rd, Stage &st, int launch_rc, const Round *next) {
   if (!rd.parts.empty()) (void)hipEventSynchronize(st.done);
   // per-filter errors of this round (updates only)
   std::map<int, int> err;
@@ -356,8 +443,16 @@ void complete_round(qf_server *s, Round &rd, Stage &st, int launch_rc) {
   if (updates && launch_rc == QF_OK && st.nerr) {
     uint32_t o = 0;
     for (auto &kv : s->sets) {
-      for (size_t i = 0; i < kv.second.ids.size(); ++i)
-        if (st.h_err[o + i]) err[kv.second.ids[i]] = static_cast<int>(st.h_err[o + i]);
+      for (size_t i = 0; i < kv.second.ids.size(); ++i) {
+        const int id = kv.second.ids[i];
+        if (st.h_err[o + i]) err[id] = static_cast<int>(st.h_err[o + i]);
+        uint64_t t = static_cast<uint64_t>(st.h_tail[o + i]);
+        if (next) {
+          auto it = next->ins.find(id);
+          if (it != next->ins.end()) t += 3 * it->second;
+        }
+        s->tail_hi[id] = t;
+      }
       o += static_cast<uint32_t>(kv.second.ids.size());
     }
   }
@@ -393,9 +488,10 @@ void complete_round(qf_server *s, Round &rd, Stage &st, int launch_rc) {
   }
   if (!rd.closes.empty()) admit_locked(s);
   for (Part &p : rd.parts)
-    for (Req *q : p.reqs) {
-      s->done.push_back(q);
-      s->keys += q->keys.size();
+    for (size_t k = 0; k < p.reqs.size(); ++k) {
+      s->done.push_back(p.reqs[k]);
+      s->keys += p.reqs[k]->keys.size();
+      if (p.op == OP_INSERT || p.op == OP_DELETE) ++(p.pt[k] ? s->upd_point : s->upd_bulk);
     }
   for (Req *c : rd.closes) s->done.push_back(c);
   for (Req *e : rd.exports) s->done.push_back(e);
@@ -429,7 +525,7 @@ void serve(qf_server *s) {
     }
     int rc = QF_OK;
     if (!rd.parts.empty()) rc = launch_round(s, rd, s->stage[cur]);
-    if (have) complete_round(s, inflight, s->stage[cur ^ 1], inflight_rc);
+    if (have) complete_round(s, inflight, s->stage[cur ^ 1], inflight_rc, rd.empty() ? nullptr : &rd);
     have = !rd.empty();
     if (have) {
       inflight = rd;
@@ -604,6 +700,8 @@ int qfs_stats(qfs_t *s, uint64_t *st) {
   st[5] = s->used;
   st[6] = s->budget;
   st[7] = s->queue.size();
+  st[8] = s->upd_point;
+  st[9] = s->upd_bulk;
   return QF_OK;
 }
 

@@ -82,6 +82,25 @@ __global__ __launch_bounds__(NT) void k_take_errors(const FDesc *__restrict__ de
   st[ST_ERR] = 0;
 }
 
+// Used slots past the last quotient: a slot at or after N is used only if
+// the slot before it is, so they form one stretch [N, N + t) that ends at the
+// table's last run end, and block N/64's offset is that end's distance from N
+// (0 both when it is N itself, which sets the block's first run-end bit, and
+// when it lies before N).
+template <typename T>
+__device__ int64_t tail_used(const FDesc &d) {
+  const Block<T> *b = static_cast<const Block<T> *>(d.blk[d.state[ST_CUR] & 1ull]);
+  const Block<T> &h = b[d.N >> 6];
+  return (h.off || (h.rend & 1ull)) ? static_cast<int64_t>(h.off) + 1 : 0;
+}
+
+__global__ __launch_bounds__(NT) void k_take_tails(const FDesc *__restrict__ desc, uint32_t nf,
+                                                   int64_t *__restrict__ tail) {
+  const uint32_t f = blockIdx.x * NT + threadIdx.x;
+  if (f >= nf) return;
+  tail[f] = desc[f].r == 8 ? tail_used<uint8_t>(desc[f]) : tail_used<uint16_t>(desc[f]);
+}
+
 __global__ __launch_bounds__(NT) void k_fill(uint64_t *p, uint64_t n, uint64_t v) {
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * NT;
   for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * NT + threadIdx.x; i < n; i += stride)
@@ -654,6 +673,11 @@ hipError_t launch_hash_multi(const uint64_t *keys, const uint32_t *fid, uint64_t
 
 hipError_t launch_take_errors(const Pipe &p, int64_t *err, hipStream_t s) {
   k_take_errors<<<(p.nf + NT - 1) / NT, NT, 0, s>>>(p.d_desc, p.nf, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_take_tails(const Pipe &p, int64_t *tail, hipStream_t s) {
+  k_take_tails<<<(p.nf + NT - 1) / NT, NT, 0, s>>>(p.d_desc, p.nf, tail);
   return hipGetLastError();
 }
 

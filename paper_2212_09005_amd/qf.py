@@ -790,7 +790,8 @@ class Server:
         return res
 
     def stats(self) -> dict:
-        buf = (ctypes.c_uint64 * 8)()
+        buf = (ctypes.c_uint64 * 10)()
         _check(lib().qfs_stats(self.h, buf), "qfs_stats")
-        keys = ("rounds", "requests", "keys", "open", "pending", "bytes_used", "budget", "waiting")
+        keys = ("rounds", "requests", "keys", "open", "pending", "bytes_used", "budget", "waiting",
+                "updates_in_place", "updates_bulk")
         return dict(zip(keys, (int(v) for v in buf)))
