@@ -786,7 +786,11 @@ def bench_serve(args) -> dict:
 
     nreq = args.serve_requests
     sat_reqs = make_requests(nreq, 1)
+    st0 = srv.stats()
     sat = run(sat_reqs, None)
+    st1 = srv.stats()
+    sat["server"] = {k: st1[k] - st0[k] for k in ("rounds", "requests", "keys", "updates_in_place", "updates_bulk",
+                                                  "ns_form", "ns_launch", "ns_wait", "ns_complete", "ns_stage")}
     log(f"serve saturation: {sat}")
     loop = loop_replay(qs, rs, fill, sat_reqs, qf)
     log(f"serve, same stream as a loop of per-request calls: {loop}")

@@ -446,10 +446,12 @@ int qfs_export(qfs_t *s, int id, qf_layout_t *out, uint64_t tag);
 /* Writes up to max completions (tag, status); waits up to wait_us for one if
  * none is ready.  Returns how many were written. */
 int qfs_poll(qfs_t *s, uint64_t *tags, int32_t *status, uint32_t max, int wait_us);
-/* st[0..9] = rounds, requests completed, keys processed, filters open,
+/* st[0..14] = rounds, requests completed, keys processed, filters open,
  * filters waiting for admission, bytes in use, budget, requests waiting,
  * update requests applied in place (point updates), update requests merged
- * in bulk. */
+ * in bulk, the loop thread's nanoseconds spent forming rounds, launching
+ * them, waiting for the device and completing them, and of the launching,
+ * the nanoseconds spent copying keys into the pinned staging buffers. */
 int qfs_stats(qfs_t *s, uint64_t *st);
 
 #ifdef __cplusplus

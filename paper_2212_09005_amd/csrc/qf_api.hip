@@ -109,6 +109,11 @@ void pipe_free(qf::Pipe &p) {
   (void)hipFree(p.d_err);
   (void)hipFree(p.d_afil);
   (void)hipFree(p.d_areg);
+  for (int i = 0; i < qf::Pipe::PIN_RING; ++i) {
+    if (p.pin_ev[i]) (void)hipEventSynchronize(p.pin_ev[i]);
+    (void)hipHostFree(p.h_pin[i]);
+    if (p.pin_ev[i]) (void)hipEventDestroy(p.pin_ev[i]);
+  }
   free_scratch(p);
   delete p.timer;
   p = qf::Pipe();
@@ -234,9 +239,29 @@ int pipe_update(qf::Pipe &p, const uint64_t *keys, const uint32_t *fid, uint64_t
       if (f >= set->nf || (k && f <= h_active[k - 1])) return fail(QF_ERR_ARG);
       for (uint32_t R = 0; R < p.h_nreg[f]; ++R) p.h_areg.push_back(p.h_rbase[f] + R);
     }
-    QF_HIP(hipMemcpyAsync(p.d_afil, p.h_afil.data(), nactive * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-    QF_HIP(hipMemcpyAsync(p.d_areg, p.h_areg.data(), p.h_areg.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
-                          s));
+    // both lists through the next pinned buffer (see Pipe::h_pin)
+    const int i = p.pin_i;
+    p.pin_i = (p.pin_i + 1) % qf::Pipe::PIN_RING;
+    const uint64_t words = nactive + p.h_areg.size();
+    if (p.pin_ev[i]) QF_HIP(hipEventSynchronize(p.pin_ev[i]));
+    else QF_HIP(hipEventCreateWithFlags(&p.pin_ev[i], hipEventDisableTiming));
+    if (words > p.h_pin_cap[i]) {
+      // sized once for the longest lists (every filter and region), since
+      // pinned allocations and frees cost the host up to a millisecond
+      const uint64_t cap = std::max<uint64_t>(words, static_cast<uint64_t>(p.nf) + p.G);
+      (void)hipHostFree(p.h_pin[i]);
+      p.h_pin[i] = nullptr;
+      p.h_pin_cap[i] = 0;
+      if (hipHostMalloc(reinterpret_cast<void **>(&p.h_pin[i]), cap * sizeof(uint32_t), 0) != hipSuccess)
+        return fail(QF_ERR_OOM);
+      p.h_pin_cap[i] = cap;
+    }
+    std::copy(p.h_afil.begin(), p.h_afil.end(), p.h_pin[i]);
+    std::copy(p.h_areg.begin(), p.h_areg.end(), p.h_pin[i] + nactive);
+    QF_HIP(hipMemcpyAsync(p.d_afil, p.h_pin[i], nactive * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    QF_HIP(hipMemcpyAsync(p.d_areg, p.h_pin[i] + nactive, p.h_areg.size() * sizeof(uint32_t),
+                          hipMemcpyHostToDevice, s));
+    QF_HIP(hipEventRecord(p.pin_ev[i], s));
     p.nafil = nactive;
     p.nareg = static_cast<uint32_t>(p.h_areg.size());
   }
@@ -849,8 +874,18 @@ qf_set_t *qf_set_create(qf_t *const *filters, uint32_t nf) {
     return nullptr;
   }
   for (uint32_t i = 0; i < nf; ++i) st->fs[i] = filters[i];
-  const int rc = pipe_init(st->pipe, st->fs, nf, qf::Tune());
+  int rc = pipe_init(st->pipe, st->fs, nf, qf::Tune());
+  if (rc == QF_OK) {
+    std::vector<uint32_t *> lk(nf);
+    for (uint32_t i = 0; i < nf; ++i) lk[i] = st->fs[i]->plocks;
+    if (hipMalloc(reinterpret_cast<void **>(&st->d_plocks), nf * sizeof(uint32_t *)) != hipSuccess)
+      rc = QF_ERR_OOM;
+    else if (hipMemcpy(st->d_plocks, lk.data(), nf * sizeof(uint32_t *), hipMemcpyHostToDevice) != hipSuccess)
+      rc = QF_ERR_DEVICE;
+    if (rc != QF_OK) pipe_free(st->pipe);
+  }
   if (rc != QF_OK) {
+    (void)hipFree(st->d_plocks);
     delete[] st->fs;
     delete st;
     fail(rc);
@@ -863,6 +898,7 @@ void qf_set_destroy(qf_set_t *st) {
   if (!st) return;
   (void)hipDeviceSynchronize();
   pipe_free(st->pipe);
+  (void)hipFree(st->d_plocks);
   delete[] st->fs;
   delete st;
 }

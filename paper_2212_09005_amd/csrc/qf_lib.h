@@ -57,6 +57,16 @@ struct Pipe {
   uint32_t *d_afil = nullptr, *d_areg = nullptr;  // capacity nf, G
   uint32_t nafil = 0, nareg = 0;                  // 0: all filters
   std::vector<uint32_t> h_rbase, h_nreg, h_afil, h_areg;  // host copies
+  // pinned host staging of those lists, PIN_RING buffers used in turn; a
+  // buffer is rewritten only after the copy that last read it has run (its
+  // event), so a call does not wait for the stream's earlier work (a copy
+  // from pageable memory would); with a server's two update calls per set
+  // and round, the buffer reused was read two rounds before
+  static constexpr int PIN_RING = 4;
+  uint32_t *h_pin[PIN_RING] = {};
+  uint64_t h_pin_cap[PIN_RING] = {};  // words
+  hipEvent_t pin_ev[PIN_RING] = {};
+  int pin_i = 0;
   Tune tune;
   int device = 0;
   // grow-only scratch, capacity in keys
@@ -88,6 +98,7 @@ struct qf_set {
   uint32_t nf;
   qf_filter **fs;           // host copies of the handles (not owned)
   qf::Pipe pipe;
+  uint32_t **d_plocks = nullptr;  // device: each filter's point-update lock words
 };
 
 namespace qf {
@@ -161,6 +172,10 @@ uint64_t point_lock_words(uint64_t P);
 uint64_t point_regions(uint64_t P);
 hipError_t launch_point(qf_filter *f, const uint64_t *keys, uint64_t n, int del, int32_t *status,
                         uint64_t *not_found, hipStream_t s);
+// point updates over a set's filters, key i to filter fid[i] (locks: the
+// set's d_plocks); errors go to each filter's error word
+hipError_t launch_point_multi(const Pipe &p, uint32_t *const *locks, const uint32_t *fid, const uint64_t *keys,
+                              uint64_t n, int del, hipStream_t s);
 // records code as the calling thread's last error (qf_last_error) and returns it
 int record_error(int code);
 // enumeration (qf_enum.hip): scratch bytes for a filter, and the two passes:

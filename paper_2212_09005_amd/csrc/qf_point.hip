@@ -499,6 +499,57 @@ __global__ __launch_bounds__(NT) void k_point(Block<T> *b0, Block<T> *b1, PT<T> 
   }
 }
 
+// Point updates over a filter set: key i goes to filter fid[i], one lane per
+// key.  A filter's keys lie together, so a wave's lanes mostly share one
+// filter: the statistics are summed per filter over the wave (one atomic
+// per filter and word) rather than per lane.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_point_multi(const FDesc *__restrict__ desc, uint32_t *const *__restrict__ locks,
+                                                    const uint32_t *__restrict__ fid,
+                                                    const uint64_t *__restrict__ keys, uint64_t n, int del) {
+  const uint64_t i = static_cast<uint64_t>(blockIdx.x) * NT + threadIdx.x;
+  const bool valid = i < n;
+  uint32_t f = 0;
+  Delta dl;
+  if (valid) {
+    f = fid[i];
+    const FDesc &d = desc[f];
+    PT<T> t;
+    t.b = static_cast<Block<T> *>(d.blk[d.state[ST_CUR] & 1ull]);
+    t.N = d.N;
+    t.P = d.P;
+    t.nb = d.nblocks;
+    t.r = d.r;
+    t.state = d.state;
+    t.locks = locks[f];
+    const int rc = point_update(t, d.q, keys[i], del != 0, dl);
+    if (rc != QF_OK && rc != 1)
+      atomicCAS(reinterpret_cast<ull *>(&d.state[ST_ERR]), 0ull, static_cast<ull>(static_cast<int64_t>(rc)));
+  }
+  // per filter present in the wave: its lanes' sums, added by its first lane
+  const int lane = threadIdx.x & 63;
+  uint64_t left = __ballot(valid);
+  while (left) {
+    const int lead = __builtin_ctzll(left);
+    const uint32_t f0 = static_cast<uint32_t>(__shfl(static_cast<int>(f), lead));
+    const bool mine = valid && f == f0;
+    const uint64_t grp = __ballot(mine);
+    int64_t u = mine ? dl.used : 0, c = mine ? dl.dist : 0, tt = mine ? dl.total : 0;
+    for (int m = 32; m >= 1; m >>= 1) {
+      u += __shfl_xor(u, m);
+      c += __shfl_xor(c, m);
+      tt += __shfl_xor(tt, m);
+    }
+    if (lane == lead) {
+      uint64_t *st = desc[f0].state;
+      if (u) atomic_add_u64(&st[ST_USED], static_cast<uint64_t>(u));
+      if (c) atomic_add_u64(&st[ST_DIST], static_cast<uint64_t>(c));
+      if (tt) atomic_add_u64(&st[ST_TOTAL], static_cast<uint64_t>(tt));
+    }
+    left &= ~grp;
+  }
+}
+
 template <typename T>
 hipError_t point_t(qf_filter *f, const uint64_t *keys, uint64_t n, int del, int32_t *status, uint64_t *not_found,
                    hipStream_t s) {
@@ -529,6 +580,17 @@ hipError_t point_t(qf_filter *f, const uint64_t *keys, uint64_t n, int del, int3
 uint64_t point_lock_words(uint64_t P) { return ((P >> PLOCK_LOG) + 2) * PLOCK_STRIDE; }
 
 uint64_t point_regions(uint64_t P) { return (P >> PLOCK_LOG) + 1; }
+
+hipError_t launch_point_multi(const Pipe &p, uint32_t *const *locks, const uint32_t *fid, const uint64_t *keys,
+                              uint64_t n, int del, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const uint32_t grid = static_cast<uint32_t>((n + NT - 1) / NT);
+  if (p.r == 8)
+    k_point_multi<uint8_t><<<grid, NT, 0, s>>>(p.d_desc, locks, fid, keys, n, del);
+  else
+    k_point_multi<uint16_t><<<grid, NT, 0, s>>>(p.d_desc, locks, fid, keys, n, del);
+  return hipGetLastError();
+}
 
 hipError_t launch_point(qf_filter *f, const uint64_t *keys, uint64_t n, int del, int32_t *status,
                         uint64_t *not_found, hipStream_t s) {

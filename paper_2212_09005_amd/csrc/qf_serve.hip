@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -62,6 +63,8 @@ struct Stage {
   uint64_t *d_out64 = nullptr;
   uint8_t *d_out8 = nullptr;
   hipEvent_t done = nullptr;
+  hipEvent_t start = nullptr;                // the previous round's end, for the part streams
+  hipEvent_t part_done[3] = {nullptr, nullptr, nullptr};
   // per-filter deferred errors of the round, gathered on the stream after
   // the round's launches (nerr words per set, sets in order of r)
   // and, behind them, each filter's used slots past its last quotient
@@ -90,7 +93,11 @@ struct Stage {
            hipMalloc(reinterpret_cast<void **>(&d_fid), n * 4) == hipSuccess &&
            hipMalloc(reinterpret_cast<void **>(&d_out64), n * 8) == hipSuccess &&
            hipMalloc(reinterpret_cast<void **>(&d_out8), n) == hipSuccess &&
-           hipEventCreateWithFlags(&done, hipEventDisableTiming) == hipSuccess;
+           hipEventCreateWithFlags(&done, hipEventDisableTiming) == hipSuccess &&
+           hipEventCreateWithFlags(&start, hipEventDisableTiming) == hipSuccess &&
+           hipEventCreateWithFlags(&part_done[0], hipEventDisableTiming) == hipSuccess &&
+           hipEventCreateWithFlags(&part_done[1], hipEventDisableTiming) == hipSuccess &&
+           hipEventCreateWithFlags(&part_done[2], hipEventDisableTiming) == hipSuccess;
   }
   void release() {
     (void)hipHostFree(keys);
@@ -102,6 +109,9 @@ struct Stage {
     (void)hipFree(d_out64);
     (void)hipFree(d_out8);
     if (done) (void)hipEventDestroy(done);
+    if (start) (void)hipEventDestroy(start);
+    for (hipEvent_t e : part_done)
+      if (e) (void)hipEventDestroy(e);
     (void)hipFree(d_err);
     (void)hipHostFree(h_err);
     (void)hipFree(d_tail);
@@ -149,11 +159,19 @@ struct qf_server {
   bool stop = false;
   std::thread loop;
   hipStream_t stream = nullptr;
+  // a round's parts run on three streams (queries and counts; r = 8 updates;
+  // r = 16 updates): they touch different filters or only read, and the two
+  // update streams each keep their set's pipeline to one call at a time
+  hipStream_t pstream[3] = {nullptr, nullptr, nullptr};
   Stage stage[2];
   std::map<uint32_t, SetOf> sets;  // by r
   bool sets_dirty = true;
   uint64_t rounds = 0, requests = 0, keys = 0, seq = 0;
   uint64_t upd_point = 0, upd_bulk = 0;  // update requests by path
+  // loop thread's time (ns): forming rounds, launching them (host side),
+  // waiting for the device, completing them (outputs, statuses, closes)
+  std::atomic<uint64_t> ns_form{0}, ns_launch{0}, ns_wait{0}, ns_complete{0};
+  std::atomic<uint64_t> ns_stage{0};  // of ns_launch: copying keys into the pinned stage
   // serving thread only: per filter id, a bound on its used slots past the
   // last quotient (measured after each update round, plus 3 per key
   // inserted since)
@@ -300,17 +318,28 @@ Round form_round_locked(qf_server *s) {
   return rd;
 }
 
+uint64_t ns_since(std::chrono::steady_clock::time_point t0) {
+  return static_cast<uint64_t>(
+      std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now() - t0).count());
+}
+
+constexpr unsigned STAGE_THREADS = 8;  // host threads that stage one large part
+
 // Choose each update's path.  A filter's keys of the round are applied in
 // place (point updates: one lane per key under region locks, cost following
-// the keys) when there are no more of them than the filter has lock regions
-// (so lanes seldom wait for one another) and they cannot run out of room:
-// each key adds at most 3 used slots, and the used slots past the last
+// the keys) when there are at most INPLACE_PER_REGION of them per lock region
+// of the filter (so lanes seldom wait for one another, and at about 2.5 ns
+// per point update against about 5 ps per slot for the bulk merge they cost
+// less than rewriting the filter) and, for inserts, they cannot run out of
+// room: each key adds at most 3 used slots, and the used slots past the last
 // quotient form one stretch whose length is bounded by tail_hi, so
 // tail_hi + 3 n + 3 <= E keeps every shift inside the table and no key can
-// fail for lack of room (the request stays all or nothing).  The rest go
-// through the bulk merge, which rewrites every block of the filter.  The
-// part is reordered (in-place filters first, then by filter, each filter's
-// requests in submission order) so that each filter's keys lie together.
+// fail for lack of room (the request stays all or nothing; deletes never
+// need room).  The rest go through the bulk merge, which rewrites every block
+// of the filter.  The part is reordered (in-place filters first, then by
+// filter, each filter's requests in submission order) so that each filter's
+// keys lie together.
+constexpr uint64_t INPLACE_PER_REGION = 4;
 void plan_updates(qf_server *s, Round &rd) {
   for (Part &p : rd.parts) {
     if (p.op != OP_INSERT && p.op != OP_DELETE) continue;
@@ -322,7 +351,8 @@ void plan_updates(qf_server *s, Round &rd) {
       const qf_filter *f = so.set->fs[so.idx[kv.first]];
       const uint64_t n = kv.second, room = f->P - f->N;
       const uint64_t t = s->tail_hi[kv.first];
-      inplace[kv.first] = n > 0 && n <= qf::point_regions(f->P) && t + 3 * n + 3 <= room;
+      inplace[kv.first] = n > 0 && n <= INPLACE_PER_REGION * qf::point_regions(f->P) &&
+                          (p.op == OP_DELETE || t + 3 * n + 3 <= room);
       if (p.op == OP_INSERT) {
         rd.ins[kv.first] += n;
         s->tail_hi[kv.first] = t + 3 * n;
@@ -346,96 +376,142 @@ void plan_updates(qf_server *s, Round &rd) {
 }
 
 // Enqueue a round on the stream (no waiting).
-int launch_round(qf_server *s, Round &rd, Stage &st) {
-  plan_updates(s, rd);
-  uint64_t base = 0;
-  for (Part &p : rd.parts) {
-    SetOf &so = s->sets[p.r];
-    for (size_t k = 0; k < p.reqs.size(); ++k) {
-      Req *q = p.reqs[k];
+// Copy a part's keys and filter indexes into the pinned stage at base.  A
+// large part is split over a few threads by bytes (one core's copy rate
+// left the device idle between rounds).
+void stage_part(qf_server *s, const Part &p, Stage &st, uint64_t base) {
+  const SetOf &so = s->sets.at(p.r);
+  std::vector<uint32_t> fi(p.reqs.size());
+  for (size_t k = 0; k < p.reqs.size(); ++k) fi[k] = so.idx.at(p.reqs[k]->id);
+  auto copy = [&](size_t a, size_t b) {
+    for (size_t k = a; k < b; ++k) {
+      const Req *q = p.reqs[k];
       const uint64_t o = base + p.off[k];
       std::memcpy(st.keys + o, q->keys.data(), q->keys.size() * 8);
-      std::fill(st.fid + o, st.fid + o + q->keys.size(), so.idx[q->id]);
+      std::fill(st.fid + o, st.fid + o + q->keys.size(), fi[k]);
     }
-    base += p.n;
+  };
+  constexpr uint64_t PER_THREAD = 1ull << 16;  // keys (768 KB of staging)
+  const unsigned nt = static_cast<unsigned>(std::min<uint64_t>(STAGE_THREADS, p.n / PER_THREAD));
+  if (nt < 2 || p.reqs.size() < 2) {
+    copy(0, p.reqs.size());
+    return;
   }
-  if (base) {
-    if (hipMemcpyAsync(st.d_keys, st.keys, base * 8, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
-        hipMemcpyAsync(st.d_fid, st.fid, base * 4, hipMemcpyHostToDevice, s->stream) != hipSuccess)
-      return QF_ERR_DEVICE;
+  // request ranges of about p.n / nt keys each
+  std::vector<size_t> cut{0};
+  for (size_t k = 0; k < p.reqs.size() && cut.size() < nt; ++k)
+    if (p.off[k] >= p.n / nt * cut.size()) cut.push_back(k);
+  cut.push_back(p.reqs.size());
+  std::vector<std::thread> th;
+  for (size_t i = 1; i + 1 < cut.size(); ++i) th.emplace_back(copy, cut[i], cut[i + 1]);
+  copy(cut[0], cut[1]);
+  for (auto &t : th) t.join();
+}
+
+// Stage, send and launch one part on stream ps (stage offset base).
+int launch_part(qf_server *s, Part &p, Stage &st, uint64_t base, hipStream_t ps) {
+  // each part is staged and sent on its own, so the device starts on the
+  // first part while the host stages the next
+  const auto t0 = std::chrono::steady_clock::now();
+  stage_part(s, p, st, base);
+  s->ns_stage += ns_since(t0);
+  if (p.n && (hipMemcpyAsync(st.d_keys + base, st.keys + base, p.n * 8, hipMemcpyHostToDevice, ps) != hipSuccess ||
+              hipMemcpyAsync(st.d_fid + base, st.fid + base, p.n * 4, hipMemcpyHostToDevice, ps) != hipSuccess))
+    return QF_ERR_DEVICE;
+  const SetOf &so = s->sets.at(p.r);
+  qf_set_t *set = so.set;
+  const uint64_t *k = st.d_keys + base;
+  const uint32_t *f = st.d_fid + base;
+  int rc = QF_OK;
+  if (p.op == OP_INSERT || p.op == OP_DELETE) {
+    // in place: one launch over the keys of every such filter (errors go
+    // to each filter's error word, as a merge's do)
+    if (p.n_point &&
+        qf::launch_point_multi(set->pipe, set->d_plocks, f, k, p.n_point, p.op == OP_DELETE, ps) != hipSuccess)
+      rc = QF_ERR_DEVICE;
+    // in bulk: merge only the filters of the rest of the part
+    std::vector<uint32_t> act;
+    for (size_t a = 0; a < p.reqs.size(); ++a)
+      if (!p.pt[a] && !p.reqs[a]->keys.empty()) act.push_back(so.idx.at(p.reqs[a]->id));
+    std::sort(act.begin(), act.end());
+    act.erase(std::unique(act.begin(), act.end()), act.end());
+    const uint64_t np = p.n_point, nb = p.n - p.n_point;
+    if (!rc && !act.empty()) {
+      if (p.op == OP_INSERT)
+        rc = qf_set_insert_some(set, act.data(), static_cast<uint32_t>(act.size()), f + np, k + np, nb, ps);
+      else
+        rc = qf_set_delete_some(set, act.data(), static_cast<uint32_t>(act.size()), f + np, k + np, nb, nullptr, ps);
+    }
   }
-  base = 0;
+  if (p.op == OP_QUERY) {
+    rc = qf_set_query_batch(set, f, k, p.n, st.d_out8 + base, ps);
+    if (!rc && hipMemcpyAsync(st.out8 + base, st.d_out8 + base, p.n, hipMemcpyDeviceToHost, ps))
+      rc = QF_ERR_DEVICE;
+  }
+  if (p.op == OP_COUNT) {
+    rc = qf_set_count_batch(set, f, k, p.n, st.d_out64 + base, ps);
+    if (!rc && hipMemcpyAsync(st.out64 + base, st.d_out64 + base, p.n * 8, hipMemcpyDeviceToHost, ps))
+      rc = QF_ERR_DEVICE;
+  }
+  return rc;
+}
+
+int launch_round(qf_server *s, Round &rd, Stage &st) {
+  plan_updates(s, rd);
+  // the part streams start behind everything the main stream holds: the
+  // previous round, whose queries may read filters this round updates
+  int rc = hipEventRecord(st.start, s->stream) == hipSuccess ? QF_OK : QF_ERR_DEVICE;
+  for (hipStream_t ps : s->pstream)
+    if (!rc && hipStreamWaitEvent(ps, st.start, 0) != hipSuccess) rc = QF_ERR_DEVICE;
+  // the parts of each stream, with their stage offsets (round order)
+  std::vector<std::pair<Part *, uint64_t>> by[3];
+  uint64_t base = 0;
   for (Part &p : rd.parts) {
-    qf_set_t *set = s->sets[p.r].set;
-    const uint64_t *k = st.d_keys + base;
-    const uint32_t *f = st.d_fid + base;
-    int rc = QF_OK;
-    if (p.op == OP_INSERT || p.op == OP_DELETE) {
-      SetOf &so = s->sets[p.r];
-      // in place: one launch per filter over its keys (errors go to the
-      // filter's error word, as a merge's do)
-      for (size_t a = 0; a < p.reqs.size() && p.pt[a] && !rc;) {
-        const int id = p.reqs[a]->id;
-        size_t e = a;
-        while (e < p.reqs.size() && p.pt[e] && p.reqs[e]->id == id) ++e;
-        const uint64_t lo = p.off[a], hi = e < p.reqs.size() ? p.off[e] : p.n;
-        if (hi > lo && qf::launch_point(so.set->fs[so.idx[id]], k + lo, hi - lo, p.op == OP_DELETE, nullptr,
-                                        nullptr, s->stream) != hipSuccess)
-          rc = QF_ERR_DEVICE;
-        a = e;
-      }
-      // in bulk: merge only the filters of the rest of the part
-      std::vector<uint32_t> act;
-      for (size_t a = 0; a < p.reqs.size(); ++a)
-        if (!p.pt[a] && !p.reqs[a]->keys.empty()) act.push_back(so.idx[p.reqs[a]->id]);
-      std::sort(act.begin(), act.end());
-      act.erase(std::unique(act.begin(), act.end()), act.end());
-      const uint64_t np = p.n_point, nb = p.n - p.n_point;
-      if (!rc && !act.empty()) {
-        if (p.op == OP_INSERT)
-          rc = qf_set_insert_some(set, act.data(), static_cast<uint32_t>(act.size()), f + np, k + np, nb,
-                                  s->stream);
-        else
-          rc = qf_set_delete_some(set, act.data(), static_cast<uint32_t>(act.size()), f + np, k + np, nb,
-                                  nullptr, s->stream);
-      }
-    }
-    if (p.op == OP_QUERY) {
-      rc = qf_set_query_batch(set, f, k, p.n, st.d_out8 + base, s->stream);
-      if (!rc && hipMemcpyAsync(st.out8 + base, st.d_out8 + base, p.n, hipMemcpyDeviceToHost, s->stream))
-        rc = QF_ERR_DEVICE;
-    }
-    if (p.op == OP_COUNT) {
-      rc = qf_set_count_batch(set, f, k, p.n, st.d_out64 + base, s->stream);
-      if (!rc && hipMemcpyAsync(st.out64 + base, st.d_out64 + base, p.n * 8, hipMemcpyDeviceToHost, s->stream))
-        rc = QF_ERR_DEVICE;
-    }
-    if (rc) return rc;
+    const int si = (p.op == OP_QUERY || p.op == OP_COUNT) ? 0 : (p.r == 8 ? 1 : 2);
+    by[si].emplace_back(&p, base);
     base += p.n;
   }
+  bool used[3];
+  for (int i = 0; i < 3; ++i) {
+    used[i] = !by[i].empty();
+    for (auto &pb : by[i]) {
+      if (!rc) rc = launch_part(s, *pb.first, st, pb.second, s->pstream[i]);
+    }
+  }
+  // the main stream waits for every part stream that took work
+  for (int i = 0; i < 3; ++i)
+    if (used[i] && (hipEventRecord(st.part_done[i], s->pstream[i]) != hipSuccess ||
+                    hipStreamWaitEvent(s->stream, st.part_done[i], 0) != hipSuccess) && !rc)
+      rc = QF_ERR_DEVICE;
   // this round's per-filter errors, taken on the stream behind its updates
   bool updates = false;
   for (Part &p : rd.parts) updates |= p.op == OP_INSERT || p.op == OP_DELETE;
-  if (updates && st.nerr) {
+  if (!rc && updates && st.nerr) {
     uint32_t o = 0;
     for (auto &kv : s->sets) {
       if (qf::launch_take_errors(kv.second.set->pipe, st.d_err + o, s->stream) != hipSuccess ||
           qf::launch_take_tails(kv.second.set->pipe, st.d_tail + o, s->stream) != hipSuccess)
-        return QF_ERR_DEVICE;
+        rc = QF_ERR_DEVICE;
       o += static_cast<uint32_t>(kv.second.ids.size());
     }
-    if (hipMemcpyAsync(st.h_err, st.d_err, st.nerr * 8, hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
-        hipMemcpyAsync(st.h_tail, st.d_tail, st.nerr * 8, hipMemcpyDeviceToHost, s->stream) != hipSuccess)
-      return QF_ERR_DEVICE;
+    if (!rc && (hipMemcpyAsync(st.h_err, st.d_err, st.nerr * 8, hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
+                hipMemcpyAsync(st.h_tail, st.d_tail, st.nerr * 8, hipMemcpyDeviceToHost, s->stream) != hipSuccess))
+      rc = QF_ERR_DEVICE;
   }
-  return hipEventRecord(st.done, s->stream) == hipSuccess ? QF_OK : QF_ERR_DEVICE;
+  if (hipEventRecord(st.done, s->stream) != hipSuccess && !rc) rc = QF_ERR_DEVICE;
+  return rc;
 }
 
 // Wait for a launched round, copy outputs, set statuses, run its closes.
 // next: the round launched after it, if any (its inserts count against the
 // room measured at the end of this one).
 void complete_round(qf_server *s, Round &rd, Stage &st, int launch_rc, const Round *next) {
-  if (!rd.parts.empty()) (void)hipEventSynchronize(st.done);
+  if (!rd.parts.empty()) {
+    const auto t0 = std::chrono::steady_clock::now();
+    (void)hipEventSynchronize(st.done);
+    s->ns_wait += static_cast<uint64_t>(
+        std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now() - t0).count());
+  }
   // per-filter errors of this round (updates only)
   std::map<int, int> err;
   bool updates = false;
@@ -501,6 +577,7 @@ void complete_round(qf_server *s, Round &rd, Stage &st, int launch_rc, const Rou
   s->cv_done.notify_all();
 }
 
+
 void serve(qf_server *s) {
   (void)hipSetDevice(s->device);
   Round inflight;
@@ -521,11 +598,24 @@ void serve(qf_server *s) {
         (void)rebuild_sets(s);
         lk.lock();
       }
-      if (!s->sets_dirty) rd = form_round_locked(s);
+      if (!s->sets_dirty) {
+        const auto t0 = std::chrono::steady_clock::now();
+        rd = form_round_locked(s);
+        s->ns_form += ns_since(t0);
+      }
     }
     int rc = QF_OK;
-    if (!rd.parts.empty()) rc = launch_round(s, rd, s->stage[cur]);
-    if (have) complete_round(s, inflight, s->stage[cur ^ 1], inflight_rc, rd.empty() ? nullptr : &rd);
+    if (!rd.parts.empty()) {
+      const auto t0 = std::chrono::steady_clock::now();
+      rc = launch_round(s, rd, s->stage[cur]);
+      s->ns_launch += ns_since(t0);
+    }
+    if (have) {
+      const auto t0 = std::chrono::steady_clock::now();
+      const uint64_t w0 = s->ns_wait;
+      complete_round(s, inflight, s->stage[cur ^ 1], inflight_rc, rd.empty() ? nullptr : &rd);
+      s->ns_complete += ns_since(t0) - (s->ns_wait - w0);
+    }
     have = !rd.empty();
     if (have) {
       inflight = rd;
@@ -549,10 +639,13 @@ qfs_t *qfs_create(uint64_t budget_bytes, uint64_t max_round_keys) {
   (void)hipGetDevice(&s->device);
   bool ok = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess &&
             s->stage[0].alloc(max_round_keys) && s->stage[1].alloc(max_round_keys);
+  for (hipStream_t &ps : s->pstream) ok = ok && hipStreamCreateWithFlags(&ps, hipStreamNonBlocking) == hipSuccess;
   if (!ok) {
     s->stage[0].release();
     s->stage[1].release();
     if (s->stream) (void)hipStreamDestroy(s->stream);
+    for (hipStream_t ps : s->pstream)
+      if (ps) (void)hipStreamDestroy(ps);
     delete s;
     return nullptr;
   }
@@ -578,6 +671,7 @@ void qfs_destroy(qfs_t *s) {
   s->stage[0].release();
   s->stage[1].release();
   (void)hipStreamDestroy(s->stream);
+  for (hipStream_t ps : s->pstream) (void)hipStreamDestroy(ps);
   delete s;
 }
 
@@ -605,14 +699,18 @@ int qfs_submit(qfs_t *s, int op, int id, const uint64_t *h_keys, uint64_t n, voi
   q->out = h_out;
   q->tag = tag;
   q->status = QF_OK;
+  if (n > s->max_round) {
+    delete q;
+    return QF_ERR_ARG;
+  }
+  q->keys.assign(h_keys, h_keys + n);  // (outside the lock: the loop thread waits for it)
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if (id < 0 || static_cast<size_t>(id) >= s->slots.size() || s->slots[id].state == Slot::CLOSED ||
-        s->slots[id].closing || n > s->max_round) {
+        s->slots[id].closing) {
       delete q;
       return QF_ERR_ARG;
     }
-    q->keys.assign(h_keys, h_keys + n);
     q->seq = s->seq++;
     s->queue.push_back(q);
   }
@@ -702,6 +800,11 @@ int qfs_stats(qfs_t *s, uint64_t *st) {
   st[7] = s->queue.size();
   st[8] = s->upd_point;
   st[9] = s->upd_bulk;
+  st[10] = s->ns_form;
+  st[11] = s->ns_launch;
+  st[12] = s->ns_wait;
+  st[13] = s->ns_complete;
+  st[14] = s->ns_stage;
   return QF_OK;
 }
 

@@ -790,8 +790,8 @@ class Server:
         return res
 
     def stats(self) -> dict:
-        buf = (ctypes.c_uint64 * 10)()
+        buf = (ctypes.c_uint64 * 15)()
         _check(lib().qfs_stats(self.h, buf), "qfs_stats")
         keys = ("rounds", "requests", "keys", "open", "pending", "bytes_used", "budget", "waiting",
-                "updates_in_place", "updates_bulk")
+                "updates_in_place", "updates_bulk", "ns_form", "ns_launch", "ns_wait", "ns_complete", "ns_stage")
         return dict(zip(keys, (int(v) for v in buf)))
