@@ -106,6 +106,11 @@ struct Bench {
   }
 };
 
+// A candidate replaces the one in hand only when it is faster by more than
+// this fraction: the defaults are measured first, and differences within
+// run-to-run noise no longer move the pick.
+constexpr double MARGIN = 0.03;
+
 int tune(const uint32_t *qs, uint32_t nf, uint32_t r, double load, uint64_t n_query, qf_tuning_t *best,
          double *ms_out) {
   // the sample: every k-th filter, at most SAMPLE_SLOTS quotients in total
@@ -184,7 +189,7 @@ int tune(const uint32_t *qs, uint32_t nf, uint32_t r, double load, uint64_t n_qu
     if ((rc = qf_set_tune(b.set, &t)) != QF_OK) return rc;
     const double ms = b.insert_ms();
     if (ms < 0) return QF_ERR_DEVICE;
-    if (ms < best_ins) {
+    if (ms < best_ins * (1.0 - MARGIN)) {
       best_ins = ms;
       pick = t;
     }
@@ -199,7 +204,7 @@ int tune(const uint32_t *qs, uint32_t nf, uint32_t r, double load, uint64_t n_qu
     if ((rc = qf_set_tune(b.set, &t)) != QF_OK) return rc;
     const double ms = b.insert_ms();
     if (ms < 0) return QF_ERR_DEVICE;
-    if (ms < best_ins) {
+    if (ms < best_ins * (1.0 - MARGIN)) {
       best_ins = ms;
       pick = t;
     }
@@ -215,7 +220,7 @@ int tune(const uint32_t *qs, uint32_t nf, uint32_t r, double load, uint64_t n_qu
     if ((rc = qf_set_tune(b.set, &t)) != QF_OK) return rc;
     const double ms = b.query_ms();
     if (ms < 0) return QF_ERR_DEVICE;
-    if (ms < best_q) {
+    if (ms < best_q * (1.0 - MARGIN)) {
       best_q = ms;
       pick = t;
     }
