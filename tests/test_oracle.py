@@ -465,3 +465,55 @@ def test_kv_lookup_by_hand_and_by_brute_force():
     for k, x, c in zip(brute.fingerprints(probe, q, r - v).tolist(), val.tolist(), n.tolist()):
         s = want.get(k, set())
         assert c == len(s) and (x == min(s) if s else x == 2**64 - 1)
+
+
+# ---- two layout facts the serving loop's in-place path relies on ----------
+
+@pytest.mark.parametrize("q,load", [(8, 0.9), (10, 0.95), (10, 0.99), (12, 0.97)])
+def test_used_slots_past_the_last_quotient_from_block_offset(q, load):
+    # Slots at or past N are used only as one stretch from N that ends at the
+    # table's last run end, and block N/64's offset gives it: off + 1 when
+    # off > 0 or slot N ends a run, else 0.
+    r = 8
+    N = 1 << q
+    seen = 0
+    for seed in range(6):
+        keys = inputs.uniform_keys(1000 * q + seed, int(load * N))
+        ms = brute.multiset(brute.fingerprints(keys, q, r))
+        lay = brute.layout(ms[0], ms[1], q, r)
+        bits = np.unpackbits(np.asarray(lay.runend_words, dtype=np.uint64).view(np.uint8), bitorder="little")
+        slots = np.asarray(lay.slots)
+        ends = np.nonzero(bits)[0]
+        t_true = max(0, int(ends.max()) + 1 - N) if len(ends) else 0
+        # the stretch is contiguous: every slot of [N, N + t) holds something
+        # of a run (a remainder or counter digit, possibly 0) and none after
+        # it ends a run
+        assert not bits[N + t_true:].any()
+        off = int(np.asarray(lay.offsets)[N // 64])
+        t = off + 1 if (off or bits[N]) else 0
+        assert t == t_true, (seed, t, t_true)
+        assert (slots[N + t_true:] == 0).all()
+        seen += t_true > 0
+    assert seen > 0 or load < 0.95
+
+
+@pytest.mark.parametrize("rem", [0, 1, 77, 255])
+def test_one_more_instance_adds_at_most_three_used_slots(rem):
+    # the bound behind the in-place path's room test: each inserted key adds
+    # at most 3 used slots (remainder 0 going from 2 to 3 copies adds 3)
+    q, r = 8, 8
+    prev, worst = 0, 0
+    for c in range(1, 1500):
+        lay = brute.layout(np.array([(5 << r) | rem], dtype=np.uint64), np.array([c], dtype=np.uint64), q, r)
+        used = int(lay.header[5])
+        worst = max(worst, used - prev)
+        prev = used
+    assert worst <= 3
+    # and next to other runs the growth is the same: the run's own slots
+    base = inputs.uniform_keys(9, 200)
+    ms0 = brute.multiset(brute.fingerprints(base, q, r))
+    u0 = int(brute.layout(ms0[0], ms0[1], q, r).header[5])
+    extra = keys_for_fingerprints(np.array([(5 << r) | rem], dtype=np.uint64), q, r)
+    ms1 = brute.merge_multisets(ms0, brute.multiset(brute.fingerprints(extra, q, r)))
+    u1 = int(brute.layout(ms1[0], ms1[1], q, r).header[5])
+    assert 0 <= u1 - u0 <= 3
