@@ -326,20 +326,25 @@ uint64_t ns_since(std::chrono::steady_clock::time_point t0) {
 constexpr unsigned STAGE_THREADS = 8;  // host threads that stage one large part
 
 // Choose each update's path.  A filter's keys of the round are applied in
-// place (point updates: one lane per key under region locks, cost following
-// the keys) when there are at most INPLACE_PER_REGION of them per lock region
-// of the filter (so lanes seldom wait for one another, and at about 2.5 ns
-// per point update against about 5 ps per slot for the bulk merge they cost
-// less than rewriting the filter) and, for inserts, they cannot run out of
-// room: each key adds at most 3 used slots, and the used slots past the last
-// quotient form one stretch whose length is bounded by tail_hi, so
-// tail_hi + 3 n + 3 <= E keeps every shift inside the table and no key can
-// fail for lack of room (the request stays all or nothing; deletes never
-// need room).  The rest go through the bulk merge, which rewrites every block
-// of the filter.  The part is reordered (in-place filters first, then by
-// filter, each filter's requests in submission order) so that each filter's
-// keys lie together.
-constexpr uint64_t INPLACE_PER_REGION = 4;
+// place (point updates: one lane per key under region locks) when the filter
+// has at least 2^INPLACE_MIN_Q quotients, there are at most
+// INPLACE_PER_REGION of them per lock region, and, for inserts, they cannot
+// run out of room.  A point update is a chain of dependent device-scope
+// steps (lock, plan, shift, fences, unlock) of some 80 us, while the bulk
+// merge costs about 5 ps per slot of the filter plus the batch pipeline's
+// launches, shared by every filter of the part: measured with 4096 keys at
+// load 0.5, in place took 87 us against 317 us merged at 2^26 quotients, but
+// the merge won below about 2^23.  Few keys per region keep lanes from
+// waiting for each other.  The room test: each key adds at most 3 used
+// slots, and the used slots past the last quotient form one stretch whose
+// length is bounded by tail_hi, so tail_hi + 3 n + 3 <= E keeps every shift
+// inside the table and no key can fail for lack of room (the request stays
+// all or nothing; deletes never need room).  The rest go through the bulk
+// merge, which rewrites every block of the filter.  The part is reordered
+// (in-place filters first, then by filter, each filter's requests in
+// submission order) so that each filter's keys lie together.
+constexpr uint64_t INPLACE_PER_REGION = 2;
+constexpr uint32_t INPLACE_MIN_Q = 23;
 void plan_updates(qf_server *s, Round &rd) {
   for (Part &p : rd.parts) {
     if (p.op != OP_INSERT && p.op != OP_DELETE) continue;
@@ -351,7 +356,7 @@ void plan_updates(qf_server *s, Round &rd) {
       const qf_filter *f = so.set->fs[so.idx[kv.first]];
       const uint64_t n = kv.second, room = f->P - f->N;
       const uint64_t t = s->tail_hi[kv.first];
-      inplace[kv.first] = n > 0 && n <= INPLACE_PER_REGION * qf::point_regions(f->P) &&
+      inplace[kv.first] = n > 0 && f->q >= INPLACE_MIN_Q && n <= INPLACE_PER_REGION * qf::point_regions(f->P) &&
                           (p.op == OP_DELETE || t + 3 * n + 3 <= room);
       if (p.op == OP_INSERT) {
         rd.ins[kv.first] += n;
