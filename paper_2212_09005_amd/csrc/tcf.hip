@@ -606,24 +606,42 @@ __global__ __launch_bounds__(NT) void k_del_backing(const uint64_t *__restrict__
   }
 }
 
-// lookups of the bulk form: binary search of the tag in both sorted blocks,
-// then of the identity in the sorted backing array
+// lookups of the bulk form: 16 lanes per key, each testing 8 tags of each
+// candidate block (one 16-byte load per block and lane, so a key's two
+// 256-byte blocks arrive in one round trip instead of a chain of dependent
+// binary-search probes); a miss in both blocks then searches the sorted
+// backing array for the key's identity
 __global__ __launch_bounds__(NT) void k_bulk_query(const uint16_t *__restrict__ slots, uint64_t nb,
                                                    const uint64_t *__restrict__ bk, uint64_t bn,
                                                    const uint64_t *__restrict__ keys, uint64_t n,
                                                    uint8_t *__restrict__ out) {
-  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * NT;
-  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * NT + threadIdx.x; i < n; i += stride) {
-    const TK k = key_of(keys[i], nb);
-    const uint16_t *x = slots + static_cast<uint64_t>(k.b1) * BB, *y = slots + static_cast<uint64_t>(k.b2) * BB;
-    const uint32_t px = lb16(x, BB, k.tag), py = lb16(y, BB, k.tag);
-    bool hit = (px < BB && x[px] == k.tag) || (py < BB && y[py] == k.tag);
-    if (!hit && bn) {
-      const uint64_t pk = pair_of(k.b1, k.b2, k.tag);
-      const uint64_t p = lower_bound(bk, bn, pk);
-      hit = p < bn && bk[p] == pk;
+  constexpr uint32_t LPK = 16;  // lanes per key: LPK x 16 bytes = one block of BB tags
+  static_assert(LPK * 8 == BB, "16 lanes of 8 tags cover a block");
+  const int lane = threadIdx.x & 63, g = lane / LPK, l = lane % LPK;
+  const uint64_t per_grid = static_cast<uint64_t>(gridDim.x) * (NT / LPK);
+  // (the loop bound is the wave's first key, so every lane of a wave takes
+  // every trip and the ballot sees the whole wave)
+  for (uint64_t i0 = (static_cast<uint64_t>(blockIdx.x) * NT + (threadIdx.x & ~63u)) / LPK; i0 < n; i0 += per_grid) {
+    const uint64_t i = i0 + static_cast<uint64_t>(g);
+    const bool valid = i < n;
+    TK k{0, 0, 0, 0};
+    bool m = false;
+    if (valid) {
+      k = key_of(keys[i], nb);
+      const u64x2 vx = reinterpret_cast<const u64x2 *>(slots + static_cast<uint64_t>(k.b1) * BB)[l];
+      const u64x2 vy = reinterpret_cast<const u64x2 *>(slots + static_cast<uint64_t>(k.b2) * BB)[l];
+      m = (eq16(vx.x, k.tag) | eq16(vx.y, k.tag) | eq16(vy.x, k.tag) | eq16(vy.y, k.tag)) != 0;
     }
-    out[i] = hit ? 1 : 0;
+    const uint64_t bal = __ballot(m);
+    bool hit = ((bal >> (g * LPK)) & 0xFFFFull) != 0;
+    if (valid && l == 0) {
+      if (!hit && bn) {
+        const uint64_t pk = pair_of(k.b1, k.b2, k.tag);
+        const uint64_t p = lower_bound(bk, bn, pk);
+        hit = p < bn && bk[p] == pk;
+      }
+      out[i] = hit ? 1 : 0;
+    }
   }
 }
 
@@ -894,7 +912,8 @@ int tcf_query(tcf_t *t, const uint64_t *d_keys, uint64_t n, uint8_t *d_out, void
     tcf::k_point_query<<<tcf::grid_for(n), tcf::NT, 0, s>>>(reinterpret_cast<const uint64_t *>(t->slots), t->nb,
                                                             t->backing, t->nbt, d_keys, n, d_out);
   else
-    tcf::k_bulk_query<<<tcf::grid_for(n), tcf::NT, 0, s>>>(t->slots, t->nb, t->backing, t->bn, d_keys, n, d_out);
+    tcf::k_bulk_query<<<tcf::grid_for(n * 16), tcf::NT, 0, s>>>(t->slots, t->nb, t->backing, t->bn, d_keys, n,
+                                                                d_out);
   TCF_HIP(hipGetLastError());
   return QF_OK;
 }
