@@ -606,13 +606,26 @@ __global__ __launch_bounds__(NT) void k_del_backing(const uint64_t *__restrict__
   }
 }
 
+// Directory of the bulk form's sorted backing array: dir[d] = the first
+// entry whose smaller block index is at least d << DIR_LOG (an entry's key
+// starts with that index), for d in [0, nd); dir[nd - 1] = bn.
+constexpr uint32_t DIR_LOG = 6;
+__global__ __launch_bounds__(NT) void k_dir(const uint64_t *__restrict__ bk, uint64_t bn, uint32_t *__restrict__ dir,
+                                            uint64_t nd) {
+  const uint64_t d = static_cast<uint64_t>(blockIdx.x) * NT + threadIdx.x;
+  if (d >= nd) return;
+  dir[d] = static_cast<uint32_t>(d + 1 == nd ? bn : lower_bound(bk, bn, (d << DIR_LOG) << 40));
+}
+
 // lookups of the bulk form: 16 lanes per key, each testing 8 tags of each
 // candidate block (one 16-byte load per block and lane, so a key's two
 // 256-byte blocks arrive in one round trip instead of a chain of dependent
-// binary-search probes); a miss in both blocks then searches the sorted
-// backing array for the key's identity
+// binary-search probes); a miss in both blocks then searches the part of
+// the sorted backing array that the directory gives for the key's smaller
+// block (a few entries) for the key's identity
 __global__ __launch_bounds__(NT) void k_bulk_query(const uint16_t *__restrict__ slots, uint64_t nb,
                                                    const uint64_t *__restrict__ bk, uint64_t bn,
+                                                   const uint32_t *__restrict__ dir,
                                                    const uint64_t *__restrict__ keys, uint64_t n,
                                                    uint8_t *__restrict__ out) {
   constexpr uint32_t LPK = 16;  // lanes per key: LPK x 16 bytes = one block of BB tags
@@ -637,8 +650,10 @@ __global__ __launch_bounds__(NT) void k_bulk_query(const uint16_t *__restrict__ 
     if (valid && l == 0) {
       if (!hit && bn) {
         const uint64_t pk = pair_of(k.b1, k.b2, k.tag);
-        const uint64_t p = lower_bound(bk, bn, pk);
-        hit = p < bn && bk[p] == pk;
+        const uint32_t d = (k.b1 < k.b2 ? k.b1 : k.b2) >> DIR_LOG;
+        const uint64_t a = dir[d], e = dir[d + 1];
+        const uint64_t p = a + lower_bound(bk + a, e - a, pk);
+        hit = p < e && bk[p] == pk;
       }
       out[i] = hit ? 1 : 0;
     }
@@ -674,6 +689,8 @@ struct tcf_filter {
   uint64_t *backing = nullptr;
   uint64_t *state = nullptr;
   uint64_t bn = 0;  // bulk: backing entries in use
+  uint32_t *dir = nullptr;  // bulk: directory of the backing array (nd words)
+  uint64_t nd = 0;
   int device = 0;
   uint64_t bytes = 0;
   // bulk scratch
@@ -784,6 +801,7 @@ int bulk_insert(tcf_filter *t, const uint64_t *keys, uint64_t n, hipStream_t s) 
     if (int rc = sort64(t, t->backing, t->bk_tmp, t->bn + over, s)) return rc;
     t->bn += over;
     k_set_words<<<1, 64, 0, s>>>(t->state, TS_BACK, 1, t->bn);
+    k_dir<<<blocks_for(t->nd), NT, 0, s>>>(t->backing, t->bn, t->dir, t->nd);
   }
   k_add_word<<<1, 64, 0, s>>>(t->state, TS_HELD, n - over);
   TCF_HIP(hipGetLastError());
@@ -818,6 +836,7 @@ int bulk_delete(tcf_filter *t, const uint64_t *keys, uint64_t n, uint64_t *not_f
       std::swap(t->backing, t->bk_tmp);
       t->bn -= removed;
       k_set_words<<<1, 64, 0, s>>>(t->state, TS_BACK, 1, t->bn);
+      k_dir<<<blocks_for(t->nd), NT, 0, s>>>(t->backing, t->bn, t->dir, t->nd);
     }
   }
   TCF_HIP(hipGetLastError());
@@ -855,7 +874,9 @@ tcf_t *tcf_create(uint64_t nblocks, int kind) {
     ok = hipMalloc(&t->gs1, (nblocks + 1) * 4) == hipSuccess && hipMalloc(&t->gs2, (nblocks + 1) * 4) == hipSuccess &&
          hipMalloc(&t->ps, nblocks * 4) == hipSuccess && hipMalloc(&t->pf, nblocks * 4) == hipSuccess &&
          hipMalloc(&t->bk_tmp, t->nbt * 8) == hipSuccess;
-    t->bytes += 4 * (nblocks + 1) * 4 + t->nbt * 8;
+    t->nd = (nblocks >> tcf::DIR_LOG) + 2;
+    ok = ok && hipMalloc(&t->dir, t->nd * 4) == hipSuccess && hipMemset(t->dir, 0, t->nd * 4) == hipSuccess;
+    t->bytes += 4 * (nblocks + 1) * 4 + t->nbt * 8 + t->nd * 4;
   }
   if (!ok) {
     tcf_destroy(t);
@@ -876,6 +897,7 @@ void tcf_destroy(tcf_t *t) {
   (void)hipFree(t->ps);
   (void)hipFree(t->pf);
   (void)hipFree(t->bk_tmp);
+  (void)hipFree(t->dir);
   free_batch(t);
   if (t->h_words) (void)hipHostFree(t->h_words);
   delete t;
@@ -912,8 +934,8 @@ int tcf_query(tcf_t *t, const uint64_t *d_keys, uint64_t n, uint8_t *d_out, void
     tcf::k_point_query<<<tcf::grid_for(n), tcf::NT, 0, s>>>(reinterpret_cast<const uint64_t *>(t->slots), t->nb,
                                                             t->backing, t->nbt, d_keys, n, d_out);
   else
-    tcf::k_bulk_query<<<tcf::grid_for(n * 16), tcf::NT, 0, s>>>(t->slots, t->nb, t->backing, t->bn, d_keys, n,
-                                                                d_out);
+    tcf::k_bulk_query<<<tcf::grid_for(n * 16), tcf::NT, 0, s>>>(t->slots, t->nb, t->backing, t->bn, t->dir, d_keys,
+                                                                n, d_out);
   TCF_HIP(hipGetLastError());
   return QF_OK;
 }
