@@ -373,12 +373,24 @@ __global__ __launch_bounds__(NT) void k_gbounds_scatter(const uint64_t *__restri
 }
 
 // per block: shortcut count s and f = held + s
+// (16 lanes per block: each counts the tags among 8 slots with one 16-byte
+// load, so a block's count takes one round trip, not a chain of
+// binary-search probes; a block's tags are sorted with the empty slots
+// last, so the count is also the first empty position)
 __global__ __launch_bounds__(NT) void k_plan(const uint16_t *__restrict__ slots, uint64_t nb,
                                              const uint32_t *__restrict__ gs, uint32_t *__restrict__ ps,
                                              uint32_t *__restrict__ pf) {
-  const uint64_t b = static_cast<uint64_t>(blockIdx.x) * NT + threadIdx.x;
-  if (b >= nb) return;
-  const uint32_t held = lb16(slots + b * BB, BB, EMPTY_B);
+  const uint64_t t = static_cast<uint64_t>(blockIdx.x) * NT + threadIdx.x;
+  const uint64_t b = t / 16;
+  const uint32_t l = static_cast<uint32_t>(t % 16);
+  uint32_t c = 0;
+  if (b < nb) {
+    const u64x2 v = reinterpret_cast<const u64x2 *>(slots + b * BB)[l];
+    c = static_cast<uint32_t>(popc64(nz16(~v.x)) + popc64(nz16(~v.y)));
+  }
+  for (int m = 8; m >= 1; m >>= 1) c += __shfl_xor(c, m);  // (all lanes: the groups are aligned)
+  if (b >= nb || l != 0) return;
+  const uint32_t held = c;
   const uint32_t cnt = gs[b + 1] - gs[b];
   const uint32_t room = held < SHORT_B ? SHORT_B - held : 0;
   const uint32_t s = cnt < room ? cnt : room;
@@ -775,7 +787,7 @@ int bulk_insert(tcf_filter *t, const uint64_t *keys, uint64_t n, hipStream_t s) 
   k_compose<<<blocks_for(n), NT, 0, s>>>(keys, n, t->nb, t->bufA);
   if (int rc = sort64(t, t->bufA, t->bufB, n, s)) return rc;
   group_bounds(t, t->bufA, n, t->gs1, s, true);
-  k_plan<<<blocks_for(t->nb), NT, 0, s>>>(t->slots, t->nb, t->gs1, t->ps, t->pf);
+  k_plan<<<blocks_for(t->nb * 16), NT, 0, s>>>(t->slots, t->nb, t->gs1, t->ps, t->pf);
   k_set_words<<<1, 64, 0, s>>>(t->state, TS_OVER, 4, 0ull);  // TS_OVER .. TS_CHOSEN
   k_choose<<<blocks_for(n), NT, 0, s>>>(t->bufA, n, t->gs1, t->ps, t->pf, t->bufC, t->state);
   TCF_HIP(hipMemcpyAsync(t->h_words, t->state + TS_CHOSEN, 8, hipMemcpyDeviceToHost, s));
