@@ -26,3 +26,19 @@ def test_help_lists_every_workload():
     assert out.returncode == 0
     for w in ("c2", "sweep", "fill", "zipf", "c4", "serve", "tcf", "point"):
         assert w in out.stdout
+
+
+def test_oracle_shards_cover_every_filter_once_and_balance():
+    # the all-core oracle baselines spread filters over host threads,
+    # heaviest first to the least-loaded thread
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+
+    w = {i: (1 << (10 + i % 11)) for i in range(300)}
+    shards = bench.shard(list(w), lambda i: w[i], 16)
+    flat = sorted(i for s in shards for i in s)
+    assert flat == list(range(300))
+    loads = [sum(w[i] for i in s) for s in shards]
+    assert max(loads) - min(loads) <= max(w.values())
+    assert bench.shard([], lambda i: 1, 4) == [[], [], [], []]
+    assert 1 <= bench.host_threads() <= 16
