@@ -462,21 +462,31 @@ __global__ __launch_bounds__(NT) void k_merge_blocks(uint16_t *slots, uint64_t n
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint64_t b = static_cast<uint64_t>(blockIdx.x) * 4 + w;
   uint32_t ha = 0, ns = 0, nc = 0;
+  // the block's plan and list bounds, all requested together (then the
+  // block and its two lists in one more round trip)
+  uint32_t p_s = 0, p_f = 0, g1 = 0, g2 = 0, g2e = 0;
+  if (b < nb) {
+    p_s = ps[b];
+    p_f = pf[b];
+    g1 = gs1[b];
+    g2 = gs2[b];
+    g2e = gs2[b + 1];
+  }
   // (a block that receives nothing is neither read nor written)
-  const bool touched = b < nb && (ps[b] != 0 || gs2[b + 1] != gs2[b]);
+  const bool touched = b < nb && (p_s != 0 || g2e != g2);
   if (touched) {
-    ns = ps[b];
-    ha = pf[b] - ns;
-    const uint32_t got = gs2[b + 1] - gs2[b], room = BB - pf[b];
+    ns = p_s;
+    ha = p_f - ns;
+    const uint32_t got = g2e - g2, room = BB - p_f;
     nc = got < room ? got : room;
     const uint32_t *src = reinterpret_cast<const uint32_t *>(slots + b * BB);
     const uint32_t v = src[lane];
     A[w][2 * lane] = static_cast<uint16_t>(v & 0xFFFF);
     A[w][2 * lane + 1] = static_cast<uint16_t>(v >> 16);
-    for (uint32_t j = lane; j < ns; j += 64) S[w][j] = static_cast<uint16_t>((s1[gs1[b] + j] >> 24) & 0xFFFF);
-    for (uint32_t j = lane; j < nc; j += 64) C[w][j] = static_cast<uint16_t>((s2[gs2[b] + j] >> 24) & 0xFFFF);
+    for (uint32_t j = lane; j < ns; j += 64) S[w][j] = static_cast<uint16_t>((s1[g1 + j] >> 24) & 0xFFFF);
+    for (uint32_t j = lane; j < nc; j += 64) C[w][j] = static_cast<uint16_t>((s2[g2 + j] >> 24) & 0xFFFF);
     for (uint32_t j = nc + lane; j < got; j += 64) {
-      const uint64_t e = s2[gs2[b] + j];
+      const uint64_t e = s2[g2 + j];
       const uint64_t pos = qf::atomic_add_u64(&state[TS_OVPOS], 1ull);
       bk[bn + pos] = pair_of(static_cast<uint32_t>(e >> 40), static_cast<uint32_t>(e & 0xFFFFFF),
                              static_cast<uint32_t>((e >> 24) & 0xFFFF));
