@@ -401,27 +401,41 @@ __global__ __launch_bounds__(NT) void k_plan(const uint16_t *__restrict__ slots,
 // The items not shortcut, with their keys for the second sort
 // (chosen << 40 | tag << 24 | other), packed at out[0, state[TS_CHOSEN]) in
 // no particular order (the sort orders them): one range per work-group.
+// (CHOOSE_K items per lane, so that a work-group's one reservation in the
+// output covers NT * CHOOSE_K items: same-address atomics from every
+// work-group serialise at about 12 ns each, which bounded the kernel when
+// each work-group took NT items)
+constexpr int CHOOSE_K = 8;
 __global__ __launch_bounds__(NT) void k_choose(const uint64_t *__restrict__ s1, uint64_t n,
                                                const uint32_t *__restrict__ gs, const uint32_t *__restrict__ ps,
                                                const uint32_t *__restrict__ pf, uint64_t *__restrict__ out,
                                                uint64_t *state) {
   __shared__ uint32_t wc[NT / 64];
   __shared__ uint64_t base;
-  const uint64_t i = static_cast<uint64_t>(blockIdx.x) * NT + threadIdx.x;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  bool chosen = false;
-  uint64_t key = 0;
-  if (i < n) {
-    const uint64_t c = s1[i];
-    const uint32_t b1 = static_cast<uint32_t>(c >> 40), tag = static_cast<uint32_t>((c >> 24) & 0xFFFF);
-    const uint32_t b2 = static_cast<uint32_t>(c & 0xFFFFFF);
-    if (i - gs[b1] >= ps[b1]) {
-      chosen = true;
-      key = pf[b1] <= pf[b2] ? comp_of(b1, tag, b2) : comp_of(b2, tag, b1);
+  const uint64_t i0 = static_cast<uint64_t>(blockIdx.x) * NT * CHOOSE_K + threadIdx.x;
+  bool chosen[CHOOSE_K];
+  uint64_t key[CHOOSE_K];
+  uint32_t mine = 0;  // the wave's chosen items
+  uint64_t bal[CHOOSE_K];
+#pragma unroll
+  for (int k = 0; k < CHOOSE_K; ++k) {
+    const uint64_t i = i0 + static_cast<uint64_t>(k) * NT;
+    chosen[k] = false;
+    key[k] = 0;
+    if (i < n) {
+      const uint64_t c = s1[i];
+      const uint32_t b1 = static_cast<uint32_t>(c >> 40), tag = static_cast<uint32_t>((c >> 24) & 0xFFFF);
+      const uint32_t b2 = static_cast<uint32_t>(c & 0xFFFFFF);
+      if (i - gs[b1] >= ps[b1]) {
+        chosen[k] = true;
+        key[k] = pf[b1] <= pf[b2] ? comp_of(b1, tag, b2) : comp_of(b2, tag, b1);
+      }
     }
+    bal[k] = __ballot(chosen[k]);
+    mine += static_cast<uint32_t>(popc64(bal[k]));
   }
-  const uint64_t bal = __ballot(chosen);
-  if (lane == 0) wc[w] = static_cast<uint32_t>(popc64(bal));
+  if (lane == 0) wc[w] = mine;
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t tot = 0;
@@ -433,7 +447,12 @@ __global__ __launch_bounds__(NT) void k_choose(const uint64_t *__restrict__ s1, 
     base = tot ? qf::atomic_add_u64(&state[TS_CHOSEN], tot) : 0;
   }
   __syncthreads();
-  if (chosen) out[base + wc[w] + popc64(bal & ((1ull << lane) - 1ull))] = key;
+  uint64_t at = base + wc[w];
+#pragma unroll
+  for (int k = 0; k < CHOOSE_K; ++k) {
+    if (chosen[k]) out[at + popc64(bal[k] & ((1ull << lane) - 1ull))] = key[k];
+    at += static_cast<uint64_t>(popc64(bal[k]));
+  }
 }
 
 // items beyond each block's free slots: their total in state[TS_OVER]
@@ -799,7 +818,8 @@ int bulk_insert(tcf_filter *t, const uint64_t *keys, uint64_t n, hipStream_t s) 
   group_bounds(t, t->bufA, n, t->gs1, s, true);
   k_plan<<<blocks_for(t->nb * 16), NT, 0, s>>>(t->slots, t->nb, t->gs1, t->ps, t->pf);
   k_set_words<<<1, 64, 0, s>>>(t->state, TS_OVER, 4, 0ull);  // TS_OVER .. TS_CHOSEN
-  k_choose<<<blocks_for(n), NT, 0, s>>>(t->bufA, n, t->gs1, t->ps, t->pf, t->bufC, t->state);
+  k_choose<<<blocks_for((n + CHOOSE_K - 1) / CHOOSE_K), NT, 0, s>>>(t->bufA, n, t->gs1, t->ps, t->pf, t->bufC,
+                                                                     t->state);
   TCF_HIP(hipMemcpyAsync(t->h_words, t->state + TS_CHOSEN, 8, hipMemcpyDeviceToHost, s));
   TCF_HIP(hipStreamSynchronize(s));
   // only the items that did not take the shortcut are sorted again (none
