@@ -718,6 +718,13 @@ uint32_t grid_for(uint64_t n) {
   return static_cast<uint32_t>(g < 1 ? 1 : (g > 16384 ? 16384 : g));
 }
 uint32_t blocks_for(uint64_t n) { return static_cast<uint32_t>((n + NT - 1) / NT); }
+// grids of the point updates, which end with a same-address atomic per
+// work-group (about 12 ns each, serialised): 4096 work-groups of 256 lanes
+// still fill the chip twice over
+uint32_t grid_for_updates(uint64_t n) {
+  const uint32_t g = grid_for(n);
+  return g > 4096 ? 4096 : g;
+}
 
 }  // namespace
 }  // namespace tcf
@@ -958,7 +965,7 @@ int tcf_insert(tcf_t *t, const uint64_t *d_keys, uint64_t n, int32_t *d_status, 
     // table at load 0.9 with every key in flight at once loses items that one
     // key at a time never does).  Large tables never have that many lanes.
     const uint64_t lanes = t->nb / 4 > static_cast<uint64_t>(tcf::NT) ? t->nb / 4 : tcf::NT;
-    const uint32_t g = tcf::grid_for(n), gmax = static_cast<uint32_t>((lanes + tcf::NT - 1) / tcf::NT);
+    const uint32_t g = tcf::grid_for_updates(n), gmax = static_cast<uint32_t>((lanes + tcf::NT - 1) / tcf::NT);
     tcf::k_point_insert<<<g < gmax ? g : gmax, tcf::NT, 0, s>>>(reinterpret_cast<uint64_t *>(t->slots), t->nb,
                                                                 t->backing, t->nbt, d_keys, n, d_status, t->state);
     TCF_HIP(hipGetLastError());
@@ -988,7 +995,7 @@ int tcf_delete(tcf_t *t, const uint64_t *d_keys, uint64_t n, uint64_t *d_not_fou
   if (n > 0xFFFFFFFFull) return qf::record_error(QF_ERR_ARG);
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (t->kind == TCF_POINT) {
-    tcf::k_point_delete<<<tcf::grid_for(n), tcf::NT, 0, s>>>(reinterpret_cast<uint64_t *>(t->slots), t->nb,
+    tcf::k_point_delete<<<tcf::grid_for_updates(n), tcf::NT, 0, s>>>(reinterpret_cast<uint64_t *>(t->slots), t->nb,
                                                              t->backing, t->nbt, d_keys, n, d_not_found, t->state);
     TCF_HIP(hipGetLastError());
     return QF_OK;
